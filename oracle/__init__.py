@@ -1,0 +1,177 @@
+"""ctypes front end of the FP64 CPU oracle (``pic_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the independent reference the GPU library is
+checked against.  Only the test suite, the package smoke check and the benchmark's
+CPU-baseline leg may import it; the library itself never does.  It shares no code with
+the GPU path.  Pins that tie it to the paper live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
+
+
+class OCfg(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("n_cells", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("length", ctypes.c_double),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double),
+                ("b_ext", ctypes.c_double * 3)]
+
+
+class ODiag(ctypes.Structure):
+    _fields_ = [("kinetic", ctypes.c_double), ("field_e", ctypes.c_double),
+                ("field_b", ctypes.c_double), ("total", ctypes.c_double),
+                ("max_gamma_dev", ctypes.c_double), ("fallbacks", ctypes.c_int64),
+                ("nonfinite", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+DIAG_DTYPE = np.dtype([("kinetic", "f8"), ("field_e", "f8"), ("field_b", "f8"),
+                       ("total", "f8"), ("max_gamma_dev", "f8"), ("fallbacks", "i8"),
+                       ("nonfinite", "i4"), ("pad", "i4")])
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_run.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, dp, ctypes.c_int64,
+                                 ctypes.c_int, ctypes.c_void_p]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_run_gamma.argtypes = L.oracle_run.argtypes + [dp]
+        L.oracle_run_gamma.restype = ctypes.c_int
+        L.oracle_check.argtypes = [ctypes.POINTER(OCfg)]
+        L.oracle_stencil.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ip, dp]
+        L.oracle_stencil.restype = ctypes.c_int
+        L.oracle_deposit.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_gather.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_gauss.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_int,
+                                   ctypes.c_double, dp]
+        L.oracle_cn_solve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_energy.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_cfg(nv, scheme, order, n_cells, n_particles, length, dt, c=1.0, b_ext=(0, 0, 0)):
+    cfg = OCfg()
+    cfg.nv, cfg.scheme, cfg.order, cfg.n_cells = nv, SCHEMES.get(scheme, scheme), order, n_cells
+    cfg.n_particles, cfg.length, cfg.dt, cfg.c = n_particles, length, dt, c
+    for i in range(3):
+        cfg.b_ext[i] = b_ext[i]
+    return cfg
+
+
+class State:
+    """Host arrays of one run, in the layout the oracle uses (SoA FP64)."""
+
+    def __init__(self, wl, scheme: Optional[str] = None):
+        self.cfg = make_cfg(wl.nv, scheme or wl.scheme, wl.order, wl.n_cells,
+                            wl.n_particles, wl.length, wl.dt, wl.c, wl.b_ext)
+        self.x = np.ascontiguousarray(wl.x, dtype=np.float64).copy()
+        self.v = np.ascontiguousarray(wl.v, dtype=np.float64).reshape(wl.nv, -1).copy()
+        self.w = None if wl.w is None else np.ascontiguousarray(wl.w, dtype=np.float64).copy()
+        self.E = np.zeros((3, wl.n_cells)) if wl.E0 is None else \
+            np.ascontiguousarray(wl.E0, dtype=np.float64).reshape(3, -1).copy()
+        self.B = np.zeros((2, wl.n_cells)) if wl.B0 is None else \
+            np.ascontiguousarray(wl.B0, dtype=np.float64).reshape(2, -1).copy()
+        self.pending_gauss = bool(wl.init_gauss)
+        self.records = []
+
+    def run(self, nsteps: int, gamma_out: Optional[np.ndarray] = None) -> np.ndarray:
+        """Advance ``nsteps``; returns the records (initial state first).  ``gamma_out``
+        ([N_p]) receives Gamma of the last step, NaN where the fallback was taken."""
+        rec = np.zeros(nsteps + 1, dtype=DIAG_DTYPE)
+        rc = lib().oracle_run_gamma(ctypes.byref(self.cfg), _p(self.x), _p(self.v),
+                                    _p(self.w), _p(self.E), _p(self.B), nsteps,
+                                    int(self.pending_gauss), rec.ctypes.data, _p(gamma_out))
+        if rc != 0:
+            raise ValueError("oracle rejected the configuration")
+        self.pending_gauss = False
+        if not self.records:
+            self.records.append(rec[0])
+        self.records.extend(rec[1:])
+        return rec
+
+
+def stencil(order: int, pos: float, h: float, ng: int, shift: float = 0.0):
+    idx = np.zeros(4, dtype=np.int64)
+    wt = np.zeros(4)
+    n = lib().oracle_stencil(order, pos, h, shift, ng,
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(wt))
+    return idx[:n].copy(), wt[:n].copy()
+
+
+def deposit(order, x, w, u, ng, h, shift=0.0):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(ng)
+    lib().oracle_deposit(order, x.size, _p(x), _p(w), _p(u), ng, h, shift, _p(out))
+    return out
+
+
+def gather(order, x, field, h, shift=0.0):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    field = np.ascontiguousarray(field, dtype=np.float64)
+    out = np.zeros(x.size)
+    lib().oracle_gather(order, x.size, _p(x), _p(field), field.size, h, shift, _p(out))
+    return out
+
+
+def gauss(order, x, w, ng, length):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    E = np.zeros(ng)
+    lib().oracle_gauss(order, x.size, _p(x), _p(w), ng, length, _p(E))
+    return E
+
+
+def cn_solve(ng, h, s, r):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    y = np.zeros(ng)
+    lib().oracle_cn_solve(ng, h, s, _p(r), _p(y))
+    return y
+
+
+def energy(state: State) -> np.void:
+    rec = np.zeros(1, dtype=DIAG_DTYPE)
+    lib().oracle_energy(ctypes.byref(state.cfg), _p(state.v), _p(state.w), _p(state.E),
+                        _p(state.B), rec.ctypes.data)
+    return rec[0]

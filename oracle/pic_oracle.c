@@ -1,0 +1,565 @@
+/*
+ * Plain, slow FP64 CPU oracle for the explicit energy-conserving particle-in-cell step of
+ * Ricketson & Hu, "An explicit, energy-conserving particle-in-cell scheme".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent check of the GPU library: only
+ * the test suite, the package smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or constant with the GPU path.
+ *
+ * Everything is a direct transcription of the paper's definitions in one spatial
+ * dimension, periodic in x on [0, L) with nodes x_i = i h, h = L / N_g:
+ *   - shape functions are the cardinal B-splines of section 2.2 (degree 1 is the tent
+ *     S(z) = max(0, 1 - |z|/h); degree 2 is the next member of the family), evaluated
+ *     at every node that can lie in the support;
+ *   - deposit  j_i = (1/h) sum_p w_p v_p S(x_i - x_p)       (section 2.2),
+ *     gather   E_p = sum_i E_i S(x_p - x_i)                 (section 2.2);
+ *   - ESEC2: the corrected scheme, eq. (good_translation) with (doublestardef);
+ *   - ESEC1: the first scheme, eq. (naivetranslation) + eq. (PICmodification) with the
+ *     closed-form root eq. (opt_solution);
+ *   - EMEC(LI): eq. (EMbasic), Crank-Nicolson Maxwell on a staggered 1D grid;
+ *   - the fallback Gamma := 1 when the root is imaginary (section 3.2), counted;
+ *   - total energy of section 5.1.
+ * The electrostatic Ampere update is E <- E - dt (j - mean j): in 1D, E = -d(phi)/dx
+ * (section 3.2) makes the mean of E zero, so only the mean-free part of j drives E.
+ * Sums over particles run in particle index order; energy sums are compensated.
+ * No loop is blocked, fused or reordered beyond what the equations say.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t nv;          /* 1 (1D-1V) or 3 (1D-3V)                                  */
+    int32_t scheme;      /* 0 = ESEC2, 1 = ESEC1, 2 = EMEC(LI)                       */
+    int32_t order;       /* B-spline degree: 1 or 2                                  */
+    int32_t n_cells;     /* N_g                                                      */
+    int64_t n_particles; /* N_p                                                      */
+    double length;       /* L                                                        */
+    double dt;
+    double c;            /* speed of light in thermal-speed units (EM only)          */
+    double b_ext[3];     /* uniform imposed magnetic field                           */
+} ocfg;
+
+typedef struct {
+    double kinetic, field_e, field_b, total, max_gamma_dev;
+    int64_t fallbacks;
+    int32_t nonfinite;
+    int32_t pad;
+} odiag;
+
+/* ---------------------------------------------------------------- shape functions */
+
+/* Cardinal B-spline of degree `order` in units of h, centred at 0 (section 2.2). */
+static double bspline(int order, double t)
+{
+    t = fabs(t);
+    if (order == 1)
+        return t < 1.0 ? 1.0 - t : 0.0;
+    /* degree 2: 3/4 - t^2 on |t| < 1/2, (3/2 - |t|)^2 / 2 on 1/2 <= |t| < 3/2 */
+    if (t < 0.5)
+        return 0.75 - t * t;
+    if (t < 1.5)
+        return 0.5 * (1.5 - t) * (1.5 - t);
+    return 0.0;
+}
+
+static int64_t pmod(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Nodes whose shape value at position xi (in units of h, grid offset `shift`) may be
+ * non-zero: j = floor(xi) - 1 .. floor(xi) + 2 covers support radius <= 3/2. */
+static int stencil(int order, double pos, double h, double shift, int ng, int64_t *idx,
+                   double *wt)
+{
+    double xi = pos / h - shift;
+    int64_t j0 = (int64_t)floor(xi);
+    int n = 0;
+    for (int64_t j = j0 - 1; j <= j0 + 2; ++j) {
+        double s = bspline(order, (double)j - xi);
+        if (s != 0.0) {
+            idx[n] = pmod(j, ng);
+            wt[n] = s;
+            ++n;
+        }
+    }
+    return n;
+}
+
+int oracle_stencil(int order, double pos, double h, double shift, int ng, int64_t *idx,
+                   double *wt)
+{
+    return stencil(order, pos, h, shift, ng, idx, wt);
+}
+
+/* j_i = (1/h) sum_p q_p S(x_i - x_p);  q_p = w_p u_p.  out is zeroed first. */
+void oracle_deposit(int order, int64_t np, const double *x, const double *w,
+                    const double *u, int ng, double h, double shift, double *out)
+{
+    int64_t idx[4];
+    double wt[4];
+    memset(out, 0, sizeof(double) * (size_t)ng);
+    for (int64_t p = 0; p < np; ++p) {
+        int n = stencil(order, x[p], h, shift, ng, idx, wt);
+        for (int k = 0; k < n; ++k)
+            out[idx[k]] += w[p] * u[p] * wt[k] / h;
+    }
+}
+
+/* E_p = sum_i E_i S(x_p - x_i) */
+void oracle_gather(int order, int64_t np, const double *x, const double *field, int ng,
+                   double h, double shift, double *out)
+{
+    int64_t idx[4];
+    double wt[4];
+    for (int64_t p = 0; p < np; ++p) {
+        int n = stencil(order, x[p], h, shift, ng, idx, wt);
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k)
+            acc += field[idx[k]] * wt[k];
+        out[p] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------- small helpers */
+
+typedef struct { double s, c; } nsum;   /* Neumaier compensated sum */
+
+static void nadd(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double wrap(double x, double L)
+{
+    x = x - L * floor(x / L);
+    if (x < 0.0)
+        x += L;
+    if (x >= L)
+        x = 0.0;
+    return x;
+}
+
+static double mean(const double *a, int n)
+{
+    nsum s = {0.0, 0.0};
+    for (int i = 0; i < n; ++i)
+        nadd(&s, a[i]);
+    return (s.s + s.c) / n;
+}
+
+/* ----------------------------------------------------------- initial Gauss solve */
+
+/* dE/dx = rho - 1 solved spectrally on the nodes (Poisson form, section 2.1): with
+ * DFT coefficients rho_m, E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2;
+ * the mean mode and (even N) the Nyquist mode of E are zero. */
+void oracle_gauss(int order, int64_t np, const double *x, const double *w, int ng,
+                  double L, double *E)
+{
+    double h = L / ng;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)ng);
+    double *ones = (double *)malloc(sizeof(double) * (size_t)np);
+    for (int64_t p = 0; p < np; ++p)
+        ones[p] = 1.0;
+    oracle_deposit(order, np, x, w, ones, ng, h, 0.0, rho);
+    double *ere = (double *)calloc((size_t)ng, sizeof(double));
+    double *eim = (double *)calloc((size_t)ng, sizeof(double));
+    for (int m = 1; m < ng; ++m) {
+        if (2 * m == ng)
+            continue;                               /* Nyquist mode stays zero */
+        int ms = m <= ng / 2 ? m : m - ng;          /* signed mode number */
+        double re = 0.0, im = 0.0;                  /* rho_hat_m */
+        for (int l = 0; l < ng; ++l) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * l) % ng) / ng;
+            re += rho[l] * cos(th);
+            im -= rho[l] * sin(th);
+        }
+        double k = 2.0 * M_PI * ms / L;
+        ere[m] = im / k;                            /* rho_hat / (i k) */
+        eim[m] = -re / k;
+    }
+    for (int i = 0; i < ng; ++i) {
+        double acc = 0.0;
+        for (int m = 1; m < ng; ++m) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * i) % ng) / ng;
+            acc += ere[m] * cos(th) - eim[m] * sin(th);
+        }
+        E[i] = acc / ng;
+    }
+    free(ere);
+    free(eim);
+    free(ones);
+    free(rho);
+}
+
+/* -------------------------------------------- Crank-Nicolson circulant solve (EM) */
+
+/* Solve (I - s L_h) y = r with L_h the periodic 3-point Laplacian (f_{i+1} - 2 f_i +
+ * f_{i-1}) / h^2 and s = (dt/2)^2 c^2: the matrix is circulant, diagonal in the DFT
+ * basis with eigenvalues 1 + s (4/h^2) sin^2(pi m / N). */
+void oracle_cn_solve(int ng, double h, double s, const double *r, double *y)
+{
+    double *re = (double *)malloc(sizeof(double) * (size_t)ng);
+    double *im = (double *)malloc(sizeof(double) * (size_t)ng);
+    for (int m = 0; m < ng; ++m) {
+        double a = 0.0, b = 0.0;
+        for (int l = 0; l < ng; ++l) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * l) % ng) / ng;
+            a += r[l] * cos(th);
+            b -= r[l] * sin(th);
+        }
+        double sn = sin(M_PI * m / ng);
+        double lam = 1.0 + s * 4.0 / (h * h) * sn * sn;
+        re[m] = a / lam;
+        im[m] = b / lam;
+    }
+    for (int i = 0; i < ng; ++i) {
+        double acc = 0.0;
+        for (int m = 0; m < ng; ++m) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * i) % ng) / ng;
+            acc += re[m] * cos(th) - im[m] * sin(th);
+        }
+        y[i] = acc / ng;
+    }
+    free(re);
+    free(im);
+}
+
+/* Staggered differences: node arrays f[i] at i h, half-node arrays g[i] at (i + 1/2) h.
+ * D+ f at half node i: (f[i+1] - f[i]) / h;  D- g at node i: (g[i] - g[i-1]) / h. */
+static double dplus(const double *f, int i, int ng, double h)
+{
+    return (f[(i + 1) % ng] - f[i]) / h;
+}
+
+static double dminus(const double *g, int i, int ng, double h)
+{
+    return (g[i] - g[(i + ng - 1) % ng]) / h;
+}
+
+/* ------------------------------------------------------------------------ energy */
+
+void oracle_energy(const ocfg *cfg, const double *v, const double *w, const double *E,
+                   const double *B, odiag *d)
+{
+    int64_t np = cfg->n_particles;
+    int ng = cfg->n_cells, nv = cfg->nv;
+    double h = cfg->length / ng, wu = cfg->length / (double)np;
+    nsum ke = {0, 0}, we = {0, 0}, wb = {0, 0};
+    for (int64_t p = 0; p < np; ++p) {
+        double v2 = 0.0;
+        for (int c = 0; c < nv; ++c)
+            v2 += v[c * np + p] * v[c * np + p];
+        nadd(&ke, 0.5 * (w ? w[p] : wu) * v2);
+    }
+    int ne = cfg->scheme == 2 ? 3 : 1;
+    for (int c = 0; c < ne; ++c)
+        for (int i = 0; i < ng; ++i)
+            nadd(&we, 0.5 * h * E[c * ng + i] * E[c * ng + i]);
+    if (cfg->scheme == 2 && B)
+        for (int c = 0; c < 2; ++c)
+            for (int i = 0; i < ng; ++i)
+                nadd(&wb, 0.5 * cfg->c * cfg->c * h * B[c * ng + i] * B[c * ng + i]);
+    d->kinetic = ke.s + ke.c;
+    d->field_e = we.s + we.c;
+    d->field_b = wb.s + wb.c;
+    d->total = d->kinetic + d->field_e + d->field_b;
+}
+
+/* --------------------------------------------------------------------- the step */
+
+typedef struct {
+    double *xs, *x1, *xh, *vs, *wv, *gE, *gB;
+    double *J1, *J2, *Es, *Bs, *En, *Bn, *Eb, *Bb, *R;
+} owork;
+
+static void cross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Solve v = u + v x t for v (the implicit half-step velocity of eq. (EMbasic), also the
+ * rotation of the symmetric Boris push): v = (u + u x t + (u.t) t) / (1 + |t|^2). */
+static void solve_vstar(const double *u, const double *t, double *v)
+{
+    double uxt[3];
+    cross(u, t, uxt);
+    double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int c = 0; c < 3; ++c)
+        v[c] = (u[c] + uxt[c] + ut * t[c]) / (1.0 + tt);
+}
+
+static int step(const ocfg *cfg, double *x, double *v, const double *w, double *E,
+                double *B, owork *o, odiag *d, double *gamma_out)
+{
+    const int64_t np = cfg->n_particles;
+    const int ng = cfg->n_cells, nv = cfg->nv, ord = cfg->order, sch = cfg->scheme;
+    const double L = cfg->length, h = L / ng, dt = cfg->dt, c2 = cfg->c * cfg->c;
+    const double wu = L / (double)np;
+    const int em = sch == 2;
+    const int ncur = em ? 3 : 1;                 /* current components that matter */
+    double *vx = v;
+
+    for (int64_t p = 0; p < np; ++p)
+        o->wv[p] = w ? w[p] : wu;
+
+    /* S1: x* = x^n + dt/2 v^n */
+    for (int64_t p = 0; p < np; ++p)
+        o->xs[p] = x[p] + 0.5 * dt * vx[p];
+
+    /* S2-S3: predictor deposit j^{n,*} (velocity v^n at x*) and predictor fields */
+    if (sch == 1) {
+        memcpy(o->Es, E, sizeof(double) * (size_t)ng);
+    } else {
+        for (int c = 0; c < ncur; ++c)
+            oracle_deposit(ord, np, o->xs, o->wv, v + c * np, ng, h, 0.0, o->J1 + c * ng);
+        if (!em) {
+            double m = mean(o->J1, ng);
+            for (int i = 0; i < ng; ++i)
+                o->Es[i] = E[i] - 0.5 * dt * (o->J1[i] - m);
+        } else {
+            const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
+            const double *By = B, *Bz = B + ng;
+            for (int i = 0; i < ng; ++i) {
+                /* E* = E + dt/2 (c^2 curl B - j):  (curl B)_y = -D-Bz, (curl B)_z = D-By */
+                o->Es[i] = Ex[i] - 0.5 * dt * o->J1[i];
+                o->Es[ng + i] = Ey[i] + 0.5 * dt * (-c2 * dminus(Bz, i, ng, h) - o->J1[ng + i]);
+                o->Es[2 * ng + i] = Ez[i] + 0.5 * dt * (c2 * dminus(By, i, ng, h) - o->J1[2 * ng + i]);
+                /* B* = B - dt/2 curl E:  (curl E)_y = -D+Ez, (curl E)_z = D+Ey */
+                o->Bs[i] = By[i] + 0.5 * dt * dplus(Ez, i, ng, h);
+                o->Bs[ng + i] = Bz[i] - 0.5 * dt * dplus(Ey, i, ng, h);
+            }
+        }
+    }
+
+    /* S4-S5: gather at x* and the half-step velocity v* */
+    if (nv == 1) {
+        oracle_gather(ord, np, o->xs, o->Es, ng, h, 0.0, o->gE);
+        for (int64_t p = 0; p < np; ++p)
+            o->vs[p] = v[p] + 0.5 * dt * o->gE[p];
+    } else {
+        int ne = em ? 3 : 1;
+        double *gE = o->gE;                        /* [3][np] */
+        for (int c = 0; c < 3; ++c) {
+            if (c < ne)
+                oracle_gather(ord, np, o->xs, o->Es + c * ng, ng, h, 0.0, gE + c * np);
+            else
+                memset(gE + c * np, 0, sizeof(double) * (size_t)np);
+        }
+        if (em) {   /* B_y, B_z live on the half nodes */
+            oracle_gather(ord, np, o->xs, o->Bs, ng, h, 0.5, o->gB);
+            oracle_gather(ord, np, o->xs, o->Bs + ng, ng, h, 0.5, o->gB + np);
+        }
+        for (int64_t p = 0; p < np; ++p) {
+            double u[3], t[3], vs[3];
+            double bb[3] = {cfg->b_ext[0], cfg->b_ext[1], cfg->b_ext[2]};
+            if (em) {
+                bb[1] += o->gB[p];
+                bb[2] += o->gB[np + p];
+            }
+            for (int c = 0; c < 3; ++c) {
+                u[c] = v[c * np + p] + 0.5 * dt * gE[c * np + p];
+                t[c] = 0.5 * dt * bb[c];
+            }
+            solve_vstar(u, t, vs);
+            for (int c = 0; c < 3; ++c)
+                o->vs[c * np + p] = vs[c];
+        }
+    }
+
+    /* S6: x^{n+1} = x^n + dt v*_x (unwrapped) and x^{n+1/2} = (x^n + x^{n+1}) / 2 */
+    for (int64_t p = 0; p < np; ++p) {
+        o->x1[p] = x[p] + dt * o->vs[p];
+        o->xh[p] = 0.5 * (x[p] + o->x1[p]);
+    }
+
+    /* S7: centred deposit j^{*,n+1/2} (velocity v* at x^{n+1/2}) */
+    for (int c = 0; c < ncur; ++c)
+        oracle_deposit(ord, np, o->xh, o->wv, o->vs + c * np, ng, h, 0.0, o->J2 + c * ng);
+
+    /* S8: field update */
+    if (!em) {
+        double m = mean(o->J2, ng);
+        for (int i = 0; i < ng; ++i)
+            o->En[i] = E[i] - dt * (o->J2[i] - m);
+        for (int i = 0; i < ng; ++i)
+            o->Eb[i] = 0.5 * (E[i] + o->En[i]);
+    } else {
+        const double a = 0.5 * dt, s = a * a * c2;
+        const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
+        const double *By = B, *Bz = B + ng;
+        double *Lf = o->R + ng;
+        /* E_x: no curl term in 1D */
+        for (int i = 0; i < ng; ++i)
+            o->En[i] = Ex[i] - dt * o->J2[i];
+        /* (I - s L) Ey' = (I + s L) Ey - dt c^2 D-Bz - dt jy */
+        for (int i = 0; i < ng; ++i) {
+            double lap = (Ey[(i + 1) % ng] - 2.0 * Ey[i] + Ey[(i + ng - 1) % ng]) / (h * h);
+            o->R[i] = Ey[i] + s * lap - dt * c2 * dminus(Bz, i, ng, h) - dt * o->J2[ng + i];
+        }
+        oracle_cn_solve(ng, h, s, o->R, o->En + ng);
+        /* (I - s L) Ez' = (I + s L) Ez + dt c^2 D-By - dt jz */
+        for (int i = 0; i < ng; ++i) {
+            double lap = (Ez[(i + 1) % ng] - 2.0 * Ez[i] + Ez[(i + ng - 1) % ng]) / (h * h);
+            o->R[i] = Ez[i] + s * lap + dt * c2 * dminus(By, i, ng, h) - dt * o->J2[2 * ng + i];
+        }
+        oracle_cn_solve(ng, h, s, o->R, o->En + 2 * ng);
+        /* Bz' = Bz - a D+(Ey + Ey'),  By' = By + a D+(Ez + Ez') */
+        for (int i = 0; i < ng; ++i)
+            Lf[i] = Ey[i] + o->En[ng + i];
+        for (int i = 0; i < ng; ++i)
+            o->Bn[ng + i] = Bz[i] - a * dplus(Lf, i, ng, h);
+        for (int i = 0; i < ng; ++i)
+            Lf[i] = Ez[i] + o->En[2 * ng + i];
+        for (int i = 0; i < ng; ++i)
+            o->Bn[i] = By[i] + a * dplus(Lf, i, ng, h);
+        for (int i = 0; i < 3 * ng; ++i)
+            o->Eb[i] = 0.5 * (E[i] + o->En[i]);
+        for (int i = 0; i < 2 * ng; ++i)
+            o->Bb[i] = 0.5 * (B[i] + o->Bn[i]);
+    }
+
+    /* S9-S13: gather at x^{n+1/2}, provisional v-dagger, energy-restoring Gamma */
+    int64_t fb = 0;
+    double gmax = 0.0;
+    int nonfinite = 0;
+    int ne = em ? 3 : 1;
+    double *gE = o->gE, *gBy = o->gB, *gBz = o->gB + np;
+    for (int c = 0; c < nv; ++c) {
+        if (c < ne)
+            oracle_gather(ord, np, o->xh, o->Eb + c * ng, ng, h, 0.0, gE + c * np);
+        else
+            memset(gE + c * np, 0, sizeof(double) * (size_t)np);
+    }
+    if (em) {
+        oracle_gather(ord, np, o->xh, o->Bb, ng, h, 0.5, gBy);
+        oracle_gather(ord, np, o->xh, o->Bb + ng, ng, h, 0.5, gBz);
+    }
+    for (int64_t p = 0; p < np; ++p) {
+        double vn[3] = {0, 0, 0}, vs[3] = {0, 0, 0}, vd[3] = {0, 0, 0};
+        for (int c = 0; c < nv; ++c) {
+            vn[c] = v[c * np + p];
+            vs[c] = o->vs[c * np + p];
+        }
+        if (nv == 1) {
+            vd[0] = vn[0] + dt * gE[p];
+        } else {
+            double bb[3] = {cfg->b_ext[0], cfg->b_ext[1], cfg->b_ext[2]}, vxb[3];
+            if (em) {
+                bb[1] += gBy[p];
+                bb[2] += gBz[p];
+            }
+            cross(vs, bb, vxb);
+            for (int c = 0; c < 3; ++c)
+                vd[c] = vn[c] + dt * (gE[c * np + p] + vxb[c]);
+        }
+        /* S11: r = 1 + 2 (v* - (v-dagger + v^n)/2) . (v-dagger - v^n) / |v-dagger|^2 */
+        double num = 0.0, den = 0.0;
+        for (int c = 0; c < nv; ++c) {
+            num += (vs[c] - 0.5 * (vd[c] + vn[c])) * (vd[c] - vn[c]);
+            den += vd[c] * vd[c];
+        }
+        double r = 1.0 + 2.0 * num / den;
+        double g;
+        /* S12: the root is real iff r >= 0; otherwise (or if r is not finite) Gamma := 1 */
+        if (r >= 0.0 && isfinite(r)) {
+            g = sqrt(r);
+        } else {
+            g = 1.0;
+            ++fb;
+        }
+        if (fabs(g - 1.0) > gmax)
+            gmax = fabs(g - 1.0);
+        if (gamma_out)
+            gamma_out[p] = (r >= 0.0 && isfinite(r)) ? g : NAN;
+        /* S13 */
+        for (int c = 0; c < nv; ++c) {
+            v[c * np + p] = g * vd[c];
+            if (!isfinite(v[c * np + p]))
+                nonfinite = 1;
+        }
+        if (!isfinite(o->x1[p]))
+            nonfinite = 1;
+        x[p] = wrap(o->x1[p], L);
+    }
+    memcpy(E, o->En, sizeof(double) * (size_t)(ne * ng));
+    if (em)
+        memcpy(B, o->Bn, sizeof(double) * (size_t)(2 * ng));
+
+    oracle_energy(cfg, v, w, E, B, d);
+    d->fallbacks = fb;
+    d->max_gamma_dev = gmax;
+    d->nonfinite = nonfinite;
+    return 0;
+}
+
+/* Validate the configuration: 0 if usable, -1 otherwise. */
+int oracle_check(const ocfg *cfg)
+{
+    if (!cfg || (cfg->nv != 1 && cfg->nv != 3) || cfg->scheme < 0 || cfg->scheme > 2)
+        return -1;
+    if (cfg->order < 1 || cfg->order > 2 || cfg->n_particles < 1)
+        return -1;
+    if (cfg->n_cells < 2 * cfg->order + 1 || !(cfg->length > 0.0) || !(cfg->dt > 0.0))
+        return -1;
+    if (cfg->scheme == 2 && (cfg->nv != 3 || !(cfg->c > 0.0)))
+        return -1;
+    return 0;
+}
+
+/* Run n steps.  rec[0] holds the diagnostics of the initial state, rec[k] those after
+ * step k.  If init_gauss, E_x is first set from the particles by oracle_gauss.
+ * x is wrapped into [0, L) before the first step.  If gamma_out is not NULL it
+ * receives Gamma_p of the last step, NaN where the fallback was taken. */
+int oracle_run_gamma(const ocfg *cfg, double *x, double *v, const double *w, double *E,
+                     double *B, int64_t nsteps, int init_gauss, odiag *rec, double *gamma_out)
+{
+    if (oracle_check(cfg))
+        return -1;
+    const int64_t np = cfg->n_particles;
+    const int ng = cfg->n_cells;
+    for (int64_t p = 0; p < np; ++p)
+        x[p] = wrap(x[p], cfg->length);
+    if (init_gauss) {
+        const double wu = cfg->length / (double)np;
+        double *wv = (double *)malloc(sizeof(double) * (size_t)np);
+        for (int64_t p = 0; p < np; ++p)
+            wv[p] = w ? w[p] : wu;
+        oracle_gauss(cfg->order, np, x, wv, ng, cfg->length, E);
+        free(wv);
+    }
+    owork o;
+    size_t P = sizeof(double) * (size_t)np, G = sizeof(double) * (size_t)ng;
+    o.xs = malloc(P); o.x1 = malloc(P); o.xh = malloc(P); o.wv = malloc(P);
+    o.vs = malloc(3 * P); o.gE = malloc(3 * P); o.gB = malloc(2 * P);
+    o.J1 = malloc(3 * G); o.J2 = malloc(3 * G); o.Es = malloc(3 * G); o.Bs = malloc(2 * G);
+    o.En = malloc(3 * G); o.Bn = malloc(2 * G); o.Eb = malloc(3 * G); o.Bb = malloc(2 * G);
+    o.R = malloc(2 * G);
+    memset(&rec[0], 0, sizeof(odiag));
+    oracle_energy(cfg, v, w, E, B, &rec[0]);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        memset(&rec[n + 1], 0, sizeof(odiag));
+        step(cfg, x, v, w, E, B, &o, &rec[n + 1], n + 1 == nsteps ? gamma_out : NULL);
+    }
+    free(o.xs); free(o.x1); free(o.xh); free(o.wv); free(o.vs); free(o.gE); free(o.gB);
+    free(o.J1); free(o.J2); free(o.Es); free(o.Bs); free(o.En); free(o.Bn);
+    free(o.Eb); free(o.Bb); free(o.R);
+    return 0;
+}
+
+int oracle_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
+               double *B, int64_t nsteps, int init_gauss, odiag *rec)
+{
+    return oracle_run_gamma(cfg, x, v, w, E, B, nsteps, init_gauss, rec, NULL);
+}
