@@ -1,0 +1,199 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) library for the explicit, energy-conserving
+ * particle-in-cell step of Ricketson & Hu, "An explicit, energy-conserving
+ * particle-in-cell scheme".
+ *
+ * Problem (section 2.1, eq. (vlasov), (maxwell)): dimensionless Vlasov equation for one
+ * mobile species with charge-to-mass ratio +1 on a uniform neutralising background
+ * (Gauss: div E = rho - 1), time in 1/omega_p, length in Debye lengths, velocity in
+ * thermal speeds, c = speed of light / thermal speed.  Here space is one-dimensional
+ * and periodic, x in [0, L), with velocities of 1 or 3 components ("1D-1V", "1D-3V").
+ *
+ * Discretisation (section 2.2): particles (x_p, v_p, w_p); nodes x_i = i h, h = L/N_g;
+ * cardinal B-spline shapes of degree 1 (tent, S(z) = max(0, 1 - |z|/h)) or 2; current
+ * deposit j_i = (1/h) sum_p w_p v_p S(x_i - x_p); gather E_p = sum_i E_i S(x_p - x_i).
+ * Electric field components live on the nodes; in the electromagnetic scheme B_y, B_z
+ * live on the half nodes (i + 1/2) h (a one-dimensional Yee lattice, section 2.2.2).
+ *
+ * Schemes (section 5 names them):
+ *   PIC_ESEC2   eq. (good_translation): predictor deposit j^{n,*} at x* with v^n, predictor
+ *               field E*, half-step velocity v*, centred deposit j^{*,n+1/2} at
+ *               x^{n+1/2} with v*, Ampere update, provisional v-dagger, and the
+ *               energy-restoring factor Gamma of eq. (opt_solution).
+ *   PIC_ESEC1   eq. (naivetranslation) + eq. (PICmodification): as ESEC2 without the
+ *               predictor deposit (v* uses E^n).
+ *   PIC_EMEC_LI eq. (EMbasic): ESEC2's particle update with the Crank-Nicolson
+ *               (linearly implicit) Maxwell update; requires nv == 3.
+ * Electrostatic Ampere form (eq. (ampere), 1D): E^{n+1} = E^n - dt (j - mean(j)); the
+ * mean is removed because E = -d(phi)/dx has zero mean in a periodic domain.
+ * Correction (eq. (opt_solution)): r = 1 + 2 (v* - (v-dagger + v^n)/2).(v-dagger - v^n)
+ * / |v-dagger|^2; Gamma = sqrt(r) if r >= 0 and finite, else Gamma = 1 and the particle is
+ * counted as a fallback (section 3.2: an imaginary root is replaced by 1).
+ * Energy (section 5.1): TE = 1/2 sum_p w_p |v_p|^2 + 1/2 h sum_i |E_i|^2
+ *                            + c^2/2 h sum_{i+1/2} |B_{i+1/2}|^2 (EM only).
+ *
+ * Memory: every pointer in pic_buffers is a DEVICE pointer owned by the caller and must
+ * stay valid until pic_destroy.  The library allocates no device memory: all scratch
+ * space is carved from the caller's workspace.  All work is enqueued on the caller's HIP
+ * stream; only pic_diagnostics (and the state/checkpoint calls) synchronise it.
+ * Errors: every call returns a pic_status; nothing aborts.  PIC_EINVAL leaves every
+ * argument untouched.  After PIC_EDEVICE the context is poisoned and later calls on it
+ * return PIC_ESTATE.  A context is bound to one stream and is not thread-safe.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+enum pic_status {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,         /* invalid parameter, pointer, size or alignment          */
+    PIC_ENOMEM = -2,         /* workspace smaller than pic_workspace_size()            */
+    PIC_EDEVICE = -3,        /* a HIP call failed; the context is poisoned             */
+    PIC_ESTATE = -4,         /* call on a poisoned or destroyed context                */
+    PIC_ENONFINITE = -5,     /* a particle or field value became NaN/Inf (diagnostics) */
+    PIC_EUNSUPPORTED = -6    /* valid but outside what this build handles              */
+};
+
+enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2 };
+
+enum pic_flag {
+    PIC_F_INIT_GAUSS = 1u,   /* set E_x^0 from the particles: dE/dx = rho - 1 solved
+                                spectrally on the nodes (mean and Nyquist modes zero);
+                                otherwise the caller's E (and B) are E^0 (B^0)          */
+    PIC_F_TRACK_IDS = 2u     /* permute the caller's id array with the particles        */
+};
+
+/* Deposit strategies for the current tiles (section 2.2 deposit).  Both give the same
+ * sums up to floating-point summation order. */
+enum pic_deposit_mode {
+    PIC_DEPOSIT_AUTO = 0,
+    PIC_DEPOSIT_LDS_ATOMIC = 1,   /* per-particle LDS atomics into the block's tile    */
+    PIC_DEPOSIT_WAVE_REDUCE = 2   /* wavefront pre-reduction per node, then LDS atomics;
+                                     pays off when particles are cell-sorted            */
+};
+
+typedef struct {
+    int32_t abi_version;   /* must equal PIC_ABI_VERSION                                 */
+    int32_t nv;            /* velocity components per particle: 1 or 3                   */
+    int32_t scheme;        /* enum pic_scheme; PIC_EMEC_LI requires nv == 3              */
+    int32_t shape_order;   /* B-spline degree: 1 (tent) or 2 (quadratic)                 */
+    int64_t n_particles;   /* N_p >= 1                                                   */
+    int32_t n_cells;       /* N_g >= 2 * shape_order + 1                                 */
+    int32_t rebin_every;   /* counting-sort the particles by cell every K steps; 0: never */
+    double  length;        /* L > 0                                                      */
+    double  dt;            /* time step > 0                                              */
+    double  c;             /* speed of light (PIC_EMEC_LI), > 0                          */
+    double  b_ext[3];      /* uniform imposed magnetic field added to every gathered B
+                              (section 3.2 starts from an externally imposed B); used
+                              only when nv == 3                                           */
+    uint32_t flags;        /* enum pic_flag bits                                         */
+    int32_t block_threads; /* threads per workgroup of the particle passes: 0 = default,
+                              else a multiple of 64 in [64, 1024]                         */
+    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default (by size)   */
+    int32_t deposit_mode;  /* enum pic_deposit_mode                                      */
+    int32_t record_capacity; /* per-step diagnostic records kept on the device: 0 = 4096 */
+    int32_t reserved;      /* must be 0                                                  */
+} pic_params;
+
+typedef struct {
+    double  *x;            /* [N_p] positions, in/out; wrapped into [0, L) at init       */
+    double  *v;            /* [nv][N_p] velocities (structure of arrays), in/out         */
+    const double *w;       /* [N_p] weights, or NULL for uniform w_p = L / N_p           */
+    int64_t *id;           /* [N_p] particle ids permuted with the particles (needed with
+                              PIC_F_TRACK_IDS), may be NULL otherwise                     */
+    double  *E;            /* [3][N_g] node field (E_x, E_y, E_z), in/out; the
+                              electrostatic schemes use and update E_x only               */
+    double  *B;            /* [2][N_g] half-node field (B_y, B_z), in/out; PIC_EMEC_LI
+                              only, NULL otherwise                                        */
+    void    *workspace;    /* >= pic_workspace_size(params) bytes, 256-byte aligned,
+                              caller-owned scratch the library carves up                  */
+    size_t   workspace_bytes;
+} pic_buffers;
+
+/* One record per step; pic_diagnostics returns them in step order. */
+typedef struct {
+    int64_t step;          /* n (0 = initial state)                                      */
+    double  time;          /* n * dt                                                     */
+    double  kinetic;       /* 1/2 sum_p w_p |v_p^n|^2                                    */
+    double  field_e;       /* 1/2 h sum_i |E_i^n|^2                                      */
+    double  field_b;       /* c^2/2 h sum |B^n|^2 (EM), else 0                           */
+    double  total;         /* kinetic + field_e + field_b                                */
+    double  rel_energy_err;/* |TE^n - TE^0| / TE^0                                       */
+    double  max_gamma_dev; /* max_p |Gamma_p - 1| over the particles of this step        */
+    int64_t fallbacks;     /* particles whose radicand was negative or not finite        */
+    int64_t fallbacks_total; /* cumulative since init                                    */
+    int32_t nonfinite;     /* 1 if a NaN/Inf appeared in this step's state               */
+    int32_t pad;
+} pic_diag;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of workspace the library needs for these parameters (0 if they are invalid). */
+size_t pic_workspace_size(const pic_params *p);
+
+/* Host-only check of the parameters (no GPU needed).  PIC_OK, PIC_EINVAL or
+ * PIC_EUNSUPPORTED; pic_last_error(NULL) then describes the problem. */
+int pic_validate_params(const pic_params *p);
+
+/* Bind a context to the caller's buffers and HIP stream (hipStream_t, may be NULL for
+ * the null stream) and enqueue the initial work: wrap x into [0, L); optionally the
+ * Gauss solve for E_x^0; the energy record of step 0; for ESEC2/EMEC(LI) the predictor
+ * deposit j^{0,*} and the predictor fields (eq. (good_translation), (EMbasic)).
+ * On success *out receives the context. */
+int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out);
+
+/* Enqueue n_steps steps (eq. (good_translation) / (naivetranslation)+(PICmodification) /
+ * (EMbasic)), each recording a pic_diag.  Asynchronous: returns after enqueueing. */
+int pic_step(pic_ctx *ctx, int64_t n_steps);
+
+/* Synchronise the stream and copy out the records written since the previous call (the
+ * first call also returns step 0), oldest first, at most max_records of them; records
+ * older than the device ring's capacity are lost.  *n_written receives the count.
+ * Returns PIC_ENONFINITE if any returned record has nonfinite set. */
+int pic_diagnostics(pic_ctx *ctx, pic_diag *out, int64_t max_records, int64_t *n_written);
+
+/* Synchronise and make the caller's x, v (and id) arrays hold the current particle
+ * state (after a rebin the current state may sit in the workspace). */
+int pic_sync_state(pic_ctx *ctx);
+
+/* Kernel classes timed by the optional event profiler. */
+enum pic_kernel_class {
+    PIC_K_PASS_A = 0,      /* gather at x*, v*, centred deposit                        */
+    PIC_K_FIELD = 1,       /* Ampere / Crank-Nicolson update                           */
+    PIC_K_PASS_B = 2,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit*/
+    PIC_K_TAIL = 3,        /* step record and predictor fields                         */
+    PIC_K_REBIN = 4,       /* counting-sort rebin (all of its kernels)                 */
+    PIC_K_COUNT = 5
+};
+
+/* Enable (on != 0) or disable HIP-event timing of every kernel pic_step enqueues: a
+ * hipEvent is recorded on the context's stream right before and right after each
+ * launch.  Timing adds a few microseconds per launch; use it on a separate run. */
+int pic_profile_enable(pic_ctx *ctx, int on);
+
+/* Synchronise and return, per pic_kernel_class, the summed milliseconds and the launch
+ * count since profiling was enabled (arrays of PIC_K_COUNT entries); resets them. */
+int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches);
+
+/* Release the context (host memory only; caller buffers are untouched). */
+int pic_destroy(pic_ctx *ctx);
+
+const char *pic_strerror(int status);
+
+/* Last error message of a context, or of the calling thread's last failed
+ * validation/init when ctx is NULL. */
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

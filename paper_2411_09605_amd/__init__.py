@@ -1,0 +1,7 @@
+"""MI355X (gfx950) library for the explicit energy-conserving particle-in-cell step of
+Ricketson & Hu.  The step runs in hand-written HIP kernels behind the C ABI of
+``include/pic.h``; this package is the thin Python binding over it."""
+from .binding import (  # noqa: F401
+    Pic, PicError, PicParams, make_params, validate, workspace_size, last_error,
+    DIAG_DTYPE, EXPORTS, LIB_PATH,
+)

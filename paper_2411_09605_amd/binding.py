@@ -1,0 +1,260 @@
+"""ctypes binding of ``libpic.so`` (the C ABI in ``include/pic.h``).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the HIP stream.  Importing this module
+loads the library and raises if it has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
+F_INIT_GAUSS, F_TRACK_IDS = 1, 2
+DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "wave_reduce": 2}
+ABI_VERSION = 1
+
+
+class PicParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("shape_order", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("n_cells", ctypes.c_int32),
+                ("rebin_every", ctypes.c_int32), ("length", ctypes.c_double),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double),
+                ("b_ext", ctypes.c_double * 3), ("flags", ctypes.c_uint32),
+                ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("deposit_mode", ctypes.c_int32), ("record_capacity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PicBuffers(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("id", ctypes.c_void_p), ("E", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("field_e", "f8"),
+                       ("field_b", "f8"), ("total", "f8"), ("rel_energy_err", "f8"),
+                       ("max_gamma_dev", "f8"), ("fallbacks", "i8"), ("fallbacks_total", "i8"),
+                       ("nonfinite", "i4"), ("pad", "i4")])
+
+# Every function declared in include/pic.h.
+EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
+           "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
+           "pic_destroy", "pic_strerror", "pic_last_error")
+KERNEL_CLASSES = ("pass_a", "field", "pass_b", "tail", "rebin")
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def _load():
+    # torch bundles the HIP runtime under the same soname; importing it first makes the
+    # library bind to that one runtime, so torch's streams and pointers are valid here.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2411_09605_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(PicParams)
+    vp = ctypes.c_void_p
+    lib.pic_workspace_size.argtypes = [P]
+    lib.pic_workspace_size.restype = ctypes.c_size_t
+    lib.pic_validate_params.argtypes = [P]
+    lib.pic_validate_params.restype = ctypes.c_int
+    lib.pic_init.argtypes = [P, ctypes.POINTER(PicBuffers), vp, ctypes.POINTER(vp)]
+    lib.pic_init.restype = ctypes.c_int
+    lib.pic_step.argtypes = [vp, ctypes.c_int64]
+    lib.pic_step.restype = ctypes.c_int
+    lib.pic_diagnostics.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_diagnostics.restype = ctypes.c_int
+    lib.pic_sync_state.argtypes = [vp]
+    lib.pic_sync_state.restype = ctypes.c_int
+    lib.pic_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.pic_profile_enable.restype = ctypes.c_int
+    lib.pic_profile_read.argtypes = [vp, vp, vp]
+    lib.pic_profile_read.restype = ctypes.c_int
+    lib.pic_destroy.argtypes = [vp]
+    lib.pic_destroy.restype = ctypes.c_int
+    lib.pic_strerror.argtypes = [ctypes.c_int]
+    lib.pic_strerror.restype = ctypes.c_char_p
+    lib.pic_last_error.argtypes = [vp]
+    lib.pic_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: int,
+                length: float, dt: float, c: float = 1.0, b_ext=(0.0, 0.0, 0.0),
+                init_gauss: bool = False, track_ids: bool = False, rebin_every: int = 0,
+                block_threads: int = 0, grid_blocks: int = 0, deposit_mode="auto",
+                record_capacity: int = 0) -> PicParams:
+    p = PicParams()
+    p.abi_version = ABI_VERSION
+    p.nv, p.scheme, p.shape_order = nv, SCHEMES.get(scheme, scheme), shape_order
+    p.n_particles, p.n_cells, p.rebin_every = n_particles, n_cells, rebin_every
+    p.length, p.dt, p.c = length, dt, c
+    for i in range(3):
+        p.b_ext[i] = b_ext[i]
+    p.flags = (F_INIT_GAUSS if init_gauss else 0) | (F_TRACK_IDS if track_ids else 0)
+    p.block_threads, p.grid_blocks = block_threads, grid_blocks
+    p.deposit_mode = DEPOSIT_MODES.get(deposit_mode, deposit_mode)
+    p.record_capacity, p.reserved = record_capacity, 0
+    return p
+
+
+def validate(p: PicParams) -> int:
+    return lib.pic_validate_params(ctypes.byref(p))
+
+
+def workspace_size(p: PicParams) -> int:
+    return lib.pic_workspace_size(ctypes.byref(p))
+
+
+def last_error(ctx=None) -> str:
+    return (lib.pic_last_error(ctx) or b"").decode()
+
+
+def _check(rc: int, ctx=None):
+    if rc != PIC_OK:
+        raise PicError(rc, f"{lib.pic_strerror(rc).decode()}: {last_error(ctx)}")
+
+
+class Pic:
+    """One run bound to device tensors and a HIP stream.
+
+    ``x`` [N_p], ``v`` [nv, N_p], ``E`` [3, N_g], ``B`` [2, N_g] (EM), ``w`` [N_p] or None,
+    ``ids`` [N_p] int64 or None: contiguous float64/int64 CUDA tensors owned by the
+    caller.  The workspace tensor is allocated here (uint8, 256-byte aligned)."""
+
+    def __init__(self, params: PicParams, x, v, E, B=None, w=None, ids=None, stream=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        for t in (x, v, E) + tuple(a for a in (B, w) if a is not None):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("x, v, E, B, w must be contiguous float64 CUDA tensors")
+        n, ng, nv = params.n_particles, params.n_cells, params.nv
+        if x.numel() != n or v.numel() != nv * n or E.numel() != 3 * ng:
+            raise ValueError("array sizes do not match the parameters")
+        if B is not None and B.numel() != 2 * ng:
+            raise ValueError("B must hold 2 * n_cells values")
+        if w is not None and w.numel() != n:
+            raise ValueError("w must hold n_particles values")
+        if ids is not None and (ids.dtype != torch.int64 or ids.numel() != n):
+            raise ValueError("ids must be int64 with n_particles values")
+        self.x, self.v, self.E, self.B, self.w, self.ids = x, v, E, B, w, ids
+        nbytes = workspace_size(params)
+        if nbytes == 0:
+            _check(validate(params))
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=x.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(x.device)
+        buf = PicBuffers()
+        buf.x, buf.v, buf.E = x.data_ptr(), v.data_ptr(), E.data_ptr()
+        buf.B = B.data_ptr() if B is not None else None
+        buf.w = w.data_ptr() if w is not None else None
+        buf.id = ids.data_ptr() if ids is not None else None
+        buf.workspace, buf.workspace_bytes = aligned, nbytes
+        self._buf = buf
+        ctx = ctypes.c_void_p()
+        _check(lib.pic_init(ctypes.byref(params), ctypes.byref(buf),
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.records = []
+
+    def step(self, n: int = 1):
+        _check(lib.pic_step(self.ctx, n), self.ctx)
+
+    def diagnostics(self, max_records: int = 1 << 20) -> np.ndarray:
+        """Records written since the previous call (synchronises the stream)."""
+        out = np.zeros(max_records, dtype=DIAG_DTYPE)
+        nw = ctypes.c_int64()
+        rc = lib.pic_diagnostics(self.ctx, out.ctypes.data, max_records, ctypes.byref(nw))
+        if rc not in (PIC_OK, PIC_ENONFINITE):
+            _check(rc, self.ctx)
+        recs = out[:nw.value].copy()
+        self.records.extend(recs)
+        return recs
+
+    def profile(self, on: bool = True):
+        """Turn HIP-event timing of each launch on or off."""
+        _check(lib.pic_profile_enable(self.ctx, 1 if on else 0), self.ctx)
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total ms, launches)} since the last read."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
+        _check(lib.pic_profile_read(self.ctx, ms.ctypes.data, n.ctypes.data), self.ctx)
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def sync_state(self):
+        _check(lib.pic_sync_state(self.ctx), self.ctx)
+
+    def state(self) -> dict:
+        self.sync_state()
+        d = dict(x=self.x.cpu().numpy(), v=self.v.reshape(self.params.nv, -1).cpu().numpy(),
+                 E=self.E.reshape(3, -1).cpu().numpy())
+        if self.B is not None:
+            d["B"] = self.B.reshape(2, -1).cpu().numpy()
+        if self.ids is not None:
+            d["ids"] = self.ids.cpu().numpy()
+        return d
+
+    def destroy(self):
+        if self.ctx:
+            lib.pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @classmethod
+    def from_arrays(cls, nv, scheme, order, n_cells, length, dt, x, v, E0=None, B0=None,
+                    w=None, c=1.0, b_ext=(0.0, 0.0, 0.0), init_gauss=False, ids=None,
+                    device="cuda", **knobs) -> "Pic":
+        """Copy host arrays to the device and initialise a run."""
+        import torch
+        n = int(np.asarray(x).shape[0])
+        f64 = dict(dtype=torch.float64, device=device)
+        xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).to(**f64).contiguous()
+        vt = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64).reshape(nv, n)).to(**f64).contiguous()
+        Et = torch.zeros((3, n_cells), **f64)
+        if E0 is not None:
+            Et.copy_(torch.as_tensor(np.asarray(E0, dtype=np.float64).reshape(3, n_cells)))
+        Bt = None
+        if scheme in ("emec_li", 2):
+            Bt = torch.zeros((2, n_cells), **f64)
+            if B0 is not None:
+                Bt.copy_(torch.as_tensor(np.asarray(B0, dtype=np.float64).reshape(2, n_cells)))
+        wt = None if w is None else torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(**f64)
+        it = None
+        if ids is not None:
+            it = torch.as_tensor(np.ascontiguousarray(ids, dtype=np.int64)).to(device)
+        p = make_params(nv, scheme, order, n, n_cells, length, dt, c=c, b_ext=b_ext,
+                        init_gauss=init_gauss, track_ids=ids is not None, **knobs)
+        return cls(p, xt, vt, Et, Bt, wt, it)
+
+    @classmethod
+    def from_workload(cls, wl, scheme: Optional[str] = None, device="cuda", **knobs) -> "Pic":
+        """Build from any object with the fields of ``workloads.Workload``."""
+        return cls.from_arrays(wl.nv, scheme or wl.scheme, wl.order, wl.n_cells, wl.length,
+                               wl.dt, wl.x, wl.v, E0=wl.E0, B0=wl.B0, w=wl.w, c=wl.c,
+                               b_ext=wl.b_ext, init_gauss=wl.init_gauss, device=device, **knobs)

@@ -1,0 +1,810 @@
+// Device code of the explicit energy-conserving PIC step for gfx950 (CDNA4).
+//
+// Particle state is a structure of FP64 arrays (x[N_p], v[nv][N_p]) streamed from HBM
+// with one lane per particle; the 1D grid (at most a few thousand nodes) lives in LDS for
+// the whole pass.  One step of ESEC2 / EMEC(LI) (eq. (good_translation), (EMbasic)) is
+//
+//   pass A (particles): x* = x + dt/2 v, gather E* (B*) at x*, solve v*, x^{n+1},
+//                       x^{n+1/2} = (x^n + x^{n+1}) / 2, deposit w v* at x^{n+1/2}
+//   field update (one workgroup): Ampere / Crank-Nicolson -> E^{n+1} (B^{n+1}) and the
+//                       averaged fields used by the second gather
+//   pass B (particles): recompute x*, v*, x^{n+1/2} bit-identically, gather the averaged
+//                       fields at x^{n+1/2}, v-dagger, Gamma (eq. (opt_solution)) with
+//                       the fallback, write x^{n+1} (wrapped), v^{n+1}; then, because
+//                       x*_{n+1} = x^{n+1} + dt/2 v^{n+1} is known, the NEXT step's
+//                       predictor deposit w v^{n+1} at x*_{n+1}
+//   field tail (one workgroup): energy record of the step, predictor fields E* (B*)
+//
+// so the particle state is read twice and written once per step (48 B per particle in
+// 1D-1V, 96 B in 1D-3V).  Recomputing v* instead of storing it keeps the deposit in
+// pass A and the gather in pass B at exactly the same x^{n+1/2} (compiled without FP
+// contraction), which is what the energy identity of eq. (exp_econs_simple) needs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kMaxGrid = 8192;   // upper bound on particle-pass workgroups
+
+// Per-step record, laid out exactly like pic_diag.
+struct DevRecord {
+    int64_t step;
+    double time, kinetic, field_e, field_b, total, rel_energy_err, max_gamma_dev;
+    int64_t fallbacks, fallbacks_total;
+    int32_t nonfinite, pad;
+};
+
+struct DevState {
+    int64_t step;          // steps completed
+    double te0;            // total energy of step 0
+    int64_t fb_total;
+    double we, wb;         // field energies of the state being finalised
+    int32_t nonfinite_sticky;
+    int32_t pad;
+};
+
+// Scalars of a run, passed by value to every kernel.
+struct Run {
+    int64_t np;
+    int32_t ng, nv;
+    int32_t nblocks;       // workgroups of the particle passes
+    int32_t rec_cap;
+    int64_t chunk;         // particles per workgroup (multiple of blockDim)
+    double L, h, inv_h, dt, hdt, c2;
+    double qs;             // 1/h: deposit factor (times w_p)
+    double wu;             // uniform weight L / N_p
+    double bext[3];
+    const double *w;       // [N_p] weights or nullptr (uniform)
+};
+
+// Workspace arrays (device pointers).
+struct Work {
+    double *E, *B;                 // caller fields: E[3][ng], B[2][ng] (B may be null)
+    double *Es, *Bs;               // predictor fields E*, B*
+    double *Eb, *Bb;               // (E^n + E^{n+1})/2, (B^n + B^{n+1})/2
+    double *J1, *J2;               // [3][ng] current accumulators (zero between uses)
+    double *cninv;                 // [ng] first row of the Crank-Nicolson inverse
+    double *part_ke, *part_gd;     // [nblocks] block partials
+    int64_t *part_fb;
+    int32_t *part_nf;
+    DevState *st;
+    DevRecord *rec;                // [rec_cap] ring
+};
+
+// ------------------------------------------------------------------ shape functions
+// Cardinal B-spline weights of degree ORDER for a particle at xi = x / h - shift
+// (section 2.2).  first = index of the leftmost node of the ORDER + 1 node stencil.
+template <int ORDER> struct Stencil {
+    int first;
+    double w[ORDER + 1];
+};
+
+__device__ __forceinline__ Stencil<1> stencil1(double xi)
+{
+    double f = floor(xi);
+    double d = xi - f;
+    Stencil<1> s;
+    s.first = (int)f;
+    s.w[0] = 1.0 - d;
+    s.w[1] = d;
+    return s;
+}
+
+__device__ __forceinline__ Stencil<2> stencil2(double xi)
+{
+    double f = floor(xi + 0.5);
+    double d = xi - f;                       // in [-1/2, 1/2)
+    double a = 0.5 - d, b = 0.5 + d;
+    Stencil<2> s;
+    s.first = (int)f - 1;
+    s.w[0] = 0.5 * a * a;
+    s.w[1] = 0.75 - d * d;
+    s.w[2] = 0.5 * b * b;
+    return s;
+}
+
+template <int ORDER> __device__ __forceinline__ Stencil<ORDER> stencil(double xi);
+template <> __device__ __forceinline__ Stencil<1> stencil<1>(double xi) { return stencil1(xi); }
+template <> __device__ __forceinline__ Stencil<2> stencil<2>(double xi) { return stencil2(xi); }
+
+// Periodic node index.  Positions handed to the passes are within a few cells of
+// [0, L), so the first two tests decide; the modulo keeps any input (even NaN, which
+// converts to an arbitrary int) inside the tile.
+__device__ __forceinline__ int wrap_node(int i, int ng)
+{
+    if ((unsigned)i < (unsigned)ng)
+        return i;
+    if (i < 0 && i >= -ng)
+        return i + ng;
+    if (i >= ng && i < 2 * ng)
+        return i - ng;
+    int r = i % ng;
+    return r < 0 ? r + ng : r;
+}
+
+template <int ORDER> struct Nodes {
+    int n[ORDER + 1];
+};
+
+template <int ORDER>
+__device__ __forceinline__ Nodes<ORDER> nodes_of(const Stencil<ORDER> &s, int ng)
+{
+    Nodes<ORDER> o;
+    o.n[0] = wrap_node(s.first, ng);
+#pragma unroll
+    for (int k = 1; k <= ORDER; ++k)
+        o.n[k] = (o.n[k - 1] + 1 == ng) ? 0 : o.n[k - 1] + 1;
+    return o;
+}
+
+template <int ORDER>
+__device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDER> &s,
+                                          const Nodes<ORDER> &n)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k <= ORDER; ++k)
+        acc += tile[n.n[k]] * s.w[k];
+    return acc;
+}
+
+template <int ORDER>
+__device__ __forceinline__ void deposit1(double *tile, const Stencil<ORDER> &s,
+                                         const Nodes<ORDER> &n, double q)
+{
+#pragma unroll
+    for (int k = 0; k <= ORDER; ++k)
+        atomicAdd(&tile[n.n[k]], q * s.w[k]);
+}
+
+__device__ __forceinline__ double wrap_pos(double x, double L)
+{
+    x = x - L * floor(x / L);
+    if (x < 0.0)
+        x += L;
+    if (x >= L)
+        x = 0.0;
+    return x;
+}
+
+// --------------------------------------------------------------- block reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Deterministic block sum; every thread gets the result.  red: >= 16 doubles of LDS.
+__device__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i)
+        t += red[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ double block_max(double v, double *red)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red[wid] = v;
+    __syncthreads();
+    double t = red[0];
+    for (int i = 1; i < nw; ++i)
+        t = fmax(t, red[i]);
+    __syncthreads();
+    return t;
+}
+
+// --------------------------------------------------------------- particle kernels
+// The particle's half-step quantities, computed identically in both passes.
+template <int ORDER, int NV, bool EM> struct Half {
+    double vs[NV];       // v*
+    double x1;           // x^{n+1} (unwrapped)
+    double xh;           // x^{n+1/2}
+};
+
+// v* solves v* = u + v* x t with u = v^n + dt/2 E**, t = dt/2 B** (eq. (good_translation)
+// second line, eq. (EMbasic) fourth line): v* = (u + u x t + (u.t) t) / (1 + |t|^2).
+__device__ __forceinline__ void rotate_half(const double u[3], const double t[3], double o[3])
+{
+    double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double inv = 1.0 / (1.0 + tt);
+    o[0] = (u[0] + (u[1] * t[2] - u[2] * t[1]) + ut * t[0]) * inv;
+    o[1] = (u[1] + (u[2] * t[0] - u[0] * t[2]) + ut * t[1]) * inv;
+    o[2] = (u[2] + (u[0] * t[1] - u[1] * t[0]) + ut * t[2]) * inv;
+}
+
+// tiles: es[ne][ng] predictor E, bs[2][ng] predictor B (EM)
+template <int ORDER, int NV, bool EM>
+__device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x, const double v[NV],
+                                                        const double *es, const double *bs)
+{
+    Half<ORDER, NV, EM> o;
+    const double xs = x + r.hdt * v[0];
+    const Stencil<ORDER> s = stencil<ORDER>(xs * r.inv_h);
+    const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+    if constexpr (NV == 1) {
+        o.vs[0] = v[0] + r.hdt * gather1<ORDER>(es, s, n);
+    } else {
+        double u[3], t[3];
+        u[0] = v[0] + r.hdt * gather1<ORDER>(es, s, n);
+        if constexpr (EM) {
+            u[1] = v[1] + r.hdt * gather1<ORDER>(es + r.ng, s, n);
+            u[2] = v[2] + r.hdt * gather1<ORDER>(es + 2 * r.ng, s, n);
+            const Stencil<ORDER> sh = stencil<ORDER>(xs * r.inv_h - 0.5);
+            const Nodes<ORDER> nh = nodes_of<ORDER>(sh, r.ng);
+            t[0] = r.hdt * r.bext[0];
+            t[1] = r.hdt * (r.bext[1] + gather1<ORDER>(bs, sh, nh));
+            t[2] = r.hdt * (r.bext[2] + gather1<ORDER>(bs + r.ng, sh, nh));
+        } else {
+            u[1] = v[1];
+            u[2] = v[2];
+            t[0] = r.hdt * r.bext[0];
+            t[1] = r.hdt * r.bext[1];
+            t[2] = r.hdt * r.bext[2];
+        }
+        rotate_half(u, t, o.vs);
+    }
+    o.x1 = x + r.dt * o.vs[0];
+    o.xh = 0.5 * (x + o.x1);
+    return o;
+}
+
+template <int NV, bool EM> struct TileSizes {
+    static constexpr int ne = EM ? 3 : 1;      // E components gathered
+    static constexpr int nb = EM ? 2 : 0;      // B components gathered
+    static constexpr int ncur = EM ? 3 : 1;    // current components deposited
+};
+
+// Cooperative load of n doubles into LDS.
+__device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = src[i];
+}
+
+__device__ __forceinline__ void tile_zero(double *dst, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = 0.0;
+}
+
+// Flush a block's LDS current tile into the global accumulator (hardware FP64 atomics).
+__device__ __forceinline__ void tile_flush(const double *tile, double *J, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double val = tile[i];
+        if (val != 0.0)
+            unsafeAtomicAdd(&J[i], val);
+    }
+}
+
+// Pass A: gather E* (B*) at x*, v*, deposit w v* at x^{n+1/2} into J2.
+template <int ORDER, int NV, bool EM>
+__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, const double *__restrict__ X,
+                                                 const double *__restrict__ V)
+{
+    using T = TileSizes<NV, EM>;
+    extern __shared__ double smem[];
+    double *es = smem;                         // [ne][ng]
+    double *bs = es + T::ne * r.ng;            // [nb][ng]
+    double *jt = bs + T::nb * r.ng;            // [ncur][ng]
+    tile_load(es, wk.Es, T::ne * r.ng);
+    if constexpr (EM)
+        tile_load(bs, wk.Bs, T::nb * r.ng);
+    tile_zero(jt, T::ncur * r.ng);
+    __syncthreads();
+
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double v[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            v[c] = V[c * r.np + p];
+        const double x = X[p];
+        const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, x, v, es, bs);
+        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+        const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
+        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+        deposit1<ORDER>(jt, s, n, q * hs.vs[0]);
+        if constexpr (EM) {
+            deposit1<ORDER>(jt + r.ng, s, n, q * hs.vs[1]);
+            deposit1<ORDER>(jt + 2 * r.ng, s, n, q * hs.vs[2]);
+        }
+    }
+    __syncthreads();
+    tile_flush(jt, wk.J2, T::ncur * r.ng);
+}
+
+// Pass B: recompute the half step, gather the averaged fields at x^{n+1/2}, v-dagger,
+// Gamma with fallback, write the new state; then (PRED) deposit the next step's
+// predictor current w v^{n+1} at x*_{n+1} into J1.
+template <int ORDER, int NV, bool EM, bool PRED>
+__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, const double *X, const double *V,
+                                                 double *Xo, double *Vo)
+{
+    using T = TileSizes<NV, EM>;
+    extern __shared__ double smem[];
+    double *es = smem;                         // E*
+    double *bs = es + T::ne * r.ng;            // B*
+    double *eb = bs + T::nb * r.ng;            // E-bar
+    double *bb = eb + T::ne * r.ng;            // B-bar
+    double *jt = bb + T::nb * r.ng;            // predictor current tile
+    __shared__ double red[16];
+    tile_load(es, wk.Es, T::ne * r.ng);
+    tile_load(eb, wk.Eb, T::ne * r.ng);
+    if constexpr (EM) {
+        tile_load(bs, wk.Bs, T::nb * r.ng);
+        tile_load(bb, wk.Bb, T::nb * r.ng);
+    }
+    if constexpr (PRED)
+        tile_zero(jt, T::ncur * r.ng);
+    __syncthreads();
+
+    double ke = 0.0, gdev = 0.0;
+    int fb = 0, nonfinite = 0;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double v[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            v[c] = V[c * r.np + p];
+        const double x = X[p];
+        const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, x, v, es, bs);
+        const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
+        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+        double vd[NV];
+        if constexpr (NV == 1) {
+            vd[0] = v[0] + r.dt * gather1<ORDER>(eb, s, n);
+        } else {
+            double e[3], b[3];
+            e[0] = gather1<ORDER>(eb, s, n);
+            b[0] = r.bext[0];
+            if constexpr (EM) {
+                e[1] = gather1<ORDER>(eb + r.ng, s, n);
+                e[2] = gather1<ORDER>(eb + 2 * r.ng, s, n);
+                const Stencil<ORDER> sh = stencil<ORDER>(hs.xh * r.inv_h - 0.5);
+                const Nodes<ORDER> nh = nodes_of<ORDER>(sh, r.ng);
+                b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
+                b[2] = r.bext[2] + gather1<ORDER>(bb + r.ng, sh, nh);
+            } else {
+                e[1] = 0.0;
+                e[2] = 0.0;
+                b[1] = r.bext[1];
+                b[2] = r.bext[2];
+            }
+            // v-dagger = v^n + dt (E-bar + v* x B-bar)   (eq. (good_translation), (EMbasic))
+            vd[0] = v[0] + r.dt * (e[0] + (hs.vs[1] * b[2] - hs.vs[2] * b[1]));
+            vd[1] = v[1] + r.dt * (e[1] + (hs.vs[2] * b[0] - hs.vs[0] * b[2]));
+            vd[2] = v[2] + r.dt * (e[2] + (hs.vs[0] * b[1] - hs.vs[1] * b[0]));
+        }
+        // Gamma (eq. (opt_solution)); an imaginary or undefined root falls back to 1
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            num += (hs.vs[c] - 0.5 * (vd[c] + v[c])) * (vd[c] - v[c]);
+            den += vd[c] * vd[c];
+        }
+        const double rr = 1.0 + 2.0 * num / den;
+        double g;
+        if (rr >= 0.0 && isfinite(rr)) {
+            g = sqrt(rr);
+        } else {
+            g = 1.0;
+            ++fb;
+        }
+        gdev = fmax(gdev, fabs(g - 1.0));
+        double vn[NV];
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            vn[c] = g * vd[c];
+            v2 += vn[c] * vn[c];
+            Vo[c * r.np + p] = vn[c];
+        }
+        const double xw = wrap_pos(hs.x1, r.L);
+        Xo[p] = xw;
+        const double wp = r.w ? r.w[p] : r.wu;
+        ke += wp * v2;
+        if (!isfinite(v2) || !isfinite(hs.x1))
+            nonfinite = 1;
+        if constexpr (PRED) {
+            const double q = wp * r.qs;
+            const Stencil<ORDER> s2 = stencil<ORDER>((xw + r.hdt * vn[0]) * r.inv_h);
+            const Nodes<ORDER> n2 = nodes_of<ORDER>(s2, r.ng);
+            deposit1<ORDER>(jt, s2, n2, q * vn[0]);
+            if constexpr (EM) {
+                deposit1<ORDER>(jt + r.ng, s2, n2, q * vn[1]);
+                deposit1<ORDER>(jt + 2 * r.ng, s2, n2, q * vn[2]);
+            }
+        }
+    }
+    const double bke = block_sum(ke, red);
+    const double bgd = block_max(gdev, red);
+    const double bfb = block_sum((double)fb, red);
+    const double bnf = block_max((double)nonfinite, red);
+    if (threadIdx.x == 0) {
+        wk.part_ke[blockIdx.x] = 0.5 * bke;
+        wk.part_gd[blockIdx.x] = bgd;
+        wk.part_fb[blockIdx.x] = (int64_t)bfb;
+        wk.part_nf[blockIdx.x] = (int32_t)bnf;
+    }
+    if constexpr (PRED) {
+        __syncthreads();
+        tile_flush(jt, wk.J1, T::ncur * r.ng);
+    }
+}
+
+// Predictor deposit of the initial state: w v^0 at x*_0 = x^0 + dt/2 v^0 into J1.
+template <int ORDER, int NV, bool EM>
+__global__ __launch_bounds__(1024) void k_predeposit(Run r, Work wk, const double *__restrict__ X,
+                                                     const double *__restrict__ V)
+{
+    using T = TileSizes<NV, EM>;
+    extern __shared__ double smem[];
+    double *jt = smem;
+    tile_zero(jt, T::ncur * r.ng);
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+        const double vx = V[p];
+        const Stencil<ORDER> s = stencil<ORDER>((X[p] + r.hdt * vx) * r.inv_h);
+        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+        deposit1<ORDER>(jt, s, n, q * vx);
+        if constexpr (EM) {
+            deposit1<ORDER>(jt + r.ng, s, n, q * V[r.np + p]);
+            deposit1<ORDER>(jt + 2 * r.ng, s, n, q * V[2 * r.np + p]);
+        }
+    }
+    __syncthreads();
+    tile_flush(jt, wk.J1, T::ncur * r.ng);
+}
+
+// Charge deposit rho_i = (1/h) sum_p w_p S(x_i - x_p) into J1[0..ng) (initial Gauss).
+template <int ORDER>
+__global__ __launch_bounds__(1024) void k_deposit_rho(Run r, Work wk, const double *__restrict__ X)
+{
+    extern __shared__ double smem[];
+    double *jt = smem;
+    tile_zero(jt, r.ng);
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const Stencil<ORDER> s = stencil<ORDER>(X[p] * r.inv_h);
+        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+        deposit1<ORDER>(jt, s, n, (r.w ? r.w[p] : r.wu) * r.qs);
+    }
+    __syncthreads();
+    tile_flush(jt, wk.J1, r.ng);
+}
+
+// Wrap positions into [0, L) and sum the initial kinetic energy per block.
+template <int NV>
+__global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double *__restrict__ X,
+                                                         const double *__restrict__ V)
+{
+    __shared__ double red[16];
+    double ke = 0.0;
+    int nonfinite = 0;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const double vc = V[c * r.np + p];
+            v2 += vc * vc;
+        }
+        const double x = X[p];
+        if (!isfinite(x) || !isfinite(v2))
+            nonfinite = 1;
+        X[p] = wrap_pos(x, r.L);
+        ke += (r.w ? r.w[p] : r.wu) * v2;
+    }
+    const double bke = block_sum(ke, red);
+    const double bnf = block_max((double)nonfinite, red);
+    if (threadIdx.x == 0) {
+        wk.part_ke[blockIdx.x] = 0.5 * bke;
+        wk.part_gd[blockIdx.x] = 0.0;
+        wk.part_fb[blockIdx.x] = 0;
+        wk.part_nf[blockIdx.x] = (int32_t)bnf;
+    }
+}
+
+// ------------------------------------------------------------------- grid kernels
+// All grid kernels run as ONE workgroup; the grid is at most a few thousand nodes.
+
+// Staggered differences: nodes f[i] at i h, half nodes g[i] at (i + 1/2) h.
+__device__ __forceinline__ double dplus(const double *f, int i, int ng, double inv_h)
+{
+    return (f[i + 1 == ng ? 0 : i + 1] - f[i]) * inv_h;
+}
+__device__ __forceinline__ double dminus(const double *g, int i, int ng, double inv_h)
+{
+    return (g[i] - g[i == 0 ? ng - 1 : i - 1]) * inv_h;
+}
+
+// Predictor fields from J1, then clear J1.
+//   ES   : E* = E - dt/2 (j - mean j)                        (eq. (good_translation))
+//   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
+//   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
+// In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
+__device__ void predictor_fields(const Run &r, const Work &wk, int scheme, double *red)
+{
+    const int ng = r.ng;
+    if (scheme == 1) {
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            wk.Es[i] = wk.E[i];
+        return;
+    }
+    if (scheme == 0) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            s += wk.J1[i];
+        const double mean = block_sum(s, red) / ng;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+            wk.Es[i] = wk.E[i] - r.hdt * (wk.J1[i] - mean);
+            wk.J1[i] = 0.0;
+        }
+        return;
+    }
+    const double *Ex = wk.E, *Ey = wk.E + ng, *Ez = wk.E + 2 * ng;
+    const double *By = wk.B, *Bz = wk.B + ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        wk.Es[i] = Ex[i] - r.hdt * wk.J1[i];
+        wk.Es[ng + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - wk.J1[ng + i]);
+        wk.Es[2 * ng + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - wk.J1[2 * ng + i]);
+        wk.Bs[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
+        wk.Bs[ng + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+        wk.J1[i] = 0.0;
+}
+
+__device__ void field_energies(const Run &r, const Work &wk, bool em, double *red)
+{
+    const int ng = r.ng;
+    const int ne = em ? 3 : 1;
+    double se = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < ne * ng; i += blockDim.x)
+        se += wk.E[i] * wk.E[i];
+    if (em)
+        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+            sb += wk.B[i] * wk.B[i];
+    const double we = 0.5 * r.h * block_sum(se, red);
+    const double wb = em ? 0.5 * r.c2 * r.h * block_sum(sb, red) : 0.0;
+    if (threadIdx.x == 0) {
+        wk.st->we = we;
+        wk.st->wb = wb;
+    }
+}
+
+// Ampere / Crank-Nicolson update from J2 (then cleared): E^{n+1}, B^{n+1} in place and
+// the averaged fields E-bar, B-bar for pass B; records W_E^{n+1}, W_B^{n+1}.
+//   ES: E^{n+1} = E^n - dt (j - mean j)
+//   EM (a = dt/2, s = a^2 c^2, L_h = D-D+):
+//     (I - s L_h) E_y' = (I + s L_h) E_y - dt c^2 D-B_z - dt j_y,  B_z' = B_z - a D+(E_y + E_y')
+//     (I - s L_h) E_z' = (I + s L_h) E_z + dt c^2 D-B_y - dt j_z,  B_y' = B_y + a D+(E_z + E_z')
+//     E_x' = E_x - dt j_x
+// The circulant system is solved with the precomputed first row of its inverse.
+__global__ __launch_bounds__(1024) void k_field_update(Run r, Work wk, int em)
+{
+    __shared__ double red[16];
+    const int ng = r.ng;
+    if (!em) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            s += wk.J2[i];
+        const double mean = block_sum(s, red) / ng;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+            const double e0 = wk.E[i];
+            const double e1 = e0 - r.dt * (wk.J2[i] - mean);
+            wk.E[i] = e1;
+            wk.Eb[i] = 0.5 * (e0 + e1);
+            wk.J2[i] = 0.0;
+        }
+        __syncthreads();
+        field_energies(r, wk, false, red);
+        return;
+    }
+    extern __shared__ double smem[];
+    double *E0 = smem;               // [3][ng]
+    double *B0 = E0 + 3 * ng;        // [2][ng]
+    double *R = B0 + 2 * ng;         // [2][ng] right-hand sides
+    double *E1 = R + 2 * ng;         // [3][ng]
+    double *g = E1 + 3 * ng;         // [ng]
+    tile_load(E0, wk.E, 3 * ng);
+    tile_load(B0, wk.B, 2 * ng);
+    tile_load(g, wk.cninv, ng);
+    __syncthreads();
+    const double a = r.hdt, s = a * a * r.c2, ih2 = r.inv_h * r.inv_h;
+    const double *Ey = E0 + ng, *Ez = E0 + 2 * ng, *By = B0, *Bz = B0 + ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const int ip = i + 1 == ng ? 0 : i + 1, im = i == 0 ? ng - 1 : i - 1;
+        E1[i] = E0[i] - r.dt * wk.J2[i];
+        R[i] = Ey[i] + s * (Ey[ip] - 2.0 * Ey[i] + Ey[im]) * ih2
+               - r.dt * r.c2 * dminus(Bz, i, ng, r.inv_h) - r.dt * wk.J2[ng + i];
+        R[ng + i] = Ez[i] + s * (Ez[ip] - 2.0 * Ez[i] + Ez[im]) * ih2
+                    + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * wk.J2[2 * ng + i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        double ay = 0.0, az = 0.0;
+        for (int j = 0; j < ng; ++j) {
+            int k = i - j;
+            k += k < 0 ? ng : 0;
+            ay += g[k] * R[j];
+            az += g[k] * R[ng + j];
+        }
+        E1[ng + i] = ay;
+        E1[2 * ng + i] = az;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const int ip = i + 1 == ng ? 0 : i + 1;
+        const double bz1 = Bz[i] - a * ((Ey[ip] + E1[ng + ip]) - (Ey[i] + E1[ng + i])) * r.inv_h;
+        const double by1 = By[i] + a * ((Ez[ip] + E1[2 * ng + ip]) - (Ez[i] + E1[2 * ng + i])) * r.inv_h;
+        wk.Bb[i] = 0.5 * (By[i] + by1);
+        wk.Bb[ng + i] = 0.5 * (Bz[i] + bz1);
+        wk.B[i] = by1;
+        wk.B[ng + i] = bz1;
+    }
+    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x) {
+        wk.Eb[i] = 0.5 * (E0[i] + E1[i]);
+        wk.E[i] = E1[i];
+        wk.J2[i] = 0.0;
+    }
+    __syncthreads();
+    field_energies(r, wk, true, red);
+}
+
+// Close the step: sum the block partials of pass B in a fixed order, write the record,
+// then build the next step's predictor fields.  `init` finalises step 0 instead.
+__global__ __launch_bounds__(1024) void k_field_tail(Run r, Work wk, int scheme, int init)
+{
+    __shared__ double red[16];
+    double ke = 0.0, gd = 0.0, fb = 0.0, nf = 0.0;
+    for (int b = threadIdx.x; b < r.nblocks; b += blockDim.x) {
+        ke += wk.part_ke[b];
+        gd = fmax(gd, wk.part_gd[b]);
+        fb += (double)wk.part_fb[b];
+        nf = fmax(nf, (double)wk.part_nf[b]);
+    }
+    ke = block_sum(ke, red);
+    gd = block_max(gd, red);
+    fb = block_sum(fb, red);
+    nf = block_max(nf, red);
+    if (init)
+        field_energies(r, wk, scheme == 2, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DevState *st = wk.st;
+        if (init) {
+            st->step = 0;
+            st->fb_total = 0;
+            st->nonfinite_sticky = 0;
+        } else {
+            st->step += 1;
+        }
+        const double te = ke + st->we + st->wb;
+        if (init)
+            st->te0 = te;
+        st->fb_total += (int64_t)fb;
+        st->nonfinite_sticky |= (nf != 0.0);
+        DevRecord rec;
+        rec.step = st->step;
+        rec.time = (double)st->step * r.dt;
+        rec.kinetic = ke;
+        rec.field_e = st->we;
+        rec.field_b = st->wb;
+        rec.total = te;
+        rec.rel_energy_err = fabs(te - st->te0) / st->te0;
+        rec.max_gamma_dev = gd;
+        rec.fallbacks = (int64_t)fb;
+        rec.fallbacks_total = st->fb_total;
+        rec.nonfinite = nf != 0.0;
+        rec.pad = 0;
+        wk.rec[st->step % r.rec_cap] = rec;
+    }
+    __syncthreads();
+    predictor_fields(r, wk, scheme, red);
+}
+
+// Initial Gauss solve: dE/dx = rho - 1 with rho in J1 (then cleared).  Spectrally on the
+// nodes: E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2, mean and Nyquist
+// modes zero (the Poisson form, eq. (poisson), in 1D).
+__global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
+{
+    extern __shared__ double smem[];
+    const int ng = r.ng;
+    double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
+    tile_load(rho, wk.J1, ng);
+    __syncthreads();
+    for (int m = threadIdx.x; m < ng; m += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        if (m != 0 && 2 * m != ng) {
+            for (int l = 0; l < ng; ++l) {
+                const long long ml = ((long long)m * l) % ng;
+                double sn, cs;
+                sincospi(2.0 * (double)ml / ng, &sn, &cs);
+                re += rho[l] * cs;
+                im -= rho[l] * sn;
+            }
+            const int ms = m <= ng / 2 ? m : m - ng;
+            const double k = 2.0 * M_PI * ms / r.L;
+            const double tr = re, ti = im;
+            re = ti / k;          // (tr + i ti) / (i k) = ti / k - i tr / k
+            im = -tr / k;
+        }
+        er[m] = re;
+        ei[m] = im;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        double acc = 0.0;
+        for (int m = 1; m < ng; ++m) {
+            const long long mi = ((long long)m * i) % ng;
+            double sn, cs;
+            sincospi(2.0 * (double)mi / ng, &sn, &cs);
+            acc += er[m] * cs - ei[m] * sn;
+        }
+        wk.E[i] = acc / ng;
+        wk.J1[i] = 0.0;
+    }
+}
+
+// First row of (I - s L_h)^{-1} for the periodic 3-point Laplacian: circulant, so
+// g_k = (1/N) sum_m cos(2 pi m k / N) / (1 + s (4/h^2) sin^2(pi m / N)).
+__global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk)
+{
+    const int ng = r.ng;
+    const double s = r.hdt * r.hdt * r.c2;
+    for (int k = threadIdx.x; k < ng; k += blockDim.x) {
+        double acc = 0.0;
+        for (int m = 0; m < ng; ++m) {
+            const double sn = sinpi((double)m / ng);
+            const double lam = 1.0 + s * 4.0 * r.inv_h * r.inv_h * sn * sn;
+            const long long mk = ((long long)m * k) % ng;
+            acc += cospi(2.0 * (double)mk / ng) / lam;
+        }
+        wk.cninv[k] = acc / ng;
+    }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace pic

@@ -1,0 +1,83 @@
+"""Helpers shared by the GPU tests: run a workload on the GPU (through the C ABI) and
+in the oracle on the same seeded inputs, and compare (test helper, not a test).
+
+Comparison metric (the 1e-10 relative parity bar): positions are compared modulo L
+against the scale L; velocities against max|v^0|; each field array at each step against
+the oracle's max|field| at that step.  Particles keep their index order unless a rebin
+ran, in which case they are matched through their ids.
+"""
+import numpy as np
+
+import oracle
+
+TOL = 1e-10
+
+
+def periodic_err(a, b, L):
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    return np.minimum(d, L - d)
+
+
+def order_by_ids(st):
+    if "ids" not in st:
+        return st
+    perm = np.argsort(st["ids"], kind="stable")
+    out = dict(st)
+    out["x"] = st["x"][perm]
+    out["v"] = st["v"][:, perm]
+    out["ids"] = st["ids"][perm]
+    return out
+
+
+def compare_state(gst, ost, L, vscale, em, tol=TOL, where=""):
+    gst = order_by_ids(gst)
+    ex = periodic_err(gst["x"], ost.x, L).max()
+    ev = np.abs(gst["v"] - ost.v).max()
+    assert ex <= tol * L, f"{where}: position error {ex:.3e} > {tol * L:.3e}"
+    assert ev <= tol * vscale, f"{where}: velocity error {ev:.3e} > {tol * vscale:.3e}"
+    ne = 3 if em else 1
+    for c in range(ne):
+        scale = max(np.abs(ost.E[c]).max(), 1e-300)
+        ee = np.abs(gst["E"][c] - ost.E[c]).max()
+        assert ee <= tol * scale, f"{where}: E[{c}] error {ee:.3e} > {tol * scale:.3e}"
+    if em:
+        for c in range(2):
+            scale = max(np.abs(ost.B[c]).max(), 1e-300)
+            eb = np.abs(gst["B"][c] - ost.B[c]).max()
+            assert eb <= tol * scale, f"{where}: B[{c}] error {eb:.3e} > {tol * scale:.3e}"
+    return ex, ev
+
+
+def compare_records(grec, orec, tol=TOL):
+    """GPU records (pic_diag) against oracle records: energies to tol relative to the
+    initial total energy, fallback counts exactly."""
+    te0 = orec["total"][0]
+    for f in ("kinetic", "field_e", "field_b", "total"):
+        err = np.abs(grec[f] - orec[f]).max()
+        assert err <= tol * te0, f"record {f}: {err:.3e}"
+    assert np.array_equal(grec["fallbacks"], orec["fallbacks"]), \
+        (grec["fallbacks"], orec["fallbacks"])
+
+
+def run_pair(wl, steps, scheme=None, every=1, tol=TOL, **knobs):
+    """Run ``steps`` steps on the GPU and in the oracle, comparing every ``every`` steps.
+    Returns (gpu records, oracle records, gpu Pic, oracle State)."""
+    from paper_2411_09605_amd import Pic
+    em = (scheme or wl.scheme) == "emec_li"
+    gpu = Pic.from_workload(wl, scheme=scheme, **knobs)
+    ost = oracle.State(wl, scheme=scheme)
+    vscale = max(1.0, float(np.abs(wl.v).max()))
+    grecs = [gpu.diagnostics()]
+    orecs = [ost.run(0)]
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        gpu.step(n)
+        grecs.append(gpu.diagnostics())
+        orecs.append(ost.run(n)[1:])
+        done += n
+        compare_state(gpu.state(), ost, wl.length, vscale, em, tol, where=f"step {done}")
+    grec = np.concatenate(grecs)
+    orec = np.concatenate(orecs)
+    compare_records(grec, orec, tol)
+    return grec, orec, gpu, ost

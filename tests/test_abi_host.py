@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every function
+declared in include/pic.h, and validates parameters without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pic.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2411_09605_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(P.EXPORTS) == names
+
+
+def _good(**kw):
+    import paper_2411_09605_amd as P
+    base = dict(nv=1, scheme="esec2", shape_order=2, n_particles=1000, n_cells=64,
+                length=10.0, dt=0.1)
+    base.update(kw)
+    return P.make_params(**base)
+
+
+def test_validation_accepts_and_sizes():
+    import paper_2411_09605_amd as P
+    for kw in [{}, dict(scheme="esec1"), dict(nv=3, scheme="emec_li", n_cells=256),
+               dict(nv=3, b_ext=(1.0, 0.0, 0.0)), dict(shape_order=1, n_cells=3),
+               dict(n_particles=1), dict(block_threads=1024, grid_blocks=8192)]:
+        p = _good(**kw)
+        assert P.validate(p) == 0, (kw, P.last_error())
+        assert P.workspace_size(p) > 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nv=2), -1), (dict(scheme=7), -1), (dict(nv=1, scheme="emec_li"), -1),
+    (dict(shape_order=3), -1), (dict(n_particles=0), -1), (dict(n_cells=4), -1),
+    (dict(shape_order=1, n_cells=2), -1), (dict(length=0.0), -1), (dict(dt=-1.0), -1),
+    (dict(dt=float("nan")), -1), (dict(nv=3, scheme="emec_li", c=0.0), -1),
+    (dict(nv=3, b_ext=(float("inf"), 0, 0)), -1), (dict(block_threads=100), -1),
+    (dict(grid_blocks=100000), -1), (dict(deposit_mode=9), -1), (dict(rebin_every=-1), -1),
+    (dict(n_cells=100000), -6), (dict(nv=3, scheme="emec_li", n_cells=4096), -6),
+])
+def test_validation_rejects(kw, code):
+    import paper_2411_09605_amd as P
+    p = _good(**kw)
+    assert P.validate(p) == code, P.last_error()
+    assert P.last_error()
+    assert P.workspace_size(p) == 0
+
+
+def test_abi_version_and_reserved_checked():
+    import paper_2411_09605_amd as P
+    p = _good()
+    p.abi_version = 99
+    assert P.validate(p) == -1
+    p = _good()
+    p.reserved = 1
+    assert P.validate(p) == -1
+
+
+def test_strerror_and_null_handling():
+    import paper_2411_09605_amd as P
+    lib = P.binding.lib
+    assert lib.pic_strerror(0) == b"ok"
+    assert lib.pic_strerror(-6) == b"unsupported configuration"
+    assert lib.pic_validate_params(None) == -1
+    assert lib.pic_step(None, 1) == -4
+    assert lib.pic_destroy(None) == -4
+    out = ctypes.c_void_p()
+    assert lib.pic_init(None, None, None, ctypes.byref(out)) == -1

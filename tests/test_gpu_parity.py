@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same seeded
+inputs, element by element, over the first 10 steps (1e-10 relative, the metric in
+tests/gpu_util.py), plus long-run properties and edge cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import gpu_util as gu
+from tests import theory
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_09605_amd  # noqa: F401  (raises if the library is missing)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# --------------------------------------------------------------- 10-step parity cases
+def test_landau_full_config_10_steps():
+    """1D-1V Landau, 64 cells, 1e5 particles, tent, dt 0.1 (the small workload)."""
+    _say("case: landau 1e5 x 64, esec2, order 1")
+    wl = workloads.landau()
+    grec, orec, _, _ = gu.run_pair(wl, 10)
+    assert grec["rel_energy_err"].max() < 1e-12
+
+
+def test_two_stream_mini_quadratic_10_steps():
+    _say("case: two-stream 2e5 x 512, esec2, order 2")
+    wl = workloads.two_stream(n_particles=200_000, n_cells=512, steps=10)
+    gu.run_pair(wl, 10)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_esec1_10_steps(order):
+    _say(f"case: landau esec1 order {order}")
+    wl = workloads.landau(n_particles=50_000, n_cells=48, order=order)
+    gu.run_pair(wl, 10, scheme="esec1")
+
+
+def test_es_3v_external_field_weights_ragged():
+    """1D-3V electrostatic with an imposed uniform B, non-uniform weights and a particle
+    count that leaves a ragged last workgroup."""
+    _say("case: ES 3V b_ext, weights, ragged 30001")
+    n = 30_001
+    wl = workloads.landau(n_particles=n, n_cells=40, alpha=0.1, order=2)
+    wl.v = np.stack([wl.v[0], workloads.normals(9, 12, n), workloads.normals(9, 14, n)])
+    wl.nv = 3
+    wl.b_ext = (0.3, -0.6, 1.2)
+    wl.w = wl.length / n * (1.0 + 0.5 * workloads.uniforms(9, 20, n))
+    gu.run_pair(wl, 10)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_em_li_mini_10_steps(order):
+    _say(f"case: EM weibel 1e5 x 256 order {order}")
+    wl = workloads.weibel(n_particles=100_000, n_cells=256, order=order, steps=10)
+    wl.B0 *= 50.0                    # make the field terms large enough to matter
+    gu.run_pair(wl, 10)
+
+
+def test_gauss_init_matches():
+    _say("case: Gauss initial field, two-stream 1e5 x 256")
+    from paper_2411_09605_amd import Pic
+    wl = workloads.two_stream(n_particles=100_000, n_cells=256, alpha=0.05)
+    gpu = Pic.from_workload(wl)
+    rec = gpu.diagnostics()
+    ost = oracle.State(wl)
+    orec = ost.run(0)
+    E = gpu.state()["E"][0]
+    assert np.abs(E - ost.E[0]).max() < 1e-12 * np.abs(ost.E[0]).max()
+    assert abs(rec["total"][0] - orec["total"][0]) < 1e-13 * orec["total"][0]
+
+
+# ---------------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("n,ng,order", [(1, 3, 1), (1, 5, 2), (2, 5, 2), (63, 3, 1),
+                                        (65, 7, 2), (257, 5, 1)])
+def test_tiny_and_minimum_grids(n, ng, order):
+    _say(f"case: tiny n={n} ng={ng} order={order}")
+    wl = workloads.landau(n_particles=n, n_cells=ng, order=order, alpha=0.2)
+    gu.run_pair(wl, 10)
+
+
+def test_launch_shapes_agree():
+    """Different workgroup sizes and counts give the same result (to roundoff)."""
+    _say("case: launch shapes")
+    wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
+    for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
+        gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
+
+
+def test_fast_particles_cross_several_cells():
+    """dt large enough that particles move several cells (and beyond the domain) per
+    step: node wrapping far outside [0, L)."""
+    _say("case: fast particles")
+    wl = workloads.landau(n_particles=5000, n_cells=16, dt=0.5, alpha=0.1)
+    wl.v = wl.v * 6.0
+    gu.run_pair(wl, 10)
+
+
+def test_boris_limit_on_gpu():
+    _say("case: Boris limit")
+    from paper_2411_09605_amd import Pic
+    from tests.test_oracle_pins import _boris_reference
+    n, steps, dt = 1000, 20, 0.3
+    rng = np.random.default_rng(3)
+    L = 5.0
+    x = rng.uniform(0, L, n)
+    v = rng.normal(size=(3, n))
+    b = (0.4, -1.3, 2.0)
+    for scheme in ("esec2", "emec_li"):
+        gpu = Pic.from_arrays(3, scheme, 2, 16, L, dt, x, v, w=np.zeros(n), b_ext=b)
+        gpu.step(steps)
+        st = gpu.state()
+        xr, vr = _boris_reference(x, v, b, dt, L, steps)
+        assert gu.periodic_err(st["x"], xr, L).max() < 1e-12
+        assert np.abs(st["v"] - vr).max() < 1e-12
+        rec = gpu.diagnostics()
+        assert rec["fallbacks"].sum() == 0 and rec["max_gamma_dev"].max() < 1e-14
+
+
+# ------------------------------------------------------------ long runs / properties
+def test_landau_200_steps_energy_and_rate():
+    """Whole Landau run: energy <= 1e-11 and the damping rate within 2% of the oracle's."""
+    _say("case: landau 200 steps quiet")
+    from paper_2411_09605_amd import Pic
+    wl = workloads.landau(quiet=True, steps=130)
+    gpu = Pic.from_workload(wl)
+    ost = oracle.State(wl)
+    ga, oa = [], []
+    for _ in range(wl.steps):
+        gpu.step(1)
+        ost.run(1)
+        ga.append(theory.mode_amplitude(gpu.state()["E"][0], 1))
+        oa.append(theory.mode_amplitude(ost.E[0], 1))
+    rec = np.concatenate(gpu.records + [gpu.diagnostics()]) if gpu.records else gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+    t = (np.arange(wl.steps) + 1) * wl.dt
+
+    def rate(a):
+        a = np.array(a)
+        pk = [i for i in range(1, len(a) - 1) if a[i] > a[i - 1] and a[i] >= a[i + 1]
+              and 2.0 <= t[i] <= 12.5]
+        return np.polyfit(t[pk], np.log(a[pk]), 1)[0]
+    gr, orate = rate(ga), rate(oa)
+    assert abs(gr - orate) < 0.02 * abs(orate), (gr, orate)
+
+
+def test_two_stream_growth_rate_matches_oracle():
+    _say("case: two-stream growth 1e5 quiet")
+    from paper_2411_09605_amd import Pic
+    wl = workloads.two_stream(n_particles=100_000, n_cells=128, alpha=1e-4, quiet=True,
+                              steps=400)
+    gpu = Pic.from_workload(wl)
+    ost = oracle.State(wl)
+    ga, oa = [], []
+    for _ in range(wl.steps):
+        gpu.step(1)
+        ost.run(1)
+        ga.append(theory.mode_amplitude(gpu.E[0].cpu().numpy(), 1))
+        oa.append(theory.mode_amplitude(ost.E[0], 1))
+    t = (np.arange(wl.steps) + 1) * wl.dt
+    sel = (t > 12) & (t < 20)
+    gr = np.polyfit(t[sel], np.log(np.array(ga)[sel]), 1)[0]
+    orate = np.polyfit(t[sel], np.log(np.array(oa)[sel]), 1)[0]
+    assert abs(gr - orate) < 0.02 * orate
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+
+
+# ------------------------------------------------------------- full-size workloads
+def test_two_stream_full_size_parity_and_energy():
+    """The 1e7-particle, 512-cell two-stream workload in the launch configuration the
+    benchmark times: 2 steps element by element against the oracle, then 100 more steps
+    with the energy bar."""
+    _say("case: two-stream FULL 1e7 x 512")
+    wl = workloads.two_stream()
+    grec, orec, gpu, _ = gu.run_pair(wl, 2, every=2)
+    gpu.step(100)
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+    assert rec["nonfinite"].max() == 0
+
+
+def test_weibel_full_size_parity():
+    """The 2e7-particle 1D-3V electromagnetic workload: 1 step against the oracle, then
+    50 more with the energy bar."""
+    _say("case: weibel FULL 2e7 x 256")
+    wl = workloads.weibel()
+    grec, orec, gpu, _ = gu.run_pair(wl, 1)
+    gpu.step(50)
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
