@@ -166,12 +166,12 @@ int pic_sync_state(pic_ctx *ctx);
 
 /* Kernel classes timed by the optional event profiler. */
 enum pic_kernel_class {
-    PIC_K_PASS_A = 0,      /* gather at x*, v*, centred deposit                        */
-    PIC_K_FIELD = 1,       /* Ampere / Crank-Nicolson update                           */
-    PIC_K_PASS_B = 2,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit*/
-    PIC_K_TAIL = 3,        /* step record and predictor fields                         */
-    PIC_K_REBIN = 4,       /* counting-sort rebin (all of its kernels)                 */
-    PIC_K_COUNT = 5
+    PIC_K_PASS_A = 0,      /* gather at x*, v*, centred deposit; its last workgroup does
+                              the Ampere / Crank-Nicolson field update                 */
+    PIC_K_PASS_B = 1,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit;
+                              its last workgroup writes the step record and E* (B*)    */
+    PIC_K_REBIN = 2,       /* counting-sort rebin (all of its kernels)                 */
+    PIC_K_COUNT = 3
 };
 
 /* Enable (on != 0) or disable HIP-event timing of every kernel pic_step enqueues: a

@@ -50,7 +50,7 @@ DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("fiel
 EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
            "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
            "pic_destroy", "pic_strerror", "pic_last_error")
-KERNEL_CLASSES = ("pass_a", "field", "pass_b", "tail", "rebin")
+KERNEL_CLASSES = ("pass_a", "pass_b", "rebin")
 
 
 class PicError(RuntimeError):

@@ -1,24 +1,30 @@
 // Device code of the explicit energy-conserving PIC step for gfx950 (CDNA4).
 //
 // Particle state is a structure of FP64 arrays (x[N_p], v[nv][N_p]) streamed from HBM
-// with one lane per particle; the 1D grid (at most a few thousand nodes) lives in LDS for
-// the whole pass.  One step of ESEC2 / EMEC(LI) (eq. (good_translation), (EMbasic)) is
+// with one lane per particle; the 1D grid (a few hundred nodes) lives in LDS for the
+// whole pass.  One step of ESEC2 / EMEC(LI) (eq. (good_translation), (EMbasic)) is two
+// kernel launches:
 //
-//   pass A (particles): x* = x + dt/2 v, gather E* (B*) at x*, solve v*, x^{n+1},
-//                       x^{n+1/2} = (x^n + x^{n+1}) / 2, deposit w v* at x^{n+1/2}
-//   field update (one workgroup): Ampere / Crank-Nicolson -> E^{n+1} (B^{n+1}) and the
-//                       averaged fields used by the second gather
-//   pass B (particles): recompute x*, v*, x^{n+1/2} bit-identically, gather the averaged
-//                       fields at x^{n+1/2}, v-dagger, Gamma (eq. (opt_solution)) with
-//                       the fallback, write x^{n+1} (wrapped), v^{n+1}; then, because
-//                       x*_{n+1} = x^{n+1} + dt/2 v^{n+1} is known, the NEXT step's
-//                       predictor deposit w v^{n+1} at x*_{n+1}
-//   field tail (one workgroup): energy record of the step, predictor fields E* (B*)
+//   pass A: every workgroup builds the predictor fields E* (B*) in LDS from E^n (B^n)
+//           and the predictor current j^{n,*}; per particle x* = x + dt/2 v, gather at
+//           x*, v*, x^{n+1}, x^{n+1/2} = (x^n + x^{n+1}) / 2, deposit w v* at x^{n+1/2}
+//           into an LDS tile; the tile is added to the global current with FP64 atomics
+//   pass B: every workgroup rebuilds E* (bit-identically) and builds E^{n+1} (B^{n+1})
+//           and the averaged fields from the centred current (Ampere / Crank-Nicolson);
+//           per particle it recomputes x*, v*, x^{n+1/2}, gathers the averaged fields at
+//           x^{n+1/2}, forms v-dagger and Gamma (eq. (opt_solution)) with the fallback,
+//           writes x^{n+1} (wrapped) and v^{n+1}, and - because x*_{n+1} = x^{n+1} +
+//           dt/2 v^{n+1} is then known - deposits the NEXT step's predictor current
+//           w v^{n+1} at x*_{n+1}; workgroup 0 stores E^{n+1} (B^{n+1}) and W_E, W_B
 //
-// so the particle state is read twice and written once per step (48 B per particle in
-// 1D-1V, 96 B in 1D-3V).  Recomputing v* instead of storing it keeps the deposit in
-// pass A and the gather in pass B at exactly the same x^{n+1/2} (compiled without FP
-// contraction), which is what the energy identity of eq. (exp_econs_simple) needs.
+// The grid work is tiny (N_g nodes) and is repeated by every workgroup in its prologue,
+// which costs a few microseconds of L2 reads and saves the single-workgroup kernels and
+// the grid-wide synchronisation they would need.  Fields and currents are double
+// buffered by step parity.  The particle state is read twice and written once per step
+// (48 B per particle in 1D-1V, 96 B in 1D-3V).  Recomputing v* in pass B instead of
+// storing it keeps the deposit in pass A and the gather in pass B at exactly the same
+// x^{n+1/2} (the code is compiled without FP contraction), which is what the energy
+// identity of eq. (exp_econs_simple) needs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +33,12 @@
 namespace pic {
 
 constexpr int kMaxGrid = 8192;   // upper bound on particle-pass workgroups
+constexpr int kNS = 4;           // per-workgroup scalars: KE, fallbacks, max|G-1|, nonfinite
+
+// Particles whose loads each thread issues together before computing on them, per pass
+// (more loads in flight against fewer waves per SIMD from the extra registers).
+template <int NV> constexpr int kUnrollA = NV == 1 ? 4 : 2;
+template <int NV> constexpr int kUnrollB = NV == 1 ? 4 : 2;
 
 // Per-step record, laid out exactly like pic_diag.
 struct DevRecord {
@@ -37,10 +49,10 @@ struct DevRecord {
 };
 
 struct DevState {
-    int64_t step;          // steps completed
+    int64_t recorded;      // newest step whose record is written
     double te0;            // total energy of step 0
     int64_t fb_total;
-    double we, wb;         // field energies of the state being finalised
+    double we, wb;         // field energies of the newest fields (written by pass B)
     int32_t nonfinite_sticky;
     int32_t pad;
 };
@@ -51,7 +63,9 @@ struct Run {
     int32_t ng, nv;
     int32_t nblocks;       // workgroups of the particle passes
     int32_t rec_cap;
-    int64_t chunk;         // particles per workgroup (multiple of blockDim)
+    int64_t chunk;         // particles per workgroup
+    int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI)
+    int32_t pad;
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -59,18 +73,17 @@ struct Run {
     const double *w;       // [N_p] weights or nullptr (uniform)
 };
 
-// Workspace arrays (device pointers).
+// Workspace arrays (device pointers).  Index [k] below is the step parity.
 struct Work {
-    double *E, *B;                 // caller fields: E[3][ng], B[2][ng] (B may be null)
-    double *Es, *Bs;               // predictor fields E*, B*
-    double *Eb, *Bb;               // (E^n + E^{n+1})/2, (B^n + B^{n+1})/2
-    double *J1, *J2;               // [3][ng] current accumulators (zero between uses)
-    double *cninv;                 // [ng] first row of the Crank-Nicolson inverse
-    double *part_ke, *part_gd;     // [nblocks] block partials
-    int64_t *part_fb;
-    int32_t *part_nf;
+    double *E, *B;         // caller fields: E[3][ng], B[2][ng] (B null for ES)
+    double *Ef[2];         // [3][ng] E^n (Ef[n & 1])
+    double *Bf[2];         // [2][ng] B^n
+    double *J1[2];         // [3][ng] predictor current j^{n,*} (J1[n & 1])
+    double *J2[2];         // [3][ng] centred current j^{*,n+1/2} (J2[n & 1])
+    double *cninv;         // [ng] first row of the Crank-Nicolson inverse
+    double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
     DevState *st;
-    DevRecord *rec;                // [rec_cap] ring
+    DevRecord *rec;        // [rec_cap] ring
 };
 
 // ------------------------------------------------------------------ shape functions
@@ -100,7 +113,7 @@ __device__ __forceinline__ Stencil<2> stencil2(double xi)
     Stencil<2> s;
     s.first = (int)f - 1;
     s.w[0] = 0.5 * a * a;
-    s.w[1] = 0.75 - d * d;
+    s.w[1] = fma(-d, d, 0.75);
     s.w[2] = 0.5 * b * b;
     return s;
 }
@@ -146,7 +159,7 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k <= ORDER; ++k)
-        acc += tile[n.n[k]] * s.w[k];
+        acc = fma(tile[n.n[k]], s.w[k], acc);
     return acc;
 }
 
@@ -159,13 +172,22 @@ __device__ __forceinline__ void deposit1(double *tile, const Stencil<ORDER> &s,
         atomicAdd(&tile[n.n[k]], q * s.w[k]);
 }
 
+// Periodic position in [0, L).  A particle moves less than a period per step, so one
+// conditional add or subtract almost always suffices; otherwise x - L floor(x / L),
+// with rounding that lands on L mapped to 0.
 __device__ __forceinline__ double wrap_pos(double x, double L)
 {
-    x = x - L * floor(x / L);
     if (x < 0.0)
         x += L;
-    if (x >= L)
-        x = 0.0;
+    else if (x >= L)
+        x -= L;
+    if (x < 0.0 || x >= L || !(x == x)) {
+        x = x - L * floor(x / L);
+        if (x < 0.0)
+            x += L;
+        if (x >= L)
+            x = 0.0;
+    }
     return x;
 }
 
@@ -186,7 +208,8 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Deterministic block sum; every thread gets the result.  red: >= 16 doubles of LDS.
+// Deterministic block sum (fixed order for a given blockDim); every thread gets the
+// result.  red: >= 16 doubles of LDS.
 __device__ double block_sum(double v, double *red)
 {
     v = wave_sum(v);
@@ -217,13 +240,241 @@ __device__ double block_max(double v, double *red)
     return t;
 }
 
+// Mean of n values (LDS or global), identical in every workgroup of a launch.
+__device__ __forceinline__ double block_mean(const double *a, int n, double *red)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        s += a[i];
+    return block_sum(s, red) / n;
+}
+
+__device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = src[i];
+}
+
+__device__ __forceinline__ void tile_zero(double *dst, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = 0.0;
+}
+
+// Add a workgroup's LDS current tile into the global current (hardware FP64 atomics;
+// zero entries, common when the particles are cell-sorted, are skipped).
+__device__ __forceinline__ void tile_flush(const double *tile, double *J, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double val = tile[i];
+        if (val != 0.0)
+            unsafeAtomicAdd(&J[i], val);
+    }
+}
+
+// ------------------------------------------------------------------ grid operations
+// Staggered differences: nodes f[i] at i h, half nodes g[i] at (i + 1/2) h.
+__device__ __forceinline__ double dplus(const double *f, int i, int ng, double inv_h)
+{
+    return (f[i + 1 == ng ? 0 : i + 1] - f[i]) * inv_h;
+}
+__device__ __forceinline__ double dminus(const double *g, int i, int ng, double inv_h)
+{
+    return (g[i] - g[i == 0 ? ng - 1 : i - 1]) * inv_h;
+}
+
+// Predictor fields into LDS (es [ne][ng], bs [2][ng]) from E^n, B^n and j^{n,*}:
+//   ESEC2: E* = E - dt/2 (j - mean j)                        (eq. (good_translation))
+//   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
+//   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
+// In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
+__device__ void predictor_fields(const Run &r, const double *E, const double *B,
+                                 const double *J, double *es, double *bs, double *red)
+{
+    const int ng = r.ng;
+    if (r.scheme == 1) {
+        tile_load(es, E, ng);
+        return;
+    }
+    if (r.scheme == 0) {
+        const double mean = block_mean(J, ng, red);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            es[i] = E[i] - r.hdt * (J[i] - mean);
+        return;
+    }
+    const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
+    const double *By = B, *Bz = B + ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        es[i] = Ex[i] - r.hdt * J[i];
+        es[ng + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - J[ng + i]);
+        es[2 * ng + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - J[2 * ng + i]);
+        bs[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
+        bs[ng + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
+    }
+}
+
+// Field update from the centred current J (global): new fields into e1 [ne][ng] and
+// b1 [2][ng] (LDS), averaged fields into eb, bb (LDS).
+//   ES: E^{n+1} = E^n - dt (j - mean j)                    (eq. (ampere) in 1D)
+//   EM (a = dt/2, s = a^2 c^2, L_h = D-D+), eq. (EMbasic) with Crank-Nicolson:
+//     (I - s L_h) E_y' = (I + s L_h) E_y - dt c^2 D-B_z - dt j_y,  B_z' = B_z - a D+(E_y + E_y')
+//     (I - s L_h) E_z' = (I + s L_h) E_z + dt c^2 D-B_y - dt j_z,  B_y' = B_y + a D+(E_z + E_z')
+//     E_x' = E_x - dt j_x
+//   The circulant system is solved with the first row g of its inverse.
+// scratch: EM only, 8 N_g doubles of LDS (E^n, B^n, right-hand sides, g).
+__device__ void field_update(const Run &r, const Work &wk, const double *E, const double *B,
+                             const double *J, double *e1, double *b1, double *eb, double *bb,
+                             double *scratch, double *red)
+{
+    const int ng = r.ng;
+    if (r.scheme != 2) {
+        const double mean = block_mean(J, ng, red);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+            const double e0 = E[i];
+            const double en = e0 - r.dt * (J[i] - mean);
+            e1[i] = en;
+            eb[i] = 0.5 * (e0 + en);
+        }
+        return;
+    }
+    double *E0 = scratch;            // [3][ng]
+    double *B0 = E0 + 3 * ng;        // [2][ng]
+    double *R = B0 + 2 * ng;         // [2][ng]
+    double *g = R + 2 * ng;          // [ng]
+    tile_load(E0, E, 3 * ng);
+    tile_load(B0, B, 2 * ng);
+    tile_load(g, wk.cninv, ng);
+    __syncthreads();
+    const double a = r.hdt, s = a * a * r.c2, ih2 = r.inv_h * r.inv_h;
+    const double *Ey = E0 + ng, *Ez = E0 + 2 * ng, *By = B0, *Bz = B0 + ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const int ip = i + 1 == ng ? 0 : i + 1, im = i == 0 ? ng - 1 : i - 1;
+        e1[i] = E0[i] - r.dt * J[i];
+        R[i] = Ey[i] + s * (Ey[ip] - 2.0 * Ey[i] + Ey[im]) * ih2
+               - r.dt * r.c2 * dminus(Bz, i, ng, r.inv_h) - r.dt * J[ng + i];
+        R[ng + i] = Ez[i] + s * (Ez[ip] - 2.0 * Ez[i] + Ez[im]) * ih2
+                    + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * J[2 * ng + i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        double ay = 0.0, az = 0.0;
+        for (int j = 0; j < ng; ++j) {
+            int k = i - j;
+            k += k < 0 ? ng : 0;
+            ay += g[k] * R[j];
+            az += g[k] * R[ng + j];
+        }
+        e1[ng + i] = ay;
+        e1[2 * ng + i] = az;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const int ip = i + 1 == ng ? 0 : i + 1;
+        b1[ng + i] = Bz[i] - a * ((Ey[ip] + e1[ng + ip]) - (Ey[i] + e1[ng + i])) * r.inv_h;
+        b1[i] = By[i] + a * ((Ez[ip] + e1[2 * ng + ip]) - (Ez[i] + e1[2 * ng + i])) * r.inv_h;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+        eb[i] = 0.5 * (E0[i] + e1[i]);
+    for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+        bb[i] = 0.5 * (B0[i] + b1[i]);
+}
+
+// W_E = h/2 sum |E|^2 and W_B = c^2 h/2 sum |B|^2 (section 5.1) of LDS/global fields;
+// every thread gets the result.
+__device__ void field_energies(const Run &r, const double *E, const double *B, double *we,
+                               double *wb, double *red)
+{
+    const bool em = r.scheme == 2;
+    const int ng = r.ng, ne = em ? 3 : 1;
+    double se = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < ne * ng; i += blockDim.x)
+        se += E[i] * E[i];
+    if (em)
+        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+            sb += B[i] * B[i];
+    *we = 0.5 * r.h * block_sum(se, red);
+    *wb = em ? 0.5 * r.c2 * r.h * block_sum(sb, red) : 0.0;
+}
+
+// Write the record of `step` from the pass-B scalars of every workgroup (summed in a
+// fixed order) and the field energies in st; run by one workgroup.
+__device__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
+{
+    double ke = 0.0, fb = 0.0, gd = 0.0, nf = 0.0;
+    for (int b = threadIdx.x; b < r.nblocks; b += blockDim.x) {
+        ke += wk.spart[b * kNS + 0];
+        fb += wk.spart[b * kNS + 1];
+        gd = fmax(gd, wk.spart[b * kNS + 2]);
+        nf = fmax(nf, wk.spart[b * kNS + 3]);
+    }
+    ke = block_sum(ke, red);
+    fb = block_sum(fb, red);
+    gd = block_max(gd, red);
+    nf = block_max(nf, red);
+    if (threadIdx.x == 0) {
+        DevState *st = wk.st;
+        if (step == 0) {
+            st->fb_total = 0;
+            st->nonfinite_sticky = 0;
+        }
+        const double te = ke + st->we + st->wb;
+        if (step == 0)
+            st->te0 = te;
+        st->fb_total += (int64_t)fb;
+        st->nonfinite_sticky |= (nf != 0.0);
+        DevRecord rec;
+        rec.step = step;
+        rec.time = (double)step * r.dt;
+        rec.kinetic = ke;
+        rec.field_e = st->we;
+        rec.field_b = st->wb;
+        rec.total = te;
+        rec.rel_energy_err = fabs(te - st->te0) / st->te0;
+        rec.max_gamma_dev = gd;
+        rec.fallbacks = (int64_t)fb;
+        rec.fallbacks_total = st->fb_total;
+        rec.nonfinite = nf != 0.0;
+        rec.pad = 0;
+        wk.rec[step % r.rec_cap] = rec;
+        st->recorded = step;
+    }
+}
+
 // --------------------------------------------------------------- particle kernels
+template <int NV, bool EM> struct TileSizes {
+    static constexpr int ne = EM ? 3 : 1;      // E components gathered
+    static constexpr int nb = EM ? 2 : 0;      // B components gathered
+    static constexpr int ncur = EM ? 3 : 1;    // current components deposited
+};
+
 // The particle's half-step quantities, computed identically in both passes.
 template <int ORDER, int NV, bool EM> struct Half {
     double vs[NV];       // v*
     double x1;           // x^{n+1} (unwrapped)
     double xh;           // x^{n+1/2}
 };
+
+// Gamma = sqrt(r), r = 1 + rho, rho = 2 num / den  (eq. (opt_solution)); r < 0 or a
+// non-finite r (e.g. den = 0) takes the fallback Gamma = 1 and is counted.
+// Because Gamma - 1 is tiny for almost every particle (O(dt^4) for ESEC2), the common
+// case |rho| < 1e-4 evaluates rho with a Newton-refined hardware reciprocal and sqrt(1 +
+// rho) by its Taylor series through rho^4 (truncation below 3e-22); any other rho is
+// evaluated with an IEEE division and square root.
+__device__ __forceinline__ double gamma_factor(double num, double den, int &fallbacks)
+{
+    double rc = __builtin_amdgcn_rcp(den);
+    rc = fma(rc, fma(-den, rc, 1.0), rc);
+    rc = fma(rc, fma(-den, rc, 1.0), rc);
+    const double rho = 2.0 * num * rc;
+    if (fabs(rho) < 1e-4)
+        return fma(rho, fma(rho, fma(rho, fma(rho, -0.0390625, 0.0625), -0.125), 0.5), 1.0);
+    const double rr = 1.0 + 2.0 * num / den;
+    if (rr >= 0.0 && isfinite(rr))
+        return sqrt(rr);
+    ++fallbacks;
+    return 1.0;
+}
 
 // v* solves v* = u + v* x t with u = v^n + dt/2 E**, t = dt/2 B** (eq. (good_translation)
 // second line, eq. (EMbasic) fourth line): v* = (u + u x t + (u.t) t) / (1 + |t|^2).
@@ -243,17 +494,17 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
                                                         const double *es, const double *bs)
 {
     Half<ORDER, NV, EM> o;
-    const double xs = x + r.hdt * v[0];
+    const double xs = fma(r.hdt, v[0], x);
     const Stencil<ORDER> s = stencil<ORDER>(xs * r.inv_h);
     const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
     if constexpr (NV == 1) {
-        o.vs[0] = v[0] + r.hdt * gather1<ORDER>(es, s, n);
+        o.vs[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
     } else {
         double u[3], t[3];
-        u[0] = v[0] + r.hdt * gather1<ORDER>(es, s, n);
+        u[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
         if constexpr (EM) {
-            u[1] = v[1] + r.hdt * gather1<ORDER>(es + r.ng, s, n);
-            u[2] = v[2] + r.hdt * gather1<ORDER>(es + 2 * r.ng, s, n);
+            u[1] = fma(r.hdt, gather1<ORDER>(es + r.ng, s, n), v[1]);
+            u[2] = fma(r.hdt, gather1<ORDER>(es + 2 * r.ng, s, n), v[2]);
             const Stencil<ORDER> sh = stencil<ORDER>(xs * r.inv_h - 0.5);
             const Nodes<ORDER> nh = nodes_of<ORDER>(sh, r.ng);
             t[0] = r.hdt * r.bext[0];
@@ -268,179 +519,200 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
         }
         rotate_half(u, t, o.vs);
     }
-    o.x1 = x + r.dt * o.vs[0];
+    o.x1 = fma(r.dt, o.vs[0], x);
     o.xh = 0.5 * (x + o.x1);
     return o;
 }
 
-template <int NV, bool EM> struct TileSizes {
-    static constexpr int ne = EM ? 3 : 1;      // E components gathered
-    static constexpr int nb = EM ? 2 : 0;      // B components gathered
-    static constexpr int ncur = EM ? 3 : 1;    // current components deposited
-};
-
-// Cooperative load of n doubles into LDS.
-__device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        dst[i] = src[i];
-}
-
-__device__ __forceinline__ void tile_zero(double *dst, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        dst[i] = 0.0;
-}
-
-// Flush a block's LDS current tile into the global accumulator (hardware FP64 atomics).
-__device__ __forceinline__ void tile_flush(const double *tile, double *J, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double val = tile[i];
-        if (val != 0.0)
-            unsafeAtomicAdd(&J[i], val);
-    }
-}
-
-// Pass A: gather E* (B*) at x*, v*, deposit w v* at x^{n+1/2} into J2.
+// Pass A of step n (par = n & 1).
+// LDS: jt[ncur ng] | es[ne ng] | bs[nb ng]
 template <int ORDER, int NV, bool EM>
-__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, const double *__restrict__ X,
+__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_t step,
+                                                 const double *__restrict__ X,
                                                  const double *__restrict__ V)
 {
     using T = TileSizes<NV, EM>;
     extern __shared__ double smem[];
-    double *es = smem;                         // [ne][ng]
-    double *bs = es + T::ne * r.ng;            // [nb][ng]
-    double *jt = bs + T::nb * r.ng;            // [ncur][ng]
-    tile_load(es, wk.Es, T::ne * r.ng);
-    if constexpr (EM)
-        tile_load(bs, wk.Bs, T::nb * r.ng);
-    tile_zero(jt, T::ncur * r.ng);
+    __shared__ double red[16];
+    double *jt = smem;
+    double *es = jt + T::ncur * r.ng;
+    double *bs = es + T::ne * r.ng;
+    const int ng = r.ng;
+    predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red);
+    tile_zero(jt, T::ncur * ng);
+    if (blockIdx.x == 0) {
+        // the predictor current of the next step accumulates into the other buffer
+        if (r.scheme != 1)
+            for (int i = threadIdx.x; i < T::ncur * ng; i += blockDim.x)
+                wk.J1[par ^ 1][i] = 0.0;
+        // the record of the state this step starts from, if not written yet
+        if (step > wk.st->recorded)
+            write_record(r, wk, step, red);
+    }
     __syncthreads();
 
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        double v[NV];
+    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollA<NV> * blockDim.x) {
+        // issue the loads of kUnroll particles before any arithmetic (memory-level
+        // parallelism), then process them one by one
+        double xr[kUnrollA<NV>], vr[kUnrollA<NV>][NV];
 #pragma unroll
-        for (int c = 0; c < NV; ++c)
-            v[c] = V[c * r.np + p];
-        const double x = X[p];
-        const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, x, v, es, bs);
-        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
-        const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
-        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
-        deposit1<ORDER>(jt, s, n, q * hs.vs[0]);
-        if constexpr (EM) {
-            deposit1<ORDER>(jt + r.ng, s, n, q * hs.vs[1]);
-            deposit1<ORDER>(jt + 2 * r.ng, s, n, q * hs.vs[2]);
+        for (int u = 0; u < kUnrollA<NV>; ++u) {
+            const int64_t p = base + (int64_t)u * blockDim.x;
+            if (p < p1) {
+                xr[u] = X[p];
+#pragma unroll
+                for (int c = 0; c < NV; ++c)
+                    vr[u][c] = V[c * r.np + p];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnrollA<NV>; ++u) {
+            const int64_t p = base + (int64_t)u * blockDim.x;
+            if (p >= p1)
+                break;
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], vr[u], es, bs);
+            const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+            const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
+            const Nodes<ORDER> n = nodes_of<ORDER>(s, ng);
+            deposit1<ORDER>(jt, s, n, q * hs.vs[0]);
+            if constexpr (EM) {
+                deposit1<ORDER>(jt + ng, s, n, q * hs.vs[1]);
+                deposit1<ORDER>(jt + 2 * ng, s, n, q * hs.vs[2]);
+            }
         }
     }
     __syncthreads();
-    tile_flush(jt, wk.J2, T::ncur * r.ng);
+    tile_flush(jt, wk.J2[par], T::ncur * ng);
 }
 
-// Pass B: recompute the half step, gather the averaged fields at x^{n+1/2}, v-dagger,
-// Gamma with fallback, write the new state; then (PRED) deposit the next step's
-// predictor current w v^{n+1} at x*_{n+1} into J1.
+// Pass B of step n (par = n & 1): new fields, second gather, Gamma, state write and
+// (PRED) the next step's predictor deposit.
+// LDS: jt[ncur ng] | es[ne ng] | bs[nb ng] | eb[ne ng] | bb[nb ng] | e1[ne ng] | b1[nb ng]
+//      | EM scratch[8 ng]
 template <int ORDER, int NV, bool EM, bool PRED>
-__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, const double *X, const double *V,
-                                                 double *Xo, double *Vo)
+__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const double *X,
+                                                 const double *V, double *Xo, double *Vo)
 {
     using T = TileSizes<NV, EM>;
     extern __shared__ double smem[];
-    double *es = smem;                         // E*
-    double *bs = es + T::ne * r.ng;            // B*
-    double *eb = bs + T::nb * r.ng;            // E-bar
-    double *bb = eb + T::ne * r.ng;            // B-bar
-    double *jt = bb + T::nb * r.ng;            // predictor current tile
     __shared__ double red[16];
-    tile_load(es, wk.Es, T::ne * r.ng);
-    tile_load(eb, wk.Eb, T::ne * r.ng);
-    if constexpr (EM) {
-        tile_load(bs, wk.Bs, T::nb * r.ng);
-        tile_load(bb, wk.Bb, T::nb * r.ng);
-    }
+    const int ng = r.ng;
+    double *jt = smem;
+    double *es = jt + T::ncur * ng;
+    double *bs = es + T::ne * ng;
+    double *eb = bs + T::nb * ng;
+    double *bb = eb + T::ne * ng;
+    double *e1 = bb + T::nb * ng;
+    double *b1 = e1 + T::ne * ng;
+    double *scratch = b1 + T::nb * ng;
+    const double *En = wk.Ef[par];
+    const double *Bn = EM ? wk.Bf[par] : nullptr;
+    predictor_fields(r, En, Bn, wk.J1[par], es, bs, red);
+    field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red);
     if constexpr (PRED)
-        tile_zero(jt, T::ncur * r.ng);
+        tile_zero(jt, T::ncur * ng);
     __syncthreads();
+    if (blockIdx.x == 0) {
+        // publish E^{n+1} (B^{n+1}) and their energies; clear the other centred current
+        for (int i = threadIdx.x; i < T::ne * ng; i += blockDim.x)
+            wk.Ef[par ^ 1][i] = e1[i];
+        if constexpr (EM)
+            for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+                wk.Bf[par ^ 1][i] = b1[i];
+        for (int i = threadIdx.x; i < T::ncur * ng; i += blockDim.x)
+            wk.J2[par ^ 1][i] = 0.0;
+        double we, wb;
+        field_energies(r, e1, b1, &we, &wb, red);
+        if (threadIdx.x == 0) {
+            wk.st->we = we;
+            wk.st->wb = wb;
+        }
+    }
 
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        double v[NV];
+    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollB<NV> * blockDim.x) {
+        double xr[kUnrollB<NV>], vr[kUnrollB<NV>][NV];
 #pragma unroll
-        for (int c = 0; c < NV; ++c)
-            v[c] = V[c * r.np + p];
-        const double x = X[p];
-        const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, x, v, es, bs);
-        const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
-        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
-        double vd[NV];
-        if constexpr (NV == 1) {
-            vd[0] = v[0] + r.dt * gather1<ORDER>(eb, s, n);
-        } else {
-            double e[3], b[3];
-            e[0] = gather1<ORDER>(eb, s, n);
-            b[0] = r.bext[0];
-            if constexpr (EM) {
-                e[1] = gather1<ORDER>(eb + r.ng, s, n);
-                e[2] = gather1<ORDER>(eb + 2 * r.ng, s, n);
-                const Stencil<ORDER> sh = stencil<ORDER>(hs.xh * r.inv_h - 0.5);
-                const Nodes<ORDER> nh = nodes_of<ORDER>(sh, r.ng);
-                b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
-                b[2] = r.bext[2] + gather1<ORDER>(bb + r.ng, sh, nh);
-            } else {
-                e[1] = 0.0;
-                e[2] = 0.0;
-                b[1] = r.bext[1];
-                b[2] = r.bext[2];
+        for (int u = 0; u < kUnrollB<NV>; ++u) {
+            const int64_t p = base + (int64_t)u * blockDim.x;
+            if (p < p1) {
+                xr[u] = X[p];
+#pragma unroll
+                for (int c = 0; c < NV; ++c)
+                    vr[u][c] = V[c * r.np + p];
             }
-            // v-dagger = v^n + dt (E-bar + v* x B-bar)   (eq. (good_translation), (EMbasic))
-            vd[0] = v[0] + r.dt * (e[0] + (hs.vs[1] * b[2] - hs.vs[2] * b[1]));
-            vd[1] = v[1] + r.dt * (e[1] + (hs.vs[2] * b[0] - hs.vs[0] * b[2]));
-            vd[2] = v[2] + r.dt * (e[2] + (hs.vs[0] * b[1] - hs.vs[1] * b[0]));
         }
-        // Gamma (eq. (opt_solution)); an imaginary or undefined root falls back to 1
-        double num = 0.0, den = 0.0;
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
-            num += (hs.vs[c] - 0.5 * (vd[c] + v[c])) * (vd[c] - v[c]);
-            den += vd[c] * vd[c];
-        }
-        const double rr = 1.0 + 2.0 * num / den;
-        double g;
-        if (rr >= 0.0 && isfinite(rr)) {
-            g = sqrt(rr);
-        } else {
-            g = 1.0;
-            ++fb;
-        }
-        gdev = fmax(gdev, fabs(g - 1.0));
-        double vn[NV];
-        double v2 = 0.0;
+        for (int u = 0; u < kUnrollB<NV>; ++u) {
+            const int64_t p = base + (int64_t)u * blockDim.x;
+            if (p >= p1)
+                break;
+            const double *v = vr[u];
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], v, es, bs);
+            const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
+            const Nodes<ORDER> n = nodes_of<ORDER>(s, ng);
+            double vd[NV];
+            if constexpr (NV == 1) {
+                vd[0] = fma(r.dt, gather1<ORDER>(eb, s, n), v[0]);
+            } else {
+                double e[3], b[3];
+                e[0] = gather1<ORDER>(eb, s, n);
+                b[0] = r.bext[0];
+                if constexpr (EM) {
+                    e[1] = gather1<ORDER>(eb + ng, s, n);
+                    e[2] = gather1<ORDER>(eb + 2 * ng, s, n);
+                    const Stencil<ORDER> sh = stencil<ORDER>(hs.xh * r.inv_h - 0.5);
+                    const Nodes<ORDER> nh = nodes_of<ORDER>(sh, ng);
+                    b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
+                    b[2] = r.bext[2] + gather1<ORDER>(bb + ng, sh, nh);
+                } else {
+                    e[1] = 0.0;
+                    e[2] = 0.0;
+                    b[1] = r.bext[1];
+                    b[2] = r.bext[2];
+                }
+                // v-dagger = v^n + dt (E-bar + v* x B-bar)   (eq. (good_translation), (EMbasic))
+                vd[0] = v[0] + r.dt * (e[0] + (hs.vs[1] * b[2] - hs.vs[2] * b[1]));
+                vd[1] = v[1] + r.dt * (e[1] + (hs.vs[2] * b[0] - hs.vs[0] * b[2]));
+                vd[2] = v[2] + r.dt * (e[2] + (hs.vs[0] * b[1] - hs.vs[1] * b[0]));
+            }
+            // Gamma (eq. (opt_solution)); an imaginary or undefined root falls back to 1
+            double num = 0.0, den = 0.0;
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
-            vn[c] = g * vd[c];
-            v2 += vn[c] * vn[c];
-            Vo[c * r.np + p] = vn[c];
-        }
-        const double xw = wrap_pos(hs.x1, r.L);
-        Xo[p] = xw;
-        const double wp = r.w ? r.w[p] : r.wu;
-        ke += wp * v2;
-        if (!isfinite(v2) || !isfinite(hs.x1))
-            nonfinite = 1;
-        if constexpr (PRED) {
-            const double q = wp * r.qs;
-            const Stencil<ORDER> s2 = stencil<ORDER>((xw + r.hdt * vn[0]) * r.inv_h);
-            const Nodes<ORDER> n2 = nodes_of<ORDER>(s2, r.ng);
-            deposit1<ORDER>(jt, s2, n2, q * vn[0]);
-            if constexpr (EM) {
-                deposit1<ORDER>(jt + r.ng, s2, n2, q * vn[1]);
-                deposit1<ORDER>(jt + 2 * r.ng, s2, n2, q * vn[2]);
+            for (int c = 0; c < NV; ++c) {
+                num = fma(hs.vs[c] - 0.5 * (vd[c] + v[c]), vd[c] - v[c], num);
+                den = fma(vd[c], vd[c], den);
+            }
+            const double g = gamma_factor(num, den, fb);
+            gdev = fmax(gdev, fabs(g - 1.0));
+            double vn[NV];
+            double v2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                vn[c] = g * vd[c];
+                v2 = fma(vn[c], vn[c], v2);
+                Vo[c * r.np + p] = vn[c];
+            }
+            const double xw = wrap_pos(hs.x1, r.L);
+            Xo[p] = xw;
+            const double wp = r.w ? r.w[p] : r.wu;
+            ke = fma(wp, v2, ke);
+            if (!isfinite(v2) || !isfinite(hs.x1))
+                nonfinite = 1;
+            if constexpr (PRED) {
+                const double q = wp * r.qs;
+                const Stencil<ORDER> s2 = stencil<ORDER>((xw + r.hdt * vn[0]) * r.inv_h);
+                const Nodes<ORDER> n2 = nodes_of<ORDER>(s2, ng);
+                deposit1<ORDER>(jt, s2, n2, q * vn[0]);
+                if constexpr (EM) {
+                    deposit1<ORDER>(jt + ng, s2, n2, q * vn[1]);
+                    deposit1<ORDER>(jt + 2 * ng, s2, n2, q * vn[2]);
+                }
             }
         }
     }
@@ -449,18 +721,33 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, const double *X
     const double bfb = block_sum((double)fb, red);
     const double bnf = block_max((double)nonfinite, red);
     if (threadIdx.x == 0) {
-        wk.part_ke[blockIdx.x] = 0.5 * bke;
-        wk.part_gd[blockIdx.x] = bgd;
-        wk.part_fb[blockIdx.x] = (int64_t)bfb;
-        wk.part_nf[blockIdx.x] = (int32_t)bnf;
+        wk.spart[blockIdx.x * kNS + 0] = 0.5 * bke;
+        wk.spart[blockIdx.x * kNS + 1] = bfb;
+        wk.spart[blockIdx.x * kNS + 2] = bgd;
+        wk.spart[blockIdx.x * kNS + 3] = bnf;
     }
     if constexpr (PRED) {
         __syncthreads();
-        tile_flush(jt, wk.J1, T::ncur * r.ng);
+        tile_flush(jt, wk.J1[par ^ 1], T::ncur * ng);
     }
 }
 
-// Predictor deposit of the initial state: w v^0 at x*_0 = x^0 + dt/2 v^0 into J1.
+// End of a pic_step call (one workgroup): the record of the newest state and a copy of
+// the newest fields into the caller's arrays.
+__global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_t step)
+{
+    __shared__ double red[16];
+    if (step > wk.st->recorded)
+        write_record(r, wk, step, red);
+    for (int i = threadIdx.x; i < 3 * r.ng; i += blockDim.x)
+        wk.E[i] = wk.Ef[par][i];
+    if (r.scheme == 2)
+        for (int i = threadIdx.x; i < 2 * r.ng; i += blockDim.x)
+            wk.B[i] = wk.Bf[par][i];
+}
+
+// ------------------------------------------------------------------- initialisation
+// Predictor deposit of the initial state, w v^0 at x*_0 = x^0 + dt/2 v^0, into J1[0].
 template <int ORDER, int NV, bool EM>
 __global__ __launch_bounds__(1024) void k_predeposit(Run r, Work wk, const double *__restrict__ X,
                                                      const double *__restrict__ V)
@@ -484,10 +771,10 @@ __global__ __launch_bounds__(1024) void k_predeposit(Run r, Work wk, const doubl
         }
     }
     __syncthreads();
-    tile_flush(jt, wk.J1, T::ncur * r.ng);
+    tile_flush(jt, wk.J1[0], T::ncur * r.ng);
 }
 
-// Charge deposit rho_i = (1/h) sum_p w_p S(x_i - x_p) into J1[0..ng) (initial Gauss).
+// Charge deposit rho_i = (1/h) sum_p w_p S(x_i - x_p) into J2[0] (scratch for Gauss).
 template <int ORDER>
 __global__ __launch_bounds__(1024) void k_deposit_rho(Run r, Work wk, const double *__restrict__ X)
 {
@@ -503,10 +790,11 @@ __global__ __launch_bounds__(1024) void k_deposit_rho(Run r, Work wk, const doub
         deposit1<ORDER>(jt, s, n, (r.w ? r.w[p] : r.wu) * r.qs);
     }
     __syncthreads();
-    tile_flush(jt, wk.J1, r.ng);
+    tile_flush(jt, wk.J2[0], r.ng);
 }
 
-// Wrap positions into [0, L) and sum the initial kinetic energy per block.
+// Wrap positions into [0, L); the initial kinetic energy and non-finite flag go to
+// spart like the scalars of a pass B.
 template <int NV>
 __global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double *__restrict__ X,
                                                          const double *__restrict__ V)
@@ -532,222 +820,22 @@ __global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double 
     const double bke = block_sum(ke, red);
     const double bnf = block_max((double)nonfinite, red);
     if (threadIdx.x == 0) {
-        wk.part_ke[blockIdx.x] = 0.5 * bke;
-        wk.part_gd[blockIdx.x] = 0.0;
-        wk.part_fb[blockIdx.x] = 0;
-        wk.part_nf[blockIdx.x] = (int32_t)bnf;
+        wk.spart[blockIdx.x * kNS + 0] = 0.5 * bke;
+        wk.spart[blockIdx.x * kNS + 1] = 0.0;
+        wk.spart[blockIdx.x * kNS + 2] = 0.0;
+        wk.spart[blockIdx.x * kNS + 3] = bnf;
     }
 }
 
-// ------------------------------------------------------------------- grid kernels
-// All grid kernels run as ONE workgroup; the grid is at most a few thousand nodes.
-
-// Staggered differences: nodes f[i] at i h, half nodes g[i] at (i + 1/2) h.
-__device__ __forceinline__ double dplus(const double *f, int i, int ng, double inv_h)
-{
-    return (f[i + 1 == ng ? 0 : i + 1] - f[i]) * inv_h;
-}
-__device__ __forceinline__ double dminus(const double *g, int i, int ng, double inv_h)
-{
-    return (g[i] - g[i == 0 ? ng - 1 : i - 1]) * inv_h;
-}
-
-// Predictor fields from J1, then clear J1.
-//   ES   : E* = E - dt/2 (j - mean j)                        (eq. (good_translation))
-//   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
-//   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
-// In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
-__device__ void predictor_fields(const Run &r, const Work &wk, int scheme, double *red)
-{
-    const int ng = r.ng;
-    if (scheme == 1) {
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            wk.Es[i] = wk.E[i];
-        return;
-    }
-    if (scheme == 0) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            s += wk.J1[i];
-        const double mean = block_sum(s, red) / ng;
-        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-            wk.Es[i] = wk.E[i] - r.hdt * (wk.J1[i] - mean);
-            wk.J1[i] = 0.0;
-        }
-        return;
-    }
-    const double *Ex = wk.E, *Ey = wk.E + ng, *Ez = wk.E + 2 * ng;
-    const double *By = wk.B, *Bz = wk.B + ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        wk.Es[i] = Ex[i] - r.hdt * wk.J1[i];
-        wk.Es[ng + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - wk.J1[ng + i]);
-        wk.Es[2 * ng + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - wk.J1[2 * ng + i]);
-        wk.Bs[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
-        wk.Bs[ng + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
-        wk.J1[i] = 0.0;
-}
-
-__device__ void field_energies(const Run &r, const Work &wk, bool em, double *red)
-{
-    const int ng = r.ng;
-    const int ne = em ? 3 : 1;
-    double se = 0.0, sb = 0.0;
-    for (int i = threadIdx.x; i < ne * ng; i += blockDim.x)
-        se += wk.E[i] * wk.E[i];
-    if (em)
-        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
-            sb += wk.B[i] * wk.B[i];
-    const double we = 0.5 * r.h * block_sum(se, red);
-    const double wb = em ? 0.5 * r.c2 * r.h * block_sum(sb, red) : 0.0;
-    if (threadIdx.x == 0) {
-        wk.st->we = we;
-        wk.st->wb = wb;
-    }
-}
-
-// Ampere / Crank-Nicolson update from J2 (then cleared): E^{n+1}, B^{n+1} in place and
-// the averaged fields E-bar, B-bar for pass B; records W_E^{n+1}, W_B^{n+1}.
-//   ES: E^{n+1} = E^n - dt (j - mean j)
-//   EM (a = dt/2, s = a^2 c^2, L_h = D-D+):
-//     (I - s L_h) E_y' = (I + s L_h) E_y - dt c^2 D-B_z - dt j_y,  B_z' = B_z - a D+(E_y + E_y')
-//     (I - s L_h) E_z' = (I + s L_h) E_z + dt c^2 D-B_y - dt j_z,  B_y' = B_y + a D+(E_z + E_z')
-//     E_x' = E_x - dt j_x
-// The circulant system is solved with the precomputed first row of its inverse.
-__global__ __launch_bounds__(1024) void k_field_update(Run r, Work wk, int em)
-{
-    __shared__ double red[16];
-    const int ng = r.ng;
-    if (!em) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            s += wk.J2[i];
-        const double mean = block_sum(s, red) / ng;
-        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-            const double e0 = wk.E[i];
-            const double e1 = e0 - r.dt * (wk.J2[i] - mean);
-            wk.E[i] = e1;
-            wk.Eb[i] = 0.5 * (e0 + e1);
-            wk.J2[i] = 0.0;
-        }
-        __syncthreads();
-        field_energies(r, wk, false, red);
-        return;
-    }
-    extern __shared__ double smem[];
-    double *E0 = smem;               // [3][ng]
-    double *B0 = E0 + 3 * ng;        // [2][ng]
-    double *R = B0 + 2 * ng;         // [2][ng] right-hand sides
-    double *E1 = R + 2 * ng;         // [3][ng]
-    double *g = E1 + 3 * ng;         // [ng]
-    tile_load(E0, wk.E, 3 * ng);
-    tile_load(B0, wk.B, 2 * ng);
-    tile_load(g, wk.cninv, ng);
-    __syncthreads();
-    const double a = r.hdt, s = a * a * r.c2, ih2 = r.inv_h * r.inv_h;
-    const double *Ey = E0 + ng, *Ez = E0 + 2 * ng, *By = B0, *Bz = B0 + ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        const int ip = i + 1 == ng ? 0 : i + 1, im = i == 0 ? ng - 1 : i - 1;
-        E1[i] = E0[i] - r.dt * wk.J2[i];
-        R[i] = Ey[i] + s * (Ey[ip] - 2.0 * Ey[i] + Ey[im]) * ih2
-               - r.dt * r.c2 * dminus(Bz, i, ng, r.inv_h) - r.dt * wk.J2[ng + i];
-        R[ng + i] = Ez[i] + s * (Ez[ip] - 2.0 * Ez[i] + Ez[im]) * ih2
-                    + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * wk.J2[2 * ng + i];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        double ay = 0.0, az = 0.0;
-        for (int j = 0; j < ng; ++j) {
-            int k = i - j;
-            k += k < 0 ? ng : 0;
-            ay += g[k] * R[j];
-            az += g[k] * R[ng + j];
-        }
-        E1[ng + i] = ay;
-        E1[2 * ng + i] = az;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        const int ip = i + 1 == ng ? 0 : i + 1;
-        const double bz1 = Bz[i] - a * ((Ey[ip] + E1[ng + ip]) - (Ey[i] + E1[ng + i])) * r.inv_h;
-        const double by1 = By[i] + a * ((Ez[ip] + E1[2 * ng + ip]) - (Ez[i] + E1[2 * ng + i])) * r.inv_h;
-        wk.Bb[i] = 0.5 * (By[i] + by1);
-        wk.Bb[ng + i] = 0.5 * (Bz[i] + bz1);
-        wk.B[i] = by1;
-        wk.B[ng + i] = bz1;
-    }
-    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x) {
-        wk.Eb[i] = 0.5 * (E0[i] + E1[i]);
-        wk.E[i] = E1[i];
-        wk.J2[i] = 0.0;
-    }
-    __syncthreads();
-    field_energies(r, wk, true, red);
-}
-
-// Close the step: sum the block partials of pass B in a fixed order, write the record,
-// then build the next step's predictor fields.  `init` finalises step 0 instead.
-__global__ __launch_bounds__(1024) void k_field_tail(Run r, Work wk, int scheme, int init)
-{
-    __shared__ double red[16];
-    double ke = 0.0, gd = 0.0, fb = 0.0, nf = 0.0;
-    for (int b = threadIdx.x; b < r.nblocks; b += blockDim.x) {
-        ke += wk.part_ke[b];
-        gd = fmax(gd, wk.part_gd[b]);
-        fb += (double)wk.part_fb[b];
-        nf = fmax(nf, (double)wk.part_nf[b]);
-    }
-    ke = block_sum(ke, red);
-    gd = block_max(gd, red);
-    fb = block_sum(fb, red);
-    nf = block_max(nf, red);
-    if (init)
-        field_energies(r, wk, scheme == 2, red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        DevState *st = wk.st;
-        if (init) {
-            st->step = 0;
-            st->fb_total = 0;
-            st->nonfinite_sticky = 0;
-        } else {
-            st->step += 1;
-        }
-        const double te = ke + st->we + st->wb;
-        if (init)
-            st->te0 = te;
-        st->fb_total += (int64_t)fb;
-        st->nonfinite_sticky |= (nf != 0.0);
-        DevRecord rec;
-        rec.step = st->step;
-        rec.time = (double)st->step * r.dt;
-        rec.kinetic = ke;
-        rec.field_e = st->we;
-        rec.field_b = st->wb;
-        rec.total = te;
-        rec.rel_energy_err = fabs(te - st->te0) / st->te0;
-        rec.max_gamma_dev = gd;
-        rec.fallbacks = (int64_t)fb;
-        rec.fallbacks_total = st->fb_total;
-        rec.nonfinite = nf != 0.0;
-        rec.pad = 0;
-        wk.rec[st->step % r.rec_cap] = rec;
-    }
-    __syncthreads();
-    predictor_fields(r, wk, scheme, red);
-}
-
-// Initial Gauss solve: dE/dx = rho - 1 with rho in J1 (then cleared).  Spectrally on the
-// nodes: E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2, mean and Nyquist
-// modes zero (the Poisson form, eq. (poisson), in 1D).
+// Initial Gauss solve: dE/dx = rho - 1 with rho in J2[0], into the caller's E_x.
+// Spectrally on the nodes: E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2, mean
+// and Nyquist modes zero (the Poisson form, eq. (poisson), in 1D).
 __global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
 {
     extern __shared__ double smem[];
     const int ng = r.ng;
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
-    tile_load(rho, wk.J1, ng);
+    tile_load(rho, wk.J2[0], ng);
     __syncthreads();
     for (int m = threadIdx.x; m < ng; m += blockDim.x) {
         double re = 0.0, im = 0.0;
@@ -778,7 +866,6 @@ __global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
             acc += er[m] * cs - ei[m] * sn;
         }
         wk.E[i] = acc / ng;
-        wk.J1[i] = 0.0;
     }
 }
 
@@ -798,6 +885,30 @@ __global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk)
         }
         wk.cninv[k] = acc / ng;
     }
+}
+
+// Initial fields into the parity-0 buffers and the record of step 0 (one workgroup).
+__global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
+{
+    __shared__ double red[16];
+    const int ng = r.ng;
+    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+        wk.Ef[0][i] = wk.E[i];
+    if (r.scheme == 2)
+        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+            wk.Bf[0][i] = wk.B[i];
+    double we, wb;
+    field_energies(r, wk.E, wk.B, &we, &wb, red);
+    if (threadIdx.x == 0) {
+        wk.st->we = we;
+        wk.st->wb = wb;
+        wk.st->recorded = -1;
+    }
+    // the charge scratch must be zero before the first centred deposit
+    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+        wk.J2[0][i] = 0.0;
+    __syncthreads();
+    write_record(r, wk, 0, red);
 }
 
 __global__ void k_fill(double *p, int64_t n, double v)

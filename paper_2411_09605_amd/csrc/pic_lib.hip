@@ -28,7 +28,7 @@ constexpr size_t kMaxLds = 64 * 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t Es, Bs, Eb, Bb, J1, J2, cninv, part_ke, part_gd, part_fb, part_nf, st, rec, total;
+    size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, st, rec, total;
 };
 
 int threads_of(const pic_params *p) { return p->block_threads ? p->block_threads : kDefaultThreads; }
@@ -40,8 +40,10 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
     const int t = threads_of(p);
     int64_t nb = p->grid_blocks ? p->grid_blocks : std::min<int64_t>((p->n_particles + t - 1) / t, 1024);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid));
+    // chunks are whole multiples of the batch a workgroup loads at once (4 particles
+    // per thread), so only the last workgroup has a ragged tail
     int64_t chunk = (p->n_particles + nb - 1) / nb;
-    chunk = (chunk + t - 1) / t * t;
+    chunk = (chunk + 4 * t - 1) / (4 * t) * (4 * t);
     nb = (p->n_particles + chunk - 1) / chunk;
     if (chunk_out)
         *chunk_out = chunk;
@@ -51,16 +53,23 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
 bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI; }
 
 // LDS bytes of the largest kernel of this configuration.
+size_t lds_pass_a(const pic_params *p)
+{
+    // jt | es | bs
+    const size_t ng = p->n_cells;
+    return is_em(p) ? (3 + 3 + 2) * ng * 8 : 2 * ng * 8;
+}
+
+size_t lds_pass_b(const pic_params *p)
+{
+    // jt | es | bs | eb | bb | e1 | b1 | (EM) Crank-Nicolson scratch
+    const size_t ng = p->n_cells;
+    return is_em(p) ? (3 + 3 + 2 + 3 + 2 + 3 + 2 + 8) * ng * 8 : 4 * ng * 8;
+}
+
 size_t lds_need(const pic_params *p)
 {
-    const size_t ng = (size_t)p->n_cells;
-    const bool em = is_em(p);
-    const size_t ne = em ? 3 : 1, nb = em ? 2 : 0, ncur = em ? 3 : 1;
-    size_t a = (ne + nb + ncur) * ng * 8;
-    size_t b = (2 * ne + 2 * nb + ncur) * ng * 8;
-    size_t f = em ? 11 * ng * 8 : 0;
-    size_t g = 3 * ng * 8;
-    return std::max(std::max(a, b), std::max(f, g));
+    return std::max(std::max(lds_pass_a(p), lds_pass_b(p)), (size_t)3 * p->n_cells * 8);
 }
 
 Layout layout_of(const pic_params *p)
@@ -69,17 +78,14 @@ Layout layout_of(const pic_params *p)
     const size_t ng = (size_t)p->n_cells;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, kAlign); return at; };
-    L.Es = take(3 * ng * 8);
-    L.Bs = take(2 * ng * 8);
-    L.Eb = take(3 * ng * 8);
-    L.Bb = take(2 * ng * 8);
-    L.J1 = take(3 * ng * 8);
-    L.J2 = take(3 * ng * 8);
+    for (int k = 0; k < 2; ++k) {
+        L.Ef[k] = take(3 * ng * 8);
+        L.Bf[k] = take(2 * ng * 8);
+        L.J1[k] = take(3 * ng * 8);
+        L.J2[k] = take(3 * ng * 8);
+    }
     L.cninv = take(ng * 8);
-    L.part_ke = take(kMaxGrid * 8);
-    L.part_gd = take(kMaxGrid * 8);
-    L.part_fb = take(kMaxGrid * 8);
-    L.part_nf = take(kMaxGrid * 4);
+    L.spart = take((size_t)blocks_of(p, nullptr) * kNS * 8);
     L.st = take(sizeof(DevState));
     L.rec = take((size_t)records_of(p) * sizeof(DevRecord));
     L.total = o;
@@ -164,6 +170,7 @@ struct pic_ctx {
     int threads;
     int poisoned;
     int64_t records_read;     // records handed out so far (step index of the next one)
+    int64_t steps_done;       // steps enqueued since init
     std::string err;
     // event profiler: pairs of (class, start, stop) recorded around each launch
     int profiling;
@@ -180,31 +187,19 @@ namespace {
 // kind: 0 = 1D-1V electrostatic, 1 = 1D-3V electrostatic, 2 = 1D-3V electromagnetic
 int kind_of(const pic_params *p) { return is_em(p) ? 2 : (p->nv == 3 ? 1 : 0); }
 
-size_t lds_pass_a(const pic_params *p)
-{
-    const size_t ng = p->n_cells;
-    return is_em(p) ? (3 + 2 + 3) * ng * 8 : 2 * ng * 8;
-}
-
-size_t lds_pass_b(const pic_params *p)
-{
-    const size_t ng = p->n_cells;
-    const bool pred = p->scheme != PIC_ESEC1;
-    return is_em(p) ? (6 + 4 + 3) * ng * 8 : (2 + (pred ? 1 : 0)) * ng * 8;
-}
-
 template <int ORDER, int NV, bool EM>
-void launch_a(pic_ctx *c, const double *X, const double *V)
+void launch_a(pic_ctx *c, int par, int64_t step)
 {
     hipLaunchKernelGGL((k_pass_a<ORDER, NV, EM>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_a(&c->p), c->stream, c->run, c->wk, X, V);
+                       lds_pass_a(&c->p), c->stream, c->run, c->wk, par, step, c->b.x, c->b.v);
 }
 
 template <int ORDER, int NV, bool EM, bool PRED>
-void launch_b(pic_ctx *c, const double *X, const double *V, double *Xo, double *Vo)
+void launch_b(pic_ctx *c, int par)
 {
     hipLaunchKernelGGL((k_pass_b<ORDER, NV, EM, PRED>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_b(&c->p), c->stream, c->run, c->wk, X, V, Xo, Vo);
+                       lds_pass_b(&c->p), c->stream, c->run, c->wk, par, c->b.x, c->b.v, c->b.x,
+                       c->b.v);
 }
 
 template <int ORDER, int NV, bool EM>
@@ -214,47 +209,48 @@ void launch_pre(pic_ctx *c)
                        (EM ? 3 : 1) * c->p.n_cells * 8, c->stream, c->run, c->wk, c->b.x, c->b.v);
 }
 
+enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO };
+
 template <int ORDER>
-void dispatch_order(pic_ctx *c, int what)
+void dispatch_order(pic_ctx *c, int what, int par, int64_t step)
 {
     const int kind = kind_of(&c->p);
     const bool pred = c->p.scheme != PIC_ESEC1;
-    double *X = c->b.x, *V = c->b.v;
     switch (what) {
-    case 0:   // pass A
-        if (kind == 0) launch_a<ORDER, 1, false>(c, X, V);
-        else if (kind == 1) launch_a<ORDER, 3, false>(c, X, V);
-        else launch_a<ORDER, 3, true>(c, X, V);
+    case D_PASS_A:
+        if (kind == 0) launch_a<ORDER, 1, false>(c, par, step);
+        else if (kind == 1) launch_a<ORDER, 3, false>(c, par, step);
+        else launch_a<ORDER, 3, true>(c, par, step);
         break;
-    case 1:   // pass B (in place)
+    case D_PASS_B:
         if (kind == 0) {
-            if (pred) launch_b<ORDER, 1, false, true>(c, X, V, X, V);
-            else launch_b<ORDER, 1, false, false>(c, X, V, X, V);
+            if (pred) launch_b<ORDER, 1, false, true>(c, par);
+            else launch_b<ORDER, 1, false, false>(c, par);
         } else if (kind == 1) {
-            if (pred) launch_b<ORDER, 3, false, true>(c, X, V, X, V);
-            else launch_b<ORDER, 3, false, false>(c, X, V, X, V);
+            if (pred) launch_b<ORDER, 3, false, true>(c, par);
+            else launch_b<ORDER, 3, false, false>(c, par);
         } else {
-            launch_b<ORDER, 3, true, true>(c, X, V, X, V);
+            launch_b<ORDER, 3, true, true>(c, par);
         }
         break;
-    case 2:   // initial predictor deposit
+    case D_PREDEPOSIT:
         if (kind == 0) launch_pre<ORDER, 1, false>(c);
         else if (kind == 1) launch_pre<ORDER, 3, false>(c);
         else launch_pre<ORDER, 3, true>(c);
         break;
-    case 3:   // charge deposit for the Gauss solve
+    case D_RHO:
         hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(c->run.nblocks), dim3(c->threads),
                            c->p.n_cells * 8, c->stream, c->run, c->wk, c->b.x);
         break;
     }
 }
 
-void dispatch(pic_ctx *c, int what)
+void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0)
 {
     if (c->p.shape_order == 1)
-        dispatch_order<1>(c, what);
+        dispatch_order<1>(c, what, par, step);
     else
-        dispatch_order<2>(c, what);
+        dispatch_order<2>(c, what, par, step);
 }
 
 int grid_threads(const pic_ctx *c)
@@ -374,6 +370,7 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     c->threads = threads_of(p);
     c->poisoned = 0;
     c->records_read = 0;
+    c->steps_done = 0;
     c->profiling = 0;
     for (int k = 0; k < PIC_K_COUNT; ++k) {
         c->prof_ms[k] = 0.0;
@@ -385,6 +382,8 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     r.ng = p->n_cells;
     r.nv = p->nv;
     r.nblocks = blocks_of(p, &r.chunk);
+    r.scheme = p->scheme;
+    r.pad = 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -402,22 +401,19 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     Work &w = c->wk;
     w.E = b->E;
     w.B = b->B;
-    w.Es = (double *)(ws + L.Es);
-    w.Bs = (double *)(ws + L.Bs);
-    w.Eb = (double *)(ws + L.Eb);
-    w.Bb = (double *)(ws + L.Bb);
-    w.J1 = (double *)(ws + L.J1);
-    w.J2 = (double *)(ws + L.J2);
+    for (int k = 0; k < 2; ++k) {
+        w.Ef[k] = (double *)(ws + L.Ef[k]);
+        w.Bf[k] = (double *)(ws + L.Bf[k]);
+        w.J1[k] = (double *)(ws + L.J1[k]);
+        w.J2[k] = (double *)(ws + L.J2[k]);
+    }
     w.cninv = (double *)(ws + L.cninv);
-    w.part_ke = (double *)(ws + L.part_ke);
-    w.part_gd = (double *)(ws + L.part_gd);
-    w.part_fb = (int64_t *)(ws + L.part_fb);
-    w.part_nf = (int32_t *)(ws + L.part_nf);
+    w.spart = (double *)(ws + L.spart);
     w.st = (DevState *)(ws + L.st);
     w.rec = (DevRecord *)(ws + L.rec);
 
-    // clear the accumulators and scratch fields (fill kernels, no memset)
-    fill(c, w.Es, (int64_t)(L.part_ke - L.Es) / 8, 0.0);
+    // clear the field and current buffers (fill kernels, no memset)
+    fill(c, w.Ef[0], (int64_t)(L.cninv - L.Ef[0]) / 8, 0.0);
     if (!is_em(p)) {
         // electrostatic runs carry only E_x; keep the unused components at zero
         fill(c, b->E + p->n_cells, 2 * (int64_t)p->n_cells, 0.0);
@@ -430,14 +426,14 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
         hipLaunchKernelGGL((k_init_particles<3>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w,
                            b->x, b->v);
     if (p->flags & PIC_F_INIT_GAUSS) {
-        dispatch(c, 3);
+        dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
     }
     if (is_em(p))
         hipLaunchKernelGGL(k_cn_init, dim3(1), dim3(gt), 0, c->stream, r, w);
     if (p->scheme != PIC_ESEC1)
-        dispatch(c, 2);
-    hipLaunchKernelGGL(k_field_tail, dim3(1), dim3(gt), 0, c->stream, r, w, p->scheme, 1);
+        dispatch(c, D_PREDEPOSIT);
+    hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
     rc = check(c, "pic_init launches");
     if (rc != PIC_OK) {
         g_last_error = c->err;
@@ -454,26 +450,18 @@ int pic_step(pic_ctx *c, int64_t n_steps)
         return PIC_ESTATE;
     if (n_steps < 0)
         return fail(&c->err, PIC_EINVAL, "n_steps must be >= 0");
-    const int gt = grid_threads(c);
-    const bool em = is_em(&c->p);
-    const size_t lds_f = em ? 11 * (size_t)c->p.n_cells * 8 : 0;
     for (int64_t s = 0; s < n_steps; ++s) {
+        const int64_t n = c->steps_done;
+        const int par = (int)(n & 1);
         {
             Timer t(c, PIC_K_PASS_A);
-            dispatch(c, 0);
-        }
-        {
-            Timer t(c, PIC_K_FIELD);
-            hipLaunchKernelGGL(k_field_update, dim3(1), dim3(gt), lds_f, c->stream, c->run, c->wk, em ? 1 : 0);
+            dispatch(c, D_PASS_A, par, n);
         }
         {
             Timer t(c, PIC_K_PASS_B);
-            dispatch(c, 1);
+            dispatch(c, D_PASS_B, par, n);
         }
-        {
-            Timer t(c, PIC_K_TAIL);
-            hipLaunchKernelGGL(k_field_tail, dim3(1), dim3(gt), 0, c->stream, c->run, c->wk, c->p.scheme, 0);
-        }
+        c->steps_done = n + 1;
         if (c->profiling && c->timed.size() > 4096) {
             // bound the number of outstanding events
             if (hipStreamSynchronize(c->stream) != hipSuccess)
@@ -481,6 +469,9 @@ int pic_step(pic_ctx *c, int64_t n_steps)
             collect(c);
         }
     }
+    if (n_steps > 0)
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(grid_threads(c)), 0, c->stream, c->run, c->wk,
+                           (int)(c->steps_done & 1), c->steps_done);
     return check(c, "pic_step launches");
 }
 
@@ -496,21 +487,25 @@ int pic_diagnostics(pic_ctx *c, pic_diag *out, int64_t max_records, int64_t *n_w
     DevState st;
     if (hipMemcpy(&st, c->wk.st, sizeof st, hipMemcpyDeviceToHost) != hipSuccess)
         return check(c, "pic_diagnostics state copy");
-    const int64_t last = st.step;                  // newest record
+    const int64_t last = st.recorded;              // newest record
     int64_t first = c->records_read;
     if (last - first + 1 > c->run.rec_cap)
         first = last - c->run.rec_cap + 1;           // older records were overwritten
     int64_t n = std::max<int64_t>(0, std::min<int64_t>(last - first + 1, max_records));
-    int nonfinite = 0;
-    for (int64_t k = 0; k < n; ++k) {
-        const int64_t step = first + k;
-        DevRecord rec;
-        if (hipMemcpy(&rec, c->wk.rec + step % c->run.rec_cap, sizeof rec, hipMemcpyDeviceToHost) != hipSuccess)
+    static_assert(sizeof(DevRecord) == sizeof(pic_diag), "record layout");
+    // the records are contiguous in the ring except where it wraps: at most two copies
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t slot = (first + done) % c->run.rec_cap;
+        const int64_t len = std::min<int64_t>(n - done, c->run.rec_cap - slot);
+        if (hipMemcpy(out + done, c->wk.rec + slot, (size_t)len * sizeof(DevRecord),
+                      hipMemcpyDeviceToHost) != hipSuccess)
             return check(c, "pic_diagnostics record copy");
-        static_assert(sizeof(DevRecord) == sizeof(pic_diag), "record layout");
-        std::memcpy(&out[k], &rec, sizeof rec);
-        nonfinite |= rec.nonfinite;
+        done += len;
     }
+    int nonfinite = 0;
+    for (int64_t k = 0; k < n; ++k)
+        nonfinite |= out[k].nonfinite;
     c->records_read = first + n;
     *n_written = n;
     return nonfinite ? PIC_ENONFINITE : PIC_OK;
