@@ -9,6 +9,11 @@ timed region (HIP events on the library's stream) covers only the steps.
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel (pass B,
 measured with HIP events around its launches), and the oracle timed on the host cores.
+
+``--form batched`` instead times the batched ensemble (512 Landau runs of 10^4 .. 10^6
+particles, about 1.1e8 in all) advanced together from a replayed hipGraph, with the launch
+shape picked by the autotuner, against the plain step run sequentially over the same
+runs; it prints one JSON line of its own.
 """
 import argparse
 import json
@@ -30,6 +35,107 @@ def alg_bytes(nv):
     return {"pass_a": state, "pass_b": 2 * state}
 
 
+def energy_report(recs):
+    """Energy error over the run: the largest |TE - TE0| / TE0, the largest before the
+    first Gamma fallback (the method conserves energy exactly until then), and the last
+    step at which the error is still within 1e-11."""
+    import numpy as np
+    err = recs["rel_energy_err"]
+    clean = recs["fallbacks_total"] == 0
+    bad = np.nonzero(err > 1e-11)[0]
+    return {"max_rel_err": float(err.max()),
+            "max_rel_err_before_first_fallback": float(err[clean].max()) if clean.any() else None,
+            "first_fallback_step": int(recs["step"][~clean][0]) if (~clean).any() else None,
+            "within_1e-11_through_step": int(recs["step"][bad[0] - 1]) if len(bad)
+            else int(recs["step"][-1]),
+            "fallbacks": int(recs["fallbacks_total"][-1]),
+            "steps_recorded": int(len(recs))}
+
+
+def bench_batched(args):
+    """Batched ensemble: aggregate particle-steps/s, against plain steps run by run."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2411_09605_amd import Pic, PicBatch, pack_runs
+    from paper_2411_09605_amd import autotune
+
+    runs = workloads.batched_landau()
+    ntot = sum(r.n_particles for r in runs)
+    print(f"[bench] batched: {len(runs)} runs, {ntot} particles", file=sys.stderr, flush=True)
+    packed = pack_runs(runs, "cuda:0")
+    tuned = autotune.tune(runs, packed=packed, use_cache=False)
+    print(f"[bench] tuned {tuned['block_threads']} threads, chunk {tuned['chunk']}",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    G = args.graph_steps
+    steps = max(G, args.steps // G * G) if G > 0 else args.steps
+    with torch.cuda.stream(stream):
+        b = PicBatch(packed=packed, block_threads=tuned["block_threads"], chunk=tuned["chunk"],
+                     graph_steps=G, stream=stream,
+                     record_capacity=steps + args.warmup + 8)
+        b.step(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = ntot * steps / (ms * 1e-3)
+    per_run = [energy_report(b.diagnostics(k)) for k in range(len(runs))]
+    clean = [e["max_rel_err"] for e in per_run if e["fallbacks"] == 0]
+    b.destroy()
+    del b, packed
+    torch.cuda.empty_cache()
+    print(f"[bench] batched {steps} steps in {ms:.2f} ms", file=sys.stderr, flush=True)
+
+    # the plain step, run after run, on the same runs
+    ctxs = [Pic.from_workload(r, device="cuda:0") for r in runs]
+    for c in ctxs:
+        c.step(1)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    cur = torch.cuda.current_stream()
+    s0.record(cur)
+    for c in ctxs:
+        c.step(args.seq_steps)
+    s1.record(cur)
+    torch.cuda.synchronize()
+    seq_ms = s0.elapsed_time(s1)
+    seq_value = ntot * args.seq_steps / (seq_ms * 1e-3)
+    for c in ctxs:
+        c.destroy()
+    alg = alg_bytes(1)
+    step_bytes = (alg["pass_a"] + alg["pass_b"]) * ntot
+    achieved = step_bytes / (ms / steps * 1e-3) / 1e9
+    out = {
+        "metric": "aggregate particle-steps/s, batched ensemble of 512 Landau runs (FP64)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched_landau_512runs", "n_runs": len(runs),
+                   "n_particles_total": ntot, "shape_order": runs[0].order,
+                   "scheme": runs[0].scheme, "dt": runs[0].dt, "graph_steps": G,
+                   "block_threads": tuned["block_threads"], "chunk": tuned["chunk"]},
+        "sequential_plain": {"value": seq_value, "steps": args.seq_steps,
+                             "ms_per_step": seq_ms / args.seq_steps},
+        "speedup_vs_sequential": value / seq_value,
+        "energy": {"runs_without_fallback": len(clean),
+                   "max_rel_err_runs_without_fallback": max(clean) if clean else None,
+                   "runs_with_fallbacks": len(runs) - len(clean),
+                   "fallbacks": int(sum(e["fallbacks"] for e in per_run))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole step (k_batch_pass_a + k_batch_pass_b)",
+                     "alg_bytes_per_particle_step": alg["pass_a"] + alg["pass_b"]},
+        "autotune": tuned["trials"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def workload_for(name):
     import workloads
     return workloads.by_name(name)
@@ -48,6 +154,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="oracle steps of the same workload for the CPU baseline (0: skip)")
+    ap.add_argument("--form", choices=("plain", "batched"), default="plain")
+    ap.add_argument("--graph-steps", type=int, default=50,
+                    help="batched form: steps per captured hipGraph")
+    ap.add_argument("--seq-steps", type=int, default=20,
+                    help="batched form: steps of the sequential plain-step comparison")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -55,6 +166,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the 1D grid would be all-reduced across GPUs; not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.form == "batched":
+        return bench_batched(args)
 
     import numpy as np
     import torch
@@ -68,7 +182,7 @@ def main():
                  record_capacity=max(4096, args.steps + args.warmup + args.profile_steps + 8))
     gpu = Pic.from_workload(wl, device="cuda:0", **knobs)
     gpu.step(args.warmup)
-    gpu.diagnostics()
+    warm_recs = gpu.diagnostics()
     torch.cuda.synchronize()
 
     stream = gpu.stream
@@ -81,6 +195,7 @@ def main():
     ms = t0.elapsed_time(t1)
     recs = gpu.diagnostics()
     print(f"[bench] timed {args.steps} steps in {ms:.2f} ms", file=sys.stderr, flush=True)
+    energy = energy_report(np.concatenate([warm_recs, recs]))
 
     # per-kernel durations from HIP events around each launch (separate segment)
     prof = None
@@ -139,11 +254,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": n, "n_cells": wl.n_cells,
                    "shape_order": wl.order, "scheme": wl.scheme, "dt": wl.dt,
-                   "nv": wl.nv, "block_threads": args.block_threads,
-                   "grid_blocks": args.grid_blocks, "deposit_mode": args.deposit_mode,
+                   "nv": wl.nv, "block_threads": gpu.block_threads,
+                   "grid_blocks": gpu.grid_blocks, "deposit_mode": args.deposit_mode,
                    "rebin_every": args.rebin_every},
-        "max_rel_energy_err": float(np.max(recs["rel_energy_err"])) if len(recs) else None,
-        "fallbacks": int(np.sum(recs["fallbacks"])) if len(recs) else None,
+        "energy": energy,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -71,13 +71,14 @@ enum pic_flag {
     PIC_F_TRACK_IDS = 2u     /* permute the caller's id array with the particles        */
 };
 
-/* Deposit strategies for the current tiles (section 2.2 deposit).  Both give the same
- * sums up to floating-point summation order. */
+/* Deposit strategies for the per-workgroup LDS current tiles (section 2.2 deposit).  All
+ * give the same sums up to floating-point summation order. */
 enum pic_deposit_mode {
-    PIC_DEPOSIT_AUTO = 0,
-    PIC_DEPOSIT_LDS_ATOMIC = 1,   /* per-particle LDS atomics into the block's tile    */
-    PIC_DEPOSIT_WAVE_REDUCE = 2   /* wavefront pre-reduction per node, then LDS atomics;
-                                     pays off when particles are cell-sorted            */
+    PIC_DEPOSIT_AUTO = 0,         /* WINDOW when rebin_every > 0, else LDS_ATOMIC         */
+    PIC_DEPOSIT_LDS_ATOMIC = 1,   /* every particle adds its stencil with LDS atomics     */
+    PIC_DEPOSIT_WINDOW = 2        /* each thread sums its particles' stencils in registers
+                                     over a few nodes and adds them when the window moves;
+                                     pays off when particles are cell-sorted             */
 };
 
 typedef struct {
@@ -87,7 +88,9 @@ typedef struct {
     int32_t shape_order;   /* B-spline degree: 1 (tent) or 2 (quadratic)                 */
     int64_t n_particles;   /* N_p >= 1                                                   */
     int32_t n_cells;       /* N_g >= 2 * shape_order + 1                                 */
-    int32_t rebin_every;   /* counting-sort the particles by cell every K steps; 0: never */
+    int32_t rebin_every;   /* counting-sort the particles by (cell, sign of v_x) before
+                              steps 0, K, 2K, ...; 0: never.  Particle order is then
+                              unspecified: track identities with PIC_F_TRACK_IDS          */
     double  length;        /* L > 0                                                      */
     double  dt;            /* time step > 0                                              */
     double  c;             /* speed of light (PIC_EMEC_LI), > 0                          */
@@ -95,9 +98,10 @@ typedef struct {
                               (section 3.2 starts from an externally imposed B); used
                               only when nv == 3                                           */
     uint32_t flags;        /* enum pic_flag bits                                         */
-    int32_t block_threads; /* threads per workgroup of the particle passes: 0 = default,
-                              else a multiple of 64 in [64, 1024]                         */
-    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default (by size)   */
+    int32_t block_threads; /* threads per workgroup of the particle passes: 0 = default
+                              (512), else a multiple of 64 in [64, 1024]                  */
+    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default,
+                              min(ceil(N_p / block_threads), 512)                         */
     int32_t deposit_mode;  /* enum pic_deposit_mode                                      */
     int32_t record_capacity; /* per-step diagnostic records kept on the device: 0 = 4096 */
     int32_t reserved;      /* must be 0                                                  */
@@ -179,6 +183,11 @@ enum pic_kernel_class {
  * launch.  Timing adds a few microseconds per launch; use it on a separate run. */
 int pic_profile_enable(pic_ctx *ctx, int on);
 
+/* The launch shape the context resolved (threads per workgroup, workgroups and particles
+ * per workgroup of the particle passes).  Any output pointer may be NULL. */
+int pic_launch_shape(const pic_ctx *ctx, int32_t *block_threads, int32_t *grid_blocks,
+                     int64_t *chunk);
+
 /* Synchronise and return, per pic_kernel_class, the summed milliseconds and the launch
  * count since profiling was enabled (arrays of PIC_K_COUNT entries); resets them. */
 int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches);
@@ -187,6 +196,67 @@ int pic_profile_read(pic_ctx *ctx, double *ms, int64_t *launches);
 int pic_destroy(pic_ctx *ctx);
 
 const char *pic_strerror(int status);
+
+/* ------------------------------------------------------------ batched ensemble form
+ * Many independent runs of one scheme advanced together: each run has its own particle
+ * count, cell count and length; all share the scheme, shape order, nv, dt, c and b_ext.
+ * Every pass of every step is one persistent launch over a table of work items (chunks of
+ * one run's particles), and steps can be replayed from a captured hipGraph.  Each run
+ * computes exactly what pic_step computes for it alone (same records, same parity). */
+enum pic_batch_flag {
+    PIC_BF_INIT_GAUSS = 1u       /* as PIC_F_INIT_GAUSS, for every run                     */
+};
+
+typedef struct {
+    int32_t abi_version;         /* PIC_ABI_VERSION                                       */
+    int32_t n_runs;              /* >= 1                                                  */
+    int32_t nv, scheme, shape_order;
+    uint32_t flags;              /* enum pic_batch_flag                                   */
+    double  dt, c;
+    double  b_ext[3];
+    const int64_t *n_particles;  /* HOST array [n_runs]: N_p of each run (>= 1)           */
+    const int32_t *n_cells;      /* HOST array [n_runs]: N_g of each run                  */
+    const double  *length;       /* HOST array [n_runs]: L of each run                    */
+    int32_t block_threads;       /* 0 = default, else a multiple of 64 in [64, 1024]      */
+    int32_t chunk;               /* particles per work item, 0 = default; a multiple of
+                                    block_threads                                         */
+    int32_t grid_blocks;         /* persistent grid, 0 = default                          */
+    int32_t graph_steps;         /* > 0: pic_batch_step replays a captured hipGraph of this
+                                    many steps (needs a non-null stream); 0: plain launches */
+    int32_t record_capacity;     /* per-run record ring, 0 = 1024                         */
+    int32_t reserved;            /* 0                                                     */
+} pic_batch_params;
+
+typedef struct {                 /* DEVICE pointers, caller-owned, packed by run          */
+    double  *x;                  /* [N] with N = sum_r N_p,r; run r starts at
+                                    P_r = sum_{s<r} N_p,s                                  */
+    double  *v;                  /* [nv][N]: component c of run r at c N + P_r            */
+    const double *w;             /* [N] weights or NULL (uniform L_r / N_p,r per run)     */
+    double  *E;                  /* [3 G] with G = sum_r N_g,r: run r's [3][N_g,r] block
+                                    starts at 3 sum_{s<r} N_g,s                             */
+    double  *B;                  /* [2 G] likewise (EMEC(LI) only), else NULL             */
+    void    *workspace;          /* >= pic_batch_workspace_size bytes, 256-byte aligned   */
+    size_t   workspace_bytes;
+} pic_batch_buffers;
+
+typedef struct pic_batch pic_batch;
+
+/* Workspace bytes for these parameters, 0 if invalid (pic_last_error(NULL) says why). */
+size_t pic_batch_workspace_size(const pic_batch_params *p);
+
+/* Bind and initialise every run (as pic_init does for one run). */
+int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *hip_stream,
+                   pic_batch **out);
+
+/* Enqueue n_steps steps of every run; asynchronous. */
+int pic_batch_step(pic_batch *ctx, int64_t n_steps);
+
+/* Synchronise and copy out run `run`'s records written since the previous call for that
+ * run (the first call also returns step 0), as pic_diagnostics does. */
+int pic_batch_diagnostics(pic_batch *ctx, int32_t run, pic_diag *out, int64_t max_records,
+                          int64_t *n_written);
+
+int pic_batch_destroy(pic_batch *ctx);
 
 /* Last error message of a context, or of the calling thread's last failed
  * validation/init when ctx is NULL. */

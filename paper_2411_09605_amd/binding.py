@@ -19,7 +19,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUN
     0, -1, -2, -3, -4, -5, -6
 SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
 F_INIT_GAUSS, F_TRACK_IDS = 1, 2
-DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "wave_reduce": 2}
+DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2}
 ABI_VERSION = 1
 
 
@@ -49,7 +49,7 @@ DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("fiel
 # Every function declared in include/pic.h.
 EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
            "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
-           "pic_destroy", "pic_strerror", "pic_last_error")
+           "pic_launch_shape", "pic_destroy", "pic_strerror", "pic_last_error")
 KERNEL_CLASSES = ("pass_a", "pass_b", "rebin")
 
 
@@ -85,6 +85,8 @@ def _load():
     lib.pic_profile_enable.restype = ctypes.c_int
     lib.pic_profile_read.argtypes = [vp, vp, vp]
     lib.pic_profile_read.restype = ctypes.c_int
+    lib.pic_launch_shape.argtypes = [vp, vp, vp, vp]
+    lib.pic_launch_shape.restype = ctypes.c_int
     lib.pic_destroy.argtypes = [vp]
     lib.pic_destroy.restype = ctypes.c_int
     lib.pic_strerror.argtypes = [ctypes.c_int]
@@ -191,6 +193,21 @@ class Pic:
         self.records.extend(recs)
         return recs
 
+    def launch_shape(self) -> tuple:
+        """(threads per workgroup, workgroups, particles per workgroup) of the passes."""
+        t, g, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.pic_launch_shape(self.ctx, ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)),
+               self.ctx)
+        return t.value, g.value, c.value
+
+    @property
+    def block_threads(self) -> int:
+        return self.launch_shape()[0]
+
+    @property
+    def grid_blocks(self) -> int:
+        return self.launch_shape()[1]
+
     def profile(self, on: bool = True):
         """Turn HIP-event timing of each launch on or off."""
         _check(lib.pic_profile_enable(self.ctx, 1 if on else 0), self.ctx)
@@ -229,10 +246,13 @@ class Pic:
     @classmethod
     def from_arrays(cls, nv, scheme, order, n_cells, length, dt, x, v, E0=None, B0=None,
                     w=None, c=1.0, b_ext=(0.0, 0.0, 0.0), init_gauss=False, ids=None,
-                    device="cuda", **knobs) -> "Pic":
-        """Copy host arrays to the device and initialise a run."""
+                    track_ids=False, device="cuda", **knobs) -> "Pic":
+        """Copy host arrays to the device and initialise a run.  ``track_ids`` without
+        ``ids`` numbers the particles 0 .. N_p - 1."""
         import torch
         n = int(np.asarray(x).shape[0])
+        if track_ids and ids is None:
+            ids = np.arange(n, dtype=np.int64)
         f64 = dict(dtype=torch.float64, device=device)
         xt = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).to(**f64).contiguous()
         vt = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64).reshape(nv, n)).to(**f64).contiguous()
@@ -258,3 +278,213 @@ class Pic:
         return cls.from_arrays(wl.nv, scheme or wl.scheme, wl.order, wl.n_cells, wl.length,
                                wl.dt, wl.x, wl.v, E0=wl.E0, B0=wl.B0, w=wl.w, c=wl.c,
                                b_ext=wl.b_ext, init_gauss=wl.init_gauss, device=device, **knobs)
+
+
+# ---------------------------------------------------------------- batched ensemble
+class PicBatchParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("n_runs", ctypes.c_int32),
+                ("nv", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("shape_order", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double),
+                ("b_ext", ctypes.c_double * 3),
+                ("n_particles", ctypes.POINTER(ctypes.c_int64)),
+                ("n_cells", ctypes.POINTER(ctypes.c_int32)),
+                ("length", ctypes.POINTER(ctypes.c_double)),
+                ("block_threads", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("record_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PicBatchBuffers(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+BATCH_EXPORTS = ("pic_batch_workspace_size", "pic_batch_init", "pic_batch_step",
+                 "pic_batch_diagnostics", "pic_batch_destroy")
+
+
+def _load_batch(L):
+    vp = ctypes.c_void_p
+    BP = ctypes.POINTER(PicBatchParams)
+    L.pic_batch_workspace_size.argtypes = [BP]
+    L.pic_batch_workspace_size.restype = ctypes.c_size_t
+    L.pic_batch_init.argtypes = [BP, ctypes.POINTER(PicBatchBuffers), vp, ctypes.POINTER(vp)]
+    L.pic_batch_init.restype = ctypes.c_int
+    L.pic_batch_step.argtypes = [vp, ctypes.c_int64]
+    L.pic_batch_step.restype = ctypes.c_int
+    L.pic_batch_diagnostics.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_int64)]
+    L.pic_batch_diagnostics.restype = ctypes.c_int
+    L.pic_batch_destroy.argtypes = [vp]
+    L.pic_batch_destroy.restype = ctypes.c_int
+
+
+_load_batch(lib)
+EXPORTS = EXPORTS + BATCH_EXPORTS
+
+
+def make_batch_params(nv, scheme, shape_order, n_particles, n_cells, length, dt, c=1.0,
+                      b_ext=(0.0, 0.0, 0.0), init_gauss=True, block_threads=0, chunk=0,
+                      grid_blocks=0, graph_steps=0, record_capacity=0) -> PicBatchParams:
+    """A pic_batch_params; the per-run arrays are kept alive on the returned struct."""
+    p = PicBatchParams()
+    p._np = np.ascontiguousarray(n_particles, dtype=np.int64)
+    p._ng = np.ascontiguousarray(n_cells, dtype=np.int32)
+    p._len = np.ascontiguousarray(length, dtype=np.float64)
+    if not (len(p._np) == len(p._ng) == len(p._len)):
+        raise ValueError("per-run arrays differ in length")
+    p.abi_version = ABI_VERSION
+    p.n_runs = len(p._np)
+    p.nv = nv
+    p.scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+    p.shape_order = shape_order
+    p.flags = 1 if init_gauss else 0
+    p.dt, p.c = dt, c
+    for i in range(3):
+        p.b_ext[i] = b_ext[i]
+    p.n_particles = p._np.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    p.n_cells = p._ng.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    p.length = p._len.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.block_threads, p.chunk, p.grid_blocks = block_threads, chunk, grid_blocks
+    p.graph_steps, p.record_capacity, p.reserved = graph_steps, record_capacity, 0
+    return p
+
+
+def batch_workspace_size(p: PicBatchParams) -> int:
+    return int(lib.pic_batch_workspace_size(ctypes.byref(p)))
+
+
+def pack_runs(runs, device="cuda") -> dict:
+    """Pack the runs' particles and fields into the batched layout on the device.
+
+    Returns a dict of tensors (x, v, w or None, E, B or None) and host index arrays; a
+    PicBatch built from it steps clones of the tensors, so one packing can serve several
+    contexts (the autotuner, the benchmark)."""
+    import torch
+    r0 = runs[0]
+    for r in runs:
+        if (r.nv, r.scheme, r.order, r.dt, r.c, tuple(r.b_ext)) != \
+                (r0.nv, r0.scheme, r0.order, r0.dt, r0.c, tuple(r0.b_ext)):
+            raise ValueError("runs of a batch share nv, scheme, order, dt, c and b_ext")
+    nv = r0.nv
+    np_ = np.array([r.n_particles for r in runs], dtype=np.int64)
+    ng_ = np.array([r.n_cells for r in runs], dtype=np.int32)
+    len_ = np.array([r.length for r in runs], dtype=np.float64)
+    poff = np.concatenate([[0], np.cumsum(np_)])
+    goff = np.concatenate([[0], np.cumsum(ng_)])
+    N, G = int(poff[-1]), int(goff[-1])
+    f64 = dict(dtype=torch.float64, device=device)
+    x = torch.empty(N, **f64)
+    v = torch.empty((nv, N), **f64)
+    for k, r in enumerate(runs):
+        a, b = int(poff[k]), int(poff[k + 1])
+        x[a:b] = torch.as_tensor(np.asarray(r.x, dtype=np.float64))
+        v[:, a:b] = torch.as_tensor(np.asarray(r.v, dtype=np.float64).reshape(nv, -1))
+    Eh = np.zeros(3 * G)
+    Bh = np.zeros(2 * G)
+    for k, r in enumerate(runs):
+        g0, ng = int(goff[k]), int(ng_[k])
+        if r.E0 is not None:
+            Eh[3 * g0:3 * g0 + 3 * ng] = np.asarray(r.E0, dtype=np.float64).reshape(-1)
+        if r.B0 is not None:
+            Bh[2 * g0:2 * g0 + 2 * ng] = np.asarray(r.B0, dtype=np.float64).reshape(-1)
+    w = None
+    if any(r.w is not None for r in runs):
+        w = torch.as_tensor(np.concatenate(
+            [np.asarray(r.w, dtype=np.float64) if r.w is not None
+             else np.full(r.n_particles, r.length / r.n_particles) for r in runs])).to(**f64)
+    return dict(x=x, v=v, w=w, E=torch.as_tensor(Eh).to(**f64),
+                B=torch.as_tensor(Bh).to(**f64) if r0.scheme == "emec_li" else None,
+                np=np_, ng=ng_, len=len_, poff=poff, goff=goff, nv=nv, r0=r0,
+                init_gauss=all(r.init_gauss for r in runs))
+
+
+class PicBatch:
+    """Many independent runs advanced together (one persistent launch per pass).
+
+    Built from a list of run descriptions with the fields of ``workloads.Workload`` that
+    share nv, scheme, order, dt, c and b_ext (or from ``pack_runs`` of such a list).
+    Particles are packed run after run."""
+
+    def __init__(self, runs=None, device="cuda", block_threads=0, chunk=0, grid_blocks=0,
+                 graph_steps=0, record_capacity=0, stream=None, packed=None):
+        import torch
+        self.torch = torch
+        if packed is None:
+            packed = pack_runs(runs, device)
+            own = True
+        else:
+            own = False
+        r0 = packed["r0"]
+        self.nv = packed["nv"]
+        self.np_, self.ng_, self.len_ = packed["np"], packed["ng"], packed["len"]
+        self.poff, self.goff = packed["poff"], packed["goff"]
+        self.nruns = len(self.np_)
+
+        def mine(t):
+            return None if t is None else (t if own else t.clone())
+        self.x, self.v, self.w = mine(packed["x"]), mine(packed["v"]), packed["w"]
+        self.E, self.B = mine(packed["E"]), mine(packed["B"])
+        p = make_batch_params(r0.nv, r0.scheme, r0.order, self.np_, self.ng_, self.len_,
+                              dt=r0.dt, c=r0.c, b_ext=r0.b_ext, init_gauss=packed["init_gauss"],
+                              block_threads=block_threads, chunk=chunk,
+                              grid_blocks=grid_blocks, graph_steps=graph_steps,
+                              record_capacity=record_capacity)
+        self.params = p
+        nbytes = batch_workspace_size(p)
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, last_error())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.x.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        # graph replay needs a stream other than the legacy default one
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.x.device)
+        torch.cuda.synchronize(self.x.device)
+        buf = PicBatchBuffers()
+        buf.x, buf.v, buf.E = self.x.data_ptr(), self.v.data_ptr(), self.E.data_ptr()
+        buf.B = self.B.data_ptr() if self.B is not None else None
+        buf.w = self.w.data_ptr() if self.w is not None else None
+        buf.workspace, buf.workspace_bytes = aligned, nbytes
+        self._buf = buf
+        ctx = ctypes.c_void_p()
+        rc = lib.pic_batch_init(ctypes.byref(p), ctypes.byref(buf),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        _check(rc)
+        self.ctx = ctx
+
+    @property
+    def n_particles_total(self) -> int:
+        return int(self.poff[-1])
+
+    def step(self, n: int = 1):
+        _check(lib.pic_batch_step(self.ctx, n))
+
+    def diagnostics(self, run: int, max_records: int = 1 << 16) -> np.ndarray:
+        out = np.zeros(max_records, dtype=DIAG_DTYPE)
+        nw = ctypes.c_int64()
+        rc = lib.pic_batch_diagnostics(self.ctx, run, out.ctypes.data, max_records, ctypes.byref(nw))
+        if rc not in (PIC_OK, PIC_ENONFINITE):
+            _check(rc)
+        return out[:nw.value].copy()
+
+    def state(self, run: int) -> dict:
+        self.torch.cuda.synchronize()
+        a, b = int(self.poff[run]), int(self.poff[run + 1])
+        g0, ng = int(self.goff[run]), int(self.ng_[run])
+        d = dict(x=self.x[a:b].cpu().numpy(), v=self.v[:, a:b].cpu().numpy(),
+                 E=self.E[3 * g0:3 * g0 + 3 * ng].reshape(3, ng).cpu().numpy())
+        if self.B is not None:
+            d["B"] = self.B[2 * g0:2 * g0 + 2 * ng].reshape(2, ng).cpu().numpy()
+        return d
+
+    def destroy(self):
+        if getattr(self, "ctx", None):
+            lib.pic_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

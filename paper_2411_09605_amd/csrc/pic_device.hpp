@@ -34,6 +34,8 @@ namespace pic {
 
 constexpr int kMaxGrid = 8192;   // upper bound on particle-pass workgroups
 constexpr int kNS = 4;           // per-workgroup scalars: KE, fallbacks, max|G-1|, nonfinite
+constexpr int kGhost = 4;        // ghost nodes on each side of an LDS field or current tile
+constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
 
 // Particles whose loads each thread issues together before computing on them, per pass
 // (more loads in flight against fewer waves per SIMD from the extra registers).
@@ -60,12 +62,14 @@ struct DevState {
 // Scalars of a run, passed by value to every kernel.
 struct Run {
     int64_t np;
+    int64_t vstride;       // distance between velocity components in V (N_p, or the
+                           // packed total in the batched form)
     int32_t ng, nv;
     int32_t nblocks;       // workgroups of the particle passes
     int32_t rec_cap;
     int64_t chunk;         // particles per workgroup
     int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI)
-    int32_t pad;
+    int32_t tw;            // LDS tile width: ng + 2 kGhost
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -84,6 +88,12 @@ struct Work {
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
     DevState *st;
     DevRecord *rec;        // [rec_cap] ring
+    // counting-sort rebin (only when enabled)
+    double *x2, *v2;       // [N_p], [nv][N_p] sorted copy of the state
+    int64_t *id2;          // [N_p] (ids tracked)
+    double *wcur, *w2;     // [N_p] permuted weights (non-uniform weights)
+    int64_t *hist;         // [nbins][nblocks] counts, then offsets
+    int64_t *segsum;       // [nseg] per-segment sums of hist
 };
 
 // ------------------------------------------------------------------ shape functions
@@ -137,24 +147,40 @@ __device__ __forceinline__ int wrap_node(int i, int ng)
     return r < 0 ? r + ng : r;
 }
 
-template <int ORDER> struct Nodes {
+// LDS tiles hold N_g nodes plus kGhost periodic copies on each side: node i of
+// component c sits at slot c * tw + kGhost + i (tw = N_g + 2 kGhost).  A stencil whose
+// nodes fall inside the padded range indexes the tile directly; only particles beyond
+// the ghost band go through the periodic wrap.
+template <int ORDER> struct Slots {
     int n[ORDER + 1];
 };
 
 template <int ORDER>
-__device__ __forceinline__ Nodes<ORDER> nodes_of(const Stencil<ORDER> &s, int ng)
+__device__ __forceinline__ Slots<ORDER> slots_of(const Stencil<ORDER> &s, int ng)
 {
-    Nodes<ORDER> o;
-    o.n[0] = wrap_node(s.first, ng);
+    Slots<ORDER> o;
+    const int b = s.first + kGhost;
+    if ((unsigned)b <= (unsigned)(ng + 2 * kGhost - ORDER - 1)) {
 #pragma unroll
-    for (int k = 1; k <= ORDER; ++k)
-        o.n[k] = (o.n[k - 1] + 1 == ng) ? 0 : o.n[k - 1] + 1;
+        for (int k = 0; k <= ORDER; ++k)
+            o.n[k] = b + k;
+    } else {
+#pragma unroll
+        for (int k = 0; k <= ORDER; ++k)
+            o.n[k] = wrap_node(s.first + k, ng) + kGhost;
+    }
     return o;
+}
+
+__device__ __forceinline__ int slot_of_node(int i, int ng)
+{
+    return (unsigned)(i + kGhost) < (unsigned)(ng + 2 * kGhost) ? i + kGhost
+                                                                 : wrap_node(i, ng) + kGhost;
 }
 
 template <int ORDER>
 __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDER> &s,
-                                          const Nodes<ORDER> &n)
+                                          const Slots<ORDER> &n)
 {
     double acc = 0.0;
 #pragma unroll
@@ -163,14 +189,86 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
     return acc;
 }
 
-template <int ORDER>
-__device__ __forceinline__ void deposit1(double *tile, const Stencil<ORDER> &s,
-                                         const Nodes<ORDER> &n, double q)
-{
+// Deposit accumulator of one thread for NC current components (tile stride tw).
+// DEP = 0: each particle adds its ORDER + 1 contributions with LDS atomics.
+// DEP = 1 (particles cell-sorted, so a thread's successive particles share a cell or
+// two): contributions are summed in registers over a window of ORDER + 3 nodes anchored
+// one node left of the stencil that opened it, and added to the tile only when a
+// particle's stencil leaves the window, and at the end.
+template <int ORDER, int NC, int DEP> struct Depo;
+
+template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
+    __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
+                                        const double (&q)[NC])
+    {
+        const Slots<ORDER> sl = slots_of<ORDER>(s, ng);
 #pragma unroll
-    for (int k = 0; k <= ORDER; ++k)
-        atomicAdd(&tile[n.n[k]], q * s.w[k]);
-}
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int k = 0; k <= ORDER; ++k)
+                atomicAdd(&jt[c * tw + sl.n[k]], q[c] * s.w[k]);
+    }
+    __device__ __forceinline__ void finish(double *, int, int) {}
+};
+
+template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
+    static constexpr int W = ORDER + 3;
+    int anchor;
+    bool live;
+    double acc[NC][W];
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                acc[c][j] = 0.0;
+    }
+    __device__ __forceinline__ void init()
+    {
+        live = false;
+        anchor = 0;
+        clear();
+    }
+    __device__ __forceinline__ void flush(double *jt, int tw, int ng)
+    {
+        if (!live)
+            return;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int slot = slot_of_node(anchor + j, ng);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (acc[c][j] != 0.0)
+                    atomicAdd(&jt[c * tw + slot], acc[c][j]);
+        }
+        clear();
+    }
+    __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
+                                        const double (&q)[NC])
+    {
+        int d = s.first - anchor;
+        if (!live || d < 0 || d > W - ORDER - 1) {
+            flush(jt, tw, ng);
+            anchor = s.first - 1;
+            live = true;
+            d = 1;
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k <= ORDER; ++k)
+                if (j - k >= 0 && j - k <= W - ORDER - 1)
+                    a = (d == j - k) ? s.w[k] : a;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                acc[c][j] = fma(q[c], a, acc[c][j]);
+        }
+    }
+    __device__ __forceinline__ void finish(double *jt, int tw, int ng) { flush(jt, tw, ng); }
+};
 
 // Periodic position in [0, L).  A particle moves less than a period per step, so one
 // conditional add or subtract almost always suffices; otherwise x - L floor(x / L),
@@ -261,14 +359,39 @@ __device__ __forceinline__ void tile_zero(double *dst, int n)
         dst[i] = 0.0;
 }
 
-// Add a workgroup's LDS current tile into the global current (hardware FP64 atomics;
-// zero entries, common when the particles are cell-sorted, are skipped).
-__device__ __forceinline__ void tile_flush(const double *tile, double *J, int n)
+// Fill the ghost slots of ncomp tile components from their periodic images (the
+// interior must be written and visible).
+__device__ __forceinline__ void ghost_fill(double *tile, int ncomp, int ng, int tw)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double val = tile[i];
-        if (val != 0.0)
-            unsafeAtomicAdd(&J[i], val);
+    for (int idx = threadIdx.x; idx < ncomp * 2 * kGhost; idx += blockDim.x) {
+        const int c = idx / (2 * kGhost), j = idx % (2 * kGhost);
+        const int slot = j < kGhost ? j : ng + j;
+        tile[c * tw + slot] = tile[c * tw + wrap_node(slot - kGhost, ng) + kGhost];
+    }
+}
+
+// Cooperative load of ncomp node arrays (stride ng) into a ghost-padded tile.
+__device__ __forceinline__ void tile_load_ghost(double *tile, const double *src, int ncomp,
+                                                int ng, int tw)
+{
+    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+        const int c = idx / tw, j = idx % tw;
+        tile[idx] = src[c * ng + wrap_node(j - kGhost, ng)];
+    }
+}
+
+// Add a workgroup's ghost-padded LDS current tile (ncomp components) into the global
+// current (hardware FP64 atomics); ghost slots go to their periodic nodes, zero entries
+// (common when the particles are cell-sorted) are skipped.
+__device__ __forceinline__ void tile_flush(const double *tile, double *J, int ncomp, int ng,
+                                           int tw)
+{
+    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+        const double val = tile[idx];
+        if (val != 0.0) {
+            const int c = idx / tw, j = idx % tw;
+            unsafeAtomicAdd(&J[c * ng + wrap_node(j - kGhost, ng)], val);
+        }
     }
 }
 
@@ -283,7 +406,8 @@ __device__ __forceinline__ double dminus(const double *g, int i, int ng, double 
     return (g[i] - g[i == 0 ? ng - 1 : i - 1]) * inv_h;
 }
 
-// Predictor fields into LDS (es [ne][ng], bs [2][ng]) from E^n, B^n and j^{n,*}:
+// Predictor fields into the interiors of the LDS tiles es [ne][tw], bs [2][tw] from E^n,
+// B^n and j^{n,*} (the caller fills the ghosts):
 //   ESEC2: E* = E - dt/2 (j - mean j)                        (eq. (good_translation))
 //   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
 //   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
@@ -291,30 +415,33 @@ __device__ __forceinline__ double dminus(const double *g, int i, int ng, double 
 __device__ void predictor_fields(const Run &r, const double *E, const double *B,
                                  const double *J, double *es, double *bs, double *red)
 {
-    const int ng = r.ng;
+    const int ng = r.ng, tw = r.tw;
+    double *e0 = es + kGhost, *b0 = bs + kGhost;
     if (r.scheme == 1) {
-        tile_load(es, E, ng);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            e0[i] = E[i];
         return;
     }
     if (r.scheme == 0) {
         const double mean = block_mean(J, ng, red);
         for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            es[i] = E[i] - r.hdt * (J[i] - mean);
+            e0[i] = E[i] - r.hdt * (J[i] - mean);
         return;
     }
     const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
     const double *By = B, *Bz = B + ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        es[i] = Ex[i] - r.hdt * J[i];
-        es[ng + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - J[ng + i]);
-        es[2 * ng + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - J[2 * ng + i]);
-        bs[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
-        bs[ng + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
+        e0[i] = Ex[i] - r.hdt * J[i];
+        e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - J[ng + i]);
+        e0[2 * tw + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - J[2 * ng + i]);
+        b0[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
+        b0[tw + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
     }
 }
 
 // Field update from the centred current J (global): new fields into e1 [ne][ng] and
-// b1 [2][ng] (LDS), averaged fields into eb, bb (LDS).
+// b1 [2][ng] (LDS), averaged fields into the interiors of the tiles eb [ne][tw],
+// bb [2][tw] (the caller fills the ghosts).
 //   ES: E^{n+1} = E^n - dt (j - mean j)                    (eq. (ampere) in 1D)
 //   EM (a = dt/2, s = a^2 c^2, L_h = D-D+), eq. (EMbasic) with Crank-Nicolson:
 //     (I - s L_h) E_y' = (I + s L_h) E_y - dt c^2 D-B_z - dt j_y,  B_z' = B_z - a D+(E_y + E_y')
@@ -326,14 +453,14 @@ __device__ void field_update(const Run &r, const Work &wk, const double *E, cons
                              const double *J, double *e1, double *b1, double *eb, double *bb,
                              double *scratch, double *red)
 {
-    const int ng = r.ng;
+    const int ng = r.ng, tw = r.tw;
     if (r.scheme != 2) {
         const double mean = block_mean(J, ng, red);
         for (int i = threadIdx.x; i < ng; i += blockDim.x) {
             const double e0 = E[i];
             const double en = e0 - r.dt * (J[i] - mean);
             e1[i] = en;
-            eb[i] = 0.5 * (e0 + en);
+            eb[kGhost + i] = 0.5 * (e0 + en);
         }
         return;
     }
@@ -375,9 +502,9 @@ __device__ void field_update(const Run &r, const Work &wk, const double *E, cons
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
-        eb[i] = 0.5 * (E0[i] + e1[i]);
+        eb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (E0[i] + e1[i]);
     for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
-        bb[i] = 0.5 * (B0[i] + b1[i]);
+        bb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (B0[i] + b1[i]);
 }
 
 // W_E = h/2 sum |E|^2 and W_B = c^2 h/2 sum |B|^2 (section 5.1) of LDS/global fields;
@@ -488,7 +615,7 @@ __device__ __forceinline__ void rotate_half(const double u[3], const double t[3]
     o[2] = (u[2] + (u[0] * t[1] - u[1] * t[0]) + ut * t[2]) * inv;
 }
 
-// tiles: es[ne][ng] predictor E, bs[2][ng] predictor B (EM)
+// tiles: es[ne][tw] predictor E, bs[2][tw] predictor B (EM), ghost-padded
 template <int ORDER, int NV, bool EM>
 __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x, const double v[NV],
                                                         const double *es, const double *bs)
@@ -496,20 +623,20 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
     Half<ORDER, NV, EM> o;
     const double xs = fma(r.hdt, v[0], x);
     const Stencil<ORDER> s = stencil<ORDER>(xs * r.inv_h);
-    const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
+    const Slots<ORDER> n = slots_of<ORDER>(s, r.ng);
     if constexpr (NV == 1) {
         o.vs[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
     } else {
         double u[3], t[3];
         u[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
         if constexpr (EM) {
-            u[1] = fma(r.hdt, gather1<ORDER>(es + r.ng, s, n), v[1]);
-            u[2] = fma(r.hdt, gather1<ORDER>(es + 2 * r.ng, s, n), v[2]);
+            u[1] = fma(r.hdt, gather1<ORDER>(es + r.tw, s, n), v[1]);
+            u[2] = fma(r.hdt, gather1<ORDER>(es + 2 * r.tw, s, n), v[2]);
             const Stencil<ORDER> sh = stencil<ORDER>(xs * r.inv_h - 0.5);
-            const Nodes<ORDER> nh = nodes_of<ORDER>(sh, r.ng);
+            const Slots<ORDER> nh = slots_of<ORDER>(sh, r.ng);
             t[0] = r.hdt * r.bext[0];
             t[1] = r.hdt * (r.bext[1] + gather1<ORDER>(bs, sh, nh));
-            t[2] = r.hdt * (r.bext[2] + gather1<ORDER>(bs + r.ng, sh, nh));
+            t[2] = r.hdt * (r.bext[2] + gather1<ORDER>(bs + r.tw, sh, nh));
         } else {
             u[1] = v[1];
             u[2] = v[2];
@@ -525,22 +652,23 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
 }
 
 // Pass A of step n (par = n & 1).
-// LDS: jt[ncur ng] | es[ne ng] | bs[nb ng]
-template <int ORDER, int NV, bool EM>
-__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_t step,
-                                                 const double *__restrict__ X,
-                                                 const double *__restrict__ V)
+// LDS: jt[ncur][tw] | es[ne][tw] | bs[nb][tw]
+// pass_a_body processes particles [p0, p1) of one run; `lead` marks the one workgroup
+// (per run and launch) that also clears the other predictor current and writes the record.
+template <int ORDER, int NV, bool EM, int DEP>
+__device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int par, int64_t step,
+                                            const double *__restrict__ X,
+                                            const double *__restrict__ V, int64_t p0,
+                                            int64_t p1, bool lead, double *smem, double *red)
 {
     using T = TileSizes<NV, EM>;
-    extern __shared__ double smem[];
-    __shared__ double red[16];
+    const int ng = r.ng, tw = r.tw;
     double *jt = smem;
-    double *es = jt + T::ncur * r.ng;
-    double *bs = es + T::ne * r.ng;
-    const int ng = r.ng;
+    double *es = jt + T::ncur * tw;
+    double *bs = es + T::ne * tw;
     predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red);
-    tile_zero(jt, T::ncur * ng);
-    if (blockIdx.x == 0) {
+    tile_zero(jt, T::ncur * tw);
+    if (lead) {
         // the predictor current of the next step accumulates into the other buffer
         if (r.scheme != 1)
             for (int i = threadIdx.x; i < T::ncur * ng; i += blockDim.x)
@@ -550,11 +678,15 @@ __global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_
             write_record(r, wk, step, red);
     }
     __syncthreads();
+    ghost_fill(es, T::ne, ng, tw);
+    if constexpr (EM)
+        ghost_fill(bs, T::nb, ng, tw);
+    __syncthreads();
 
-    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
+    Depo<ORDER, T::ncur, DEP> dep;
+    dep.init();
     for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollA<NV> * blockDim.x) {
-        // issue the loads of kUnroll particles before any arithmetic (memory-level
+        // issue the loads of kUnrollA particles before any arithmetic (memory-level
         // parallelism), then process them one by one
         double xr[kUnrollA<NV>], vr[kUnrollA<NV>][NV];
 #pragma unroll
@@ -564,7 +696,7 @@ __global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_
                 xr[u] = X[p];
 #pragma unroll
                 for (int c = 0; c < NV; ++c)
-                    vr[u][c] = V[c * r.np + p];
+                    vr[u][c] = V[c * r.vstride + p];
             }
         }
 #pragma unroll
@@ -574,37 +706,50 @@ __global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_
                 break;
             const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], vr[u], es, bs);
             const double q = (r.w ? r.w[p] : r.wu) * r.qs;
-            const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
-            const Nodes<ORDER> n = nodes_of<ORDER>(s, ng);
-            deposit1<ORDER>(jt, s, n, q * hs.vs[0]);
-            if constexpr (EM) {
-                deposit1<ORDER>(jt + ng, s, n, q * hs.vs[1]);
-                deposit1<ORDER>(jt + 2 * ng, s, n, q * hs.vs[2]);
-            }
+            double qv[T::ncur];
+#pragma unroll
+            for (int c = 0; c < T::ncur; ++c)
+                qv[c] = q * hs.vs[c];
+            dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv);
         }
     }
+    dep.finish(jt, tw, ng);
     __syncthreads();
-    tile_flush(jt, wk.J2[par], T::ncur * ng);
+    tile_flush(jt, wk.J2[par], T::ncur, ng, tw);
+}
+
+template <int ORDER, int NV, bool EM, int DEP>
+__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_t step,
+                                                 const double *__restrict__ X,
+                                                 const double *__restrict__ V)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, X, V, p0, min(r.np, p0 + r.chunk),
+                                    blockIdx.x == 0, smem, red);
 }
 
 // Pass B of step n (par = n & 1): new fields, second gather, Gamma, state write and
 // (PRED) the next step's predictor deposit.
-// LDS: jt[ncur ng] | es[ne ng] | bs[nb ng] | eb[ne ng] | bb[nb ng] | e1[ne ng] | b1[nb ng]
-//      | EM scratch[8 ng]
-template <int ORDER, int NV, bool EM, bool PRED>
-__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const double *X,
-                                                 const double *V, double *Xo, double *Vo)
+// LDS: jt[ncur][tw] | es[ne][tw] | bs[nb][tw] | eb[ne][tw] | bb[nb][tw] | e1[ne][ng] |
+//      b1[nb][ng] | EM scratch[8 ng]
+// pass_b_body processes particles [p0, p1) of one run and leaves its scalars in
+// spart[slot]; `lead` marks the workgroup that publishes the new fields of the run.
+template <int ORDER, int NV, bool EM, bool PRED, int DEP>
+__device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int par, const double *X,
+                                            const double *V, double *Xo, double *Vo,
+                                            int64_t p0, int64_t p1, bool lead, int slot,
+                                            double *smem, double *red)
 {
     using T = TileSizes<NV, EM>;
-    extern __shared__ double smem[];
-    __shared__ double red[16];
-    const int ng = r.ng;
+    const int ng = r.ng, tw = r.tw;
     double *jt = smem;
-    double *es = jt + T::ncur * ng;
-    double *bs = es + T::ne * ng;
-    double *eb = bs + T::nb * ng;
-    double *bb = eb + T::ne * ng;
-    double *e1 = bb + T::nb * ng;
+    double *es = jt + T::ncur * tw;
+    double *bs = es + T::ne * tw;
+    double *eb = bs + T::nb * tw;
+    double *bb = eb + T::ne * tw;
+    double *e1 = bb + T::nb * tw;
     double *b1 = e1 + T::ne * ng;
     double *scratch = b1 + T::nb * ng;
     const double *En = wk.Ef[par];
@@ -612,9 +757,15 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
     predictor_fields(r, En, Bn, wk.J1[par], es, bs, red);
     field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red);
     if constexpr (PRED)
-        tile_zero(jt, T::ncur * ng);
+        tile_zero(jt, T::ncur * tw);
     __syncthreads();
-    if (blockIdx.x == 0) {
+    ghost_fill(es, T::ne, ng, tw);
+    ghost_fill(eb, T::ne, ng, tw);
+    if constexpr (EM) {
+        ghost_fill(bs, T::nb, ng, tw);
+        ghost_fill(bb, T::nb, ng, tw);
+    }
+    if (lead) {
         // publish E^{n+1} (B^{n+1}) and their energies; clear the other centred current
         for (int i = threadIdx.x; i < T::ne * ng; i += blockDim.x)
             wk.Ef[par ^ 1][i] = e1[i];
@@ -630,11 +781,12 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
             wk.st->wb = wb;
         }
     }
+    __syncthreads();
 
+    Depo<ORDER, T::ncur, DEP> dep;
+    dep.init();
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
-    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
     for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollB<NV> * blockDim.x) {
         double xr[kUnrollB<NV>], vr[kUnrollB<NV>][NV];
 #pragma unroll
@@ -644,7 +796,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
                 xr[u] = X[p];
 #pragma unroll
                 for (int c = 0; c < NV; ++c)
-                    vr[u][c] = V[c * r.np + p];
+                    vr[u][c] = V[c * r.vstride + p];
             }
         }
 #pragma unroll
@@ -655,7 +807,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
             const double *v = vr[u];
             const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], v, es, bs);
             const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
-            const Nodes<ORDER> n = nodes_of<ORDER>(s, ng);
+            const Slots<ORDER> n = slots_of<ORDER>(s, ng);
             double vd[NV];
             if constexpr (NV == 1) {
                 vd[0] = fma(r.dt, gather1<ORDER>(eb, s, n), v[0]);
@@ -664,12 +816,12 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
                 e[0] = gather1<ORDER>(eb, s, n);
                 b[0] = r.bext[0];
                 if constexpr (EM) {
-                    e[1] = gather1<ORDER>(eb + ng, s, n);
-                    e[2] = gather1<ORDER>(eb + 2 * ng, s, n);
+                    e[1] = gather1<ORDER>(eb + tw, s, n);
+                    e[2] = gather1<ORDER>(eb + 2 * tw, s, n);
                     const Stencil<ORDER> sh = stencil<ORDER>(hs.xh * r.inv_h - 0.5);
-                    const Nodes<ORDER> nh = nodes_of<ORDER>(sh, ng);
+                    const Slots<ORDER> nh = slots_of<ORDER>(sh, ng);
                     b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
-                    b[2] = r.bext[2] + gather1<ORDER>(bb + ng, sh, nh);
+                    b[2] = r.bext[2] + gather1<ORDER>(bb + tw, sh, nh);
                 } else {
                     e[1] = 0.0;
                     e[2] = 0.0;
@@ -696,7 +848,7 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
             for (int c = 0; c < NV; ++c) {
                 vn[c] = g * vd[c];
                 v2 = fma(vn[c], vn[c], v2);
-                Vo[c * r.np + p] = vn[c];
+                Vo[c * r.vstride + p] = vn[c];
             }
             const double xw = wrap_pos(hs.x1, r.L);
             Xo[p] = xw;
@@ -706,37 +858,47 @@ __global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const 
                 nonfinite = 1;
             if constexpr (PRED) {
                 const double q = wp * r.qs;
-                const Stencil<ORDER> s2 = stencil<ORDER>((xw + r.hdt * vn[0]) * r.inv_h);
-                const Nodes<ORDER> n2 = nodes_of<ORDER>(s2, ng);
-                deposit1<ORDER>(jt, s2, n2, q * vn[0]);
-                if constexpr (EM) {
-                    deposit1<ORDER>(jt + ng, s2, n2, q * vn[1]);
-                    deposit1<ORDER>(jt + 2 * ng, s2, n2, q * vn[2]);
-                }
+                double qv[T::ncur];
+#pragma unroll
+                for (int c = 0; c < T::ncur; ++c)
+                    qv[c] = q * vn[c];
+                dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h), qv);
             }
         }
     }
+    if constexpr (PRED)
+        dep.finish(jt, tw, ng);
     const double bke = block_sum(ke, red);
     const double bgd = block_max(gdev, red);
     const double bfb = block_sum((double)fb, red);
     const double bnf = block_max((double)nonfinite, red);
     if (threadIdx.x == 0) {
-        wk.spart[blockIdx.x * kNS + 0] = 0.5 * bke;
-        wk.spart[blockIdx.x * kNS + 1] = bfb;
-        wk.spart[blockIdx.x * kNS + 2] = bgd;
-        wk.spart[blockIdx.x * kNS + 3] = bnf;
+        wk.spart[slot * kNS + 0] = 0.5 * bke;
+        wk.spart[slot * kNS + 1] = bfb;
+        wk.spart[slot * kNS + 2] = bgd;
+        wk.spart[slot * kNS + 3] = bnf;
     }
     if constexpr (PRED) {
         __syncthreads();
-        tile_flush(jt, wk.J1[par ^ 1], T::ncur * ng);
+        tile_flush(jt, wk.J1[par ^ 1], T::ncur, ng, tw);
     }
+}
+
+template <int ORDER, int NV, bool EM, bool PRED, int DEP>
+__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const double *X,
+                                                 const double *V, double *Xo, double *Vo)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, X, V, Xo, Vo, p0, min(r.np, p0 + r.chunk),
+                                          blockIdx.x == 0, blockIdx.x, smem, red);
 }
 
 // End of a pic_step call (one workgroup): the record of the newest state and a copy of
 // the newest fields into the caller's arrays.
-__global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_t step)
+__device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step, double *red)
 {
-    __shared__ double red[16];
     if (step > wk.st->recorded)
         write_record(r, wk, step, red);
     for (int i = threadIdx.x; i < 3 * r.ng; i += blockDim.x)
@@ -746,69 +908,223 @@ __global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_
             wk.B[i] = wk.Bf[par][i];
 }
 
+__global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_t step)
+{
+    __shared__ double red[16];
+    finish_body(r, wk, par, step, red);
+}
+
 // ------------------------------------------------------------------- initialisation
 // Predictor deposit of the initial state, w v^0 at x*_0 = x^0 + dt/2 v^0, into J1[0].
+template <int ORDER, int NV, bool EM>
+__device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
+                                                const double *__restrict__ X,
+                                                const double *__restrict__ V, int64_t p0,
+                                                int64_t p1, double *smem)
+{
+    using T = TileSizes<NV, EM>;
+    double *jt = smem;
+    tile_zero(jt, T::ncur * r.tw);
+    __syncthreads();
+    Depo<ORDER, T::ncur, 0> dep;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+        double qv[T::ncur];
+#pragma unroll
+        for (int c = 0; c < T::ncur; ++c)
+            qv[c] = q * V[c * r.vstride + p];
+        dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
+    }
+    __syncthreads();
+    tile_flush(jt, wk.J1[0], T::ncur, r.ng, r.tw);
+}
+
 template <int ORDER, int NV, bool EM>
 __global__ __launch_bounds__(1024) void k_predeposit(Run r, Work wk, const double *__restrict__ X,
                                                      const double *__restrict__ V)
 {
-    using T = TileSizes<NV, EM>;
     extern __shared__ double smem[];
-    double *jt = smem;
-    tile_zero(jt, T::ncur * r.ng);
-    __syncthreads();
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
-        const double vx = V[p];
-        const Stencil<ORDER> s = stencil<ORDER>((X[p] + r.hdt * vx) * r.inv_h);
-        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
-        deposit1<ORDER>(jt, s, n, q * vx);
-        if constexpr (EM) {
-            deposit1<ORDER>(jt + r.ng, s, n, q * V[r.np + p]);
-            deposit1<ORDER>(jt + 2 * r.ng, s, n, q * V[2 * r.np + p]);
-        }
-    }
-    __syncthreads();
-    tile_flush(jt, wk.J1[0], T::ncur * r.ng);
+    predeposit_body<ORDER, NV, EM>(r, wk, X, V, p0, min(r.np, p0 + r.chunk), smem);
 }
 
 // Charge deposit rho_i = (1/h) sum_p w_p S(x_i - x_p) into J2[0] (scratch for Gauss).
 template <int ORDER>
+__device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
+                                                 const double *__restrict__ X, int64_t p0,
+                                                 int64_t p1, double *smem)
+{
+    double *jt = smem;
+    tile_zero(jt, r.tw);
+    __syncthreads();
+    Depo<ORDER, 1, 0> dep;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double q[1] = {(r.w ? r.w[p] : r.wu) * r.qs};
+        dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
+    }
+    __syncthreads();
+    tile_flush(jt, wk.J2[0], 1, r.ng, r.tw);
+}
+
+template <int ORDER>
 __global__ __launch_bounds__(1024) void k_deposit_rho(Run r, Work wk, const double *__restrict__ X)
 {
     extern __shared__ double smem[];
-    double *jt = smem;
-    tile_zero(jt, r.ng);
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    deposit_rho_body<ORDER>(r, wk, X, p0, min(r.np, p0 + r.chunk), smem);
+}
+
+// ------------------------------------------------------------- counting-sort rebin
+// Particles are reordered by key = kVBins * cell + (v_x >= 0): particles of one cell and
+// one direction of motion become contiguous, so a wavefront's particles share a cell or
+// two for many steps (gathers become LDS broadcasts, deposits can be summed in registers
+// and the global tile flush touches few nodes).  Counting sort: per-workgroup histograms
+// (LDS), an exclusive scan of the [key][workgroup] counts, and a scatter in which each
+// workgroup places its particles at its own offsets (order inside a key and workgroup is
+// unspecified).
+__device__ __forceinline__ int sort_key(const Run &r, double x, double vx)
+{
+    const double cf = floor(x * r.inv_h);
+    const int c = (cf >= 0.0 && cf < (double)r.ng) ? (int)cf : (cf >= (double)r.ng ? r.ng - 1 : 0);
+    return kVBins * c + (vx >= 0.0 ? 1 : 0);
+}
+
+// hist[key * nblocks + b] = number of particles of workgroup b with that key.
+__global__ __launch_bounds__(1024) void k_rebin_count(Run r, Work wk, const double *__restrict__ X,
+                                                      const double *__restrict__ V)
+{
+    extern __shared__ int ihist[];
+    const int nbins = kVBins * r.ng;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        ihist[i] = 0;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+        atomicAdd(&ihist[sort_key(r, X[p], V[p])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        wk.hist[(int64_t)i * r.nblocks + blockIdx.x] = ihist[i];
+}
+
+// Exclusive scan of hist (length n) in three launches: per-segment sums, a scan of the
+// segment sums (one workgroup), and the per-segment rescans.
+__global__ __launch_bounds__(1024) void k_scan_sums(const int64_t *a, int64_t n, int64_t seg,
+                                                    int64_t *segsum)
+{
+    __shared__ double red[16];
+    const int64_t s0 = (int64_t)blockIdx.x * seg, s1 = min(n, s0 + seg);
+    double acc = 0.0;     // counts are exact in double below 2^53
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x)
+        acc += (double)a[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0)
+        segsum[blockIdx.x] = (int64_t)acc;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *segsum, int nseg)
+{
+    // nseg <= blockDim: one value per thread, Hillis-Steele in LDS
+    __shared__ int64_t buf[1024];
+    const int t = threadIdx.x;
+    const int64_t mine = t < nseg ? segsum[t] : 0;
+    buf[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int64_t add = t >= off ? buf[t - off] : 0;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    if (t < nseg)
+        segsum[t] = buf[t] - mine;     // exclusive
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(int64_t *a, int64_t n, int64_t seg,
+                                                     const int64_t *segsum)
+{
+    // in-place exclusive scan of one segment, processed in chunks of blockDim elements
+    __shared__ int64_t buf[1024];
+    const int t = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * seg, s1 = min(n, s0 + seg);
+    int64_t carry = segsum[blockIdx.x];
+    for (int64_t c0 = s0; c0 < s1; c0 += blockDim.x) {
+        const int64_t i = c0 + t;
+        const int64_t mine = i < s1 ? a[i] : 0;
+        buf[t] = mine;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int64_t add = t >= off ? buf[t - off] : 0;
+            __syncthreads();
+            buf[t] += add;
+            __syncthreads();
+        }
+        if (i < s1)
+            a[i] = carry + buf[t] - mine;
+        const int64_t total = buf[blockDim.x - 1];
+        __syncthreads();
+        carry += total;
+    }
+}
+
+// Scatter the state (and ids, weights) of each workgroup's particles to their sorted
+// positions in the second buffers.
+template <int NV>
+__global__ __launch_bounds__(1024) void k_rebin_scatter(Run r, Work wk, const double *__restrict__ X,
+                                                        const double *__restrict__ V,
+                                                        const int64_t *__restrict__ ID)
+{
+    extern __shared__ int64_t cursor[];
+    const int nbins = kVBins * r.ng;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        cursor[i] = wk.hist[(int64_t)i * r.nblocks + blockIdx.x];
     __syncthreads();
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const Stencil<ORDER> s = stencil<ORDER>(X[p] * r.inv_h);
-        const Nodes<ORDER> n = nodes_of<ORDER>(s, r.ng);
-        deposit1<ORDER>(jt, s, n, (r.w ? r.w[p] : r.wu) * r.qs);
+        const double x = X[p];
+        const int key = sort_key(r, x, V[p]);
+        const int64_t d = (int64_t)atomicAdd((unsigned long long *)&cursor[key], 1ull);
+        wk.x2[d] = x;
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            wk.v2[c * r.np + d] = V[c * r.vstride + p];
+        if (ID)
+            wk.id2[d] = ID[p];
+        if (wk.wcur)
+            wk.w2[d] = wk.wcur[p];
     }
-    __syncthreads();
-    tile_flush(jt, wk.J2[0], r.ng);
+}
+
+__global__ void k_copy_i64(int64_t *dst, const int64_t *src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_copy_f64(double *dst, const double *src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // Wrap positions into [0, L); the initial kinetic energy and non-finite flag go to
-// spart like the scalars of a pass B.
+// spart[slot] like the scalars of a pass B.
 template <int NV>
-__global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double *__restrict__ X,
-                                                         const double *__restrict__ V)
+__device__ __forceinline__ void init_particles_body(const Run &r, const Work &wk,
+                                                    double *__restrict__ X,
+                                                    const double *__restrict__ V, int64_t p0,
+                                                    int64_t p1, int slot, double *red)
 {
-    __shared__ double red[16];
     double ke = 0.0;
     int nonfinite = 0;
-    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         double v2 = 0.0;
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
-            const double vc = V[c * r.np + p];
+            const double vc = V[c * r.vstride + p];
             v2 += vc * vc;
         }
         const double x = X[p];
@@ -820,19 +1136,27 @@ __global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double 
     const double bke = block_sum(ke, red);
     const double bnf = block_max((double)nonfinite, red);
     if (threadIdx.x == 0) {
-        wk.spart[blockIdx.x * kNS + 0] = 0.5 * bke;
-        wk.spart[blockIdx.x * kNS + 1] = 0.0;
-        wk.spart[blockIdx.x * kNS + 2] = 0.0;
-        wk.spart[blockIdx.x * kNS + 3] = bnf;
+        wk.spart[slot * kNS + 0] = 0.5 * bke;
+        wk.spart[slot * kNS + 1] = 0.0;
+        wk.spart[slot * kNS + 2] = 0.0;
+        wk.spart[slot * kNS + 3] = bnf;
     }
+}
+
+template <int NV>
+__global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double *__restrict__ X,
+                                                         const double *__restrict__ V)
+{
+    __shared__ double red[16];
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    init_particles_body<NV>(r, wk, X, V, p0, min(r.np, p0 + r.chunk), blockIdx.x, red);
 }
 
 // Initial Gauss solve: dE/dx = rho - 1 with rho in J2[0], into the caller's E_x.
 // Spectrally on the nodes: E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2, mean
 // and Nyquist modes zero (the Poisson form, eq. (poisson), in 1D).
-__global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
+__device__ void gauss_body(const Run &r, const Work &wk, double *smem)
 {
-    extern __shared__ double smem[];
     const int ng = r.ng;
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
     tile_load(rho, wk.J2[0], ng);
@@ -869,9 +1193,15 @@ __global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
     }
 }
 
+__global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
+{
+    extern __shared__ double smem[];
+    gauss_body(r, wk, smem);
+}
+
 // First row of (I - s L_h)^{-1} for the periodic 3-point Laplacian: circulant, so
 // g_k = (1/N) sum_m cos(2 pi m k / N) / (1 + s (4/h^2) sin^2(pi m / N)).
-__global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk)
+__device__ void cn_init_body(const Run &r, const Work &wk)
 {
     const int ng = r.ng;
     const double s = r.hdt * r.hdt * r.c2;
@@ -887,10 +1217,11 @@ __global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk)
     }
 }
 
+__global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk) { cn_init_body(r, wk); }
+
 // Initial fields into the parity-0 buffers and the record of step 0 (one workgroup).
-__global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
+__device__ void init_finish_body(const Run &r, const Work &wk, double *red)
 {
-    __shared__ double red[16];
     const int ng = r.ng;
     for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
         wk.Ef[0][i] = wk.E[i];
@@ -911,11 +1242,171 @@ __global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
     write_record(r, wk, 0, red);
 }
 
+__global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
+{
+    __shared__ double red[16];
+    init_finish_body(r, wk, red);
+}
+
 __global__ void k_fill(double *p, int64_t n, double v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// ----------------------------------------------------------------- batched ensemble
+// Many independent runs (different N_p, N_g, L) advanced together.  Particles of all
+// runs are packed in one structure of arrays; each run keeps its own fields, currents,
+// state and records.  The work is a table of items, each a chunk of one run's
+// particles (chunks of a run are consecutive; the first is the run's lead).  Every pass
+// is ONE launch of a persistent grid whose workgroups stride over the table, so runs of
+// very different sizes load-balance; the step number is read from a device counter so
+// that a captured graph of several steps can be replayed unchanged.
+struct BatchRun {
+    Run r;                 // scalars; r.nblocks = items of this run, r.vstride = packed N
+    Work wk;               // this run's arrays (spart points at its first item's slot)
+    int64_t poff;          // first particle of the run in the packed arrays
+};
+
+struct BatchItem {
+    int32_t run;
+    int32_t slot;          // chunk index within the run (0 = lead)
+    int64_t p0, p1;        // run-local particle range
+};
+
+struct Batch {
+    const BatchRun *runs;
+    const BatchItem *items;
+    int32_t nitems, nruns;
+    double *X, *V;         // packed particle arrays
+    int64_t *stepc;        // steps completed (device counter)
+};
+
+template <int ORDER, int NV, bool EM, int DEP>
+__global__ __launch_bounds__(1024) void k_batch_pass_a(Batch b)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int64_t step = *b.stepc;
+    const int par = (int)(step & 1);
+    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+        const BatchItem item = b.items[it];
+        const BatchRun &br = b.runs[item.run];
+        const Run r = br.r;
+        const Work wk = br.wk;
+        pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, b.X + br.poff, b.V + br.poff, item.p0,
+                                        item.p1, item.slot == 0, smem, red);
+        __syncthreads();
+    }
+}
+
+template <int ORDER, int NV, bool EM, bool PRED, int DEP>
+__global__ __launch_bounds__(1024) void k_batch_pass_b(Batch b)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int par = (int)(*b.stepc & 1);
+    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+        const BatchItem item = b.items[it];
+        const BatchRun &br = b.runs[item.run];
+        const Run r = br.r;
+        const Work wk = br.wk;
+        pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, b.X + br.poff, b.V + br.poff,
+                                              b.X + br.poff, b.V + br.poff, item.p0, item.p1,
+                                              item.slot == 0, item.slot, smem, red);
+        __syncthreads();
+    }
+}
+
+// Advance the step counter (one thread, after both passes of a step).
+__global__ void k_batch_tick(Batch b)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *b.stepc += 1;
+}
+
+// One workgroup per run: newest record and fields into the caller's arrays.
+__global__ __launch_bounds__(1024) void k_batch_finish(Batch b)
+{
+    __shared__ double red[16];
+    const int64_t step = *b.stepc;
+    const BatchRun &br = b.runs[blockIdx.x];
+    const Run r = br.r;
+    const Work wk = br.wk;
+    finish_body(r, wk, (int)(step & 1), step, red);
+}
+
+template <int NV>
+__global__ __launch_bounds__(1024) void k_batch_init_particles(Batch b)
+{
+    __shared__ double red[16];
+    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+        const BatchItem item = b.items[it];
+        const BatchRun &br = b.runs[item.run];
+        const Run r = br.r;
+        const Work wk = br.wk;
+        init_particles_body<NV>(r, wk, b.X + br.poff, b.V + br.poff, item.p0, item.p1, item.slot,
+                                red);
+        __syncthreads();
+    }
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(1024) void k_batch_deposit_rho(Batch b)
+{
+    extern __shared__ double smem[];
+    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+        const BatchItem item = b.items[it];
+        const BatchRun &br = b.runs[item.run];
+        const Run r = br.r;
+        const Work wk = br.wk;
+        deposit_rho_body<ORDER>(r, wk, b.X + br.poff, item.p0, item.p1, smem);
+        __syncthreads();
+    }
+}
+
+template <int ORDER, int NV, bool EM>
+__global__ __launch_bounds__(1024) void k_batch_predeposit(Batch b)
+{
+    extern __shared__ double smem[];
+    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+        const BatchItem item = b.items[it];
+        const BatchRun &br = b.runs[item.run];
+        const Run r = br.r;
+        const Work wk = br.wk;
+        predeposit_body<ORDER, NV, EM>(r, wk, b.X + br.poff, b.V + br.poff, item.p0, item.p1, smem);
+        __syncthreads();
+    }
+}
+
+// One workgroup per run.
+__global__ __launch_bounds__(1024) void k_batch_gauss(Batch b)
+{
+    extern __shared__ double smem[];
+    const BatchRun &br = b.runs[blockIdx.x];
+    const Run r = br.r;
+    const Work wk = br.wk;
+    gauss_body(r, wk, smem);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_cn_init(Batch b)
+{
+    const BatchRun &br = b.runs[blockIdx.x];
+    const Run r = br.r;
+    const Work wk = br.wk;
+    cn_init_body(r, wk);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_init_finish(Batch b)
+{
+    __shared__ double red[16];
+    const BatchRun &br = b.runs[blockIdx.x];
+    const Run r = br.r;
+    const Work wk = br.wk;
+    init_finish_body(r, wk, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *b.stepc = 0;
 }
 
 }  // namespace pic

@@ -20,7 +20,10 @@ namespace {
 
 thread_local std::string g_last_error;
 
-constexpr int kDefaultThreads = 256;
+constexpr int kDefaultThreads = 512;
+// Default grid cap: two workgroups per CU; more workgroups only add prologue work and
+// global flushes of the per-workgroup current tiles.
+constexpr int kDefaultGrid = 512;
 constexpr int kDefaultRecords = 4096;
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
@@ -28,7 +31,9 @@ constexpr size_t kMaxLds = 64 * 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, st, rec, total;
+    size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, st, rec;
+    size_t x2, v2, id2, wcur, w2, hist, segsum;     // rebin (0 when unused)
+    size_t total;
 };
 
 int threads_of(const pic_params *p) { return p->block_threads ? p->block_threads : kDefaultThreads; }
@@ -38,7 +43,7 @@ int records_of(const pic_params *p) { return p->record_capacity ? p->record_capa
 int blocks_of(const pic_params *p, int64_t *chunk_out)
 {
     const int t = threads_of(p);
-    int64_t nb = p->grid_blocks ? p->grid_blocks : std::min<int64_t>((p->n_particles + t - 1) / t, 1024);
+    int64_t nb = p->grid_blocks ? p->grid_blocks : std::min<int64_t>((p->n_particles + t - 1) / t, kDefaultGrid);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid));
     // chunks are whole multiples of the batch a workgroup loads at once (4 particles
     // per thread), so only the last workgroup has a ragged tail
@@ -53,23 +58,49 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
 bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI; }
 
 // LDS bytes of the largest kernel of this configuration.
+size_t tile_width(const pic_params *p) { return (size_t)p->n_cells + 2 * kGhost; }
+
 size_t lds_pass_a(const pic_params *p)
 {
-    // jt | es | bs
-    const size_t ng = p->n_cells;
-    return is_em(p) ? (3 + 3 + 2) * ng * 8 : 2 * ng * 8;
+    // jt | es | bs   (ghost-padded tiles)
+    const size_t tw = tile_width(p);
+    return is_em(p) ? (3 + 3 + 2) * tw * 8 : 2 * tw * 8;
 }
 
 size_t lds_pass_b(const pic_params *p)
 {
-    // jt | es | bs | eb | bb | e1 | b1 | (EM) Crank-Nicolson scratch
-    const size_t ng = p->n_cells;
-    return is_em(p) ? (3 + 3 + 2 + 3 + 2 + 3 + 2 + 8) * ng * 8 : 4 * ng * 8;
+    // jt | es | bs | eb | bb (padded) | e1 | b1 | (EM) Crank-Nicolson scratch
+    const size_t tw = tile_width(p), ng = p->n_cells;
+    return is_em(p) ? (3 + 3 + 2 + 3 + 2) * tw * 8 + (3 + 2 + 8) * ng * 8 : 3 * tw * 8 + ng * 8;
 }
+
+size_t lds_rebin(const pic_params *p) { return (size_t)kVBins * p->n_cells * 8; }
 
 size_t lds_need(const pic_params *p)
 {
-    return std::max(std::max(lds_pass_a(p), lds_pass_b(p)), (size_t)3 * p->n_cells * 8);
+    size_t m = std::max(lds_pass_a(p), lds_pass_b(p));
+    m = std::max(m, (size_t)3 * p->n_cells * 8);
+    if (p->rebin_every > 0)
+        m = std::max(m, lds_rebin(p));
+    return m;
+}
+
+int64_t rebin_len(const pic_params *p) { return (int64_t)kVBins * p->n_cells * blocks_of(p, nullptr); }
+
+void scan_shape(int64_t n, int *nseg, int64_t *seg)
+{
+    int64_t ns = std::min<int64_t>(1024, std::max<int64_t>(1, (n + 2047) / 2048));
+    *seg = (n + ns - 1) / ns;
+    *nseg = (int)((n + *seg - 1) / *seg);
+}
+
+int deposit_kind(const pic_params *p)
+{
+    if (p->deposit_mode == PIC_DEPOSIT_LDS_ATOMIC)
+        return 0;
+    if (p->deposit_mode == PIC_DEPOSIT_WINDOW)
+        return 1;
+    return p->rebin_every > 0 ? 1 : 0;
 }
 
 Layout layout_of(const pic_params *p)
@@ -88,6 +119,21 @@ Layout layout_of(const pic_params *p)
     L.spart = take((size_t)blocks_of(p, nullptr) * kNS * 8);
     L.st = take(sizeof(DevState));
     L.rec = take((size_t)records_of(p) * sizeof(DevRecord));
+    L.x2 = L.v2 = L.id2 = L.wcur = L.w2 = L.hist = L.segsum = 0;
+    if (p->rebin_every > 0) {
+        const size_t np = (size_t)p->n_particles;
+        L.x2 = take(np * 8);
+        L.v2 = take(np * 8 * (size_t)p->nv);
+        if (p->flags & PIC_F_TRACK_IDS)
+            L.id2 = take(np * 8);
+        L.wcur = take(np * 8);      // used only with non-uniform weights
+        L.w2 = take(np * 8);
+        L.hist = take((size_t)rebin_len(p) * 8);
+        int nseg;
+        int64_t seg;
+        scan_shape(rebin_len(p), &nseg, &seg);
+        L.segsum = take((size_t)nseg * 8);
+    }
     L.total = o;
     return L;
 }
@@ -139,15 +185,13 @@ int validate(const pic_params *p, std::string *err)
             return fail(err, PIC_EINVAL, "b_ext must be finite");
     if (p->rebin_every < 0)
         return fail(err, PIC_EINVAL, "rebin_every must be >= 0");
-    if (p->rebin_every > 0)
-        return fail(err, PIC_EUNSUPPORTED, "rebin_every > 0 is not available in this build");
     if (p->flags & ~(uint32_t)(PIC_F_INIT_GAUSS | PIC_F_TRACK_IDS))
         return fail(err, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
     if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > 1024))
         return fail(err, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (p->grid_blocks < 0 || p->grid_blocks > kMaxGrid)
         return fail(err, PIC_EINVAL, "grid_blocks must be in [0, %d]", kMaxGrid);
-    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_WAVE_REDUCE)
+    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_WINDOW)
         return fail(err, PIC_EINVAL, "unknown deposit_mode %d", p->deposit_mode);
     if (p->record_capacity < 0)
         return fail(err, PIC_EINVAL, "record_capacity must be >= 0");
@@ -187,50 +231,49 @@ namespace {
 // kind: 0 = 1D-1V electrostatic, 1 = 1D-3V electrostatic, 2 = 1D-3V electromagnetic
 int kind_of(const pic_params *p) { return is_em(p) ? 2 : (p->nv == 3 ? 1 : 0); }
 
-template <int ORDER, int NV, bool EM>
-void launch_a(pic_ctx *c, int par, int64_t step)
+template <int ORDER, int NV, bool EM, int DEP>
+void launch_a(pic_ctx *c, int par, int64_t step, const double *X, const double *V)
 {
-    hipLaunchKernelGGL((k_pass_a<ORDER, NV, EM>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_a(&c->p), c->stream, c->run, c->wk, par, step, c->b.x, c->b.v);
+    hipLaunchKernelGGL((k_pass_a<ORDER, NV, EM, DEP>), dim3(c->run.nblocks), dim3(c->threads),
+                       lds_pass_a(&c->p), c->stream, c->run, c->wk, par, step, X, V);
 }
 
-template <int ORDER, int NV, bool EM, bool PRED>
-void launch_b(pic_ctx *c, int par)
+template <int ORDER, int NV, bool EM, bool PRED, int DEP>
+void launch_b(pic_ctx *c, int par, const double *X, const double *V)
 {
-    hipLaunchKernelGGL((k_pass_b<ORDER, NV, EM, PRED>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_b(&c->p), c->stream, c->run, c->wk, par, c->b.x, c->b.v, c->b.x,
-                       c->b.v);
+    hipLaunchKernelGGL((k_pass_b<ORDER, NV, EM, PRED, DEP>), dim3(c->run.nblocks), dim3(c->threads),
+                       lds_pass_b(&c->p), c->stream, c->run, c->wk, par, X, V, c->b.x, c->b.v);
 }
 
 template <int ORDER, int NV, bool EM>
 void launch_pre(pic_ctx *c)
 {
     hipLaunchKernelGGL((k_predeposit<ORDER, NV, EM>), dim3(c->run.nblocks), dim3(c->threads),
-                       (EM ? 3 : 1) * c->p.n_cells * 8, c->stream, c->run, c->wk, c->b.x, c->b.v);
+                       (EM ? 3 : 1) * tile_width(&c->p) * 8, c->stream, c->run, c->wk, c->b.x, c->b.v);
 }
 
 enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO };
 
-template <int ORDER>
-void dispatch_order(pic_ctx *c, int what, int par, int64_t step)
+template <int ORDER, int DEP>
+void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
     const int kind = kind_of(&c->p);
     const bool pred = c->p.scheme != PIC_ESEC1;
     switch (what) {
     case D_PASS_A:
-        if (kind == 0) launch_a<ORDER, 1, false>(c, par, step);
-        else if (kind == 1) launch_a<ORDER, 3, false>(c, par, step);
-        else launch_a<ORDER, 3, true>(c, par, step);
+        if (kind == 0) launch_a<ORDER, 1, false, DEP>(c, par, step, X, V);
+        else if (kind == 1) launch_a<ORDER, 3, false, DEP>(c, par, step, X, V);
+        else launch_a<ORDER, 3, true, DEP>(c, par, step, X, V);
         break;
     case D_PASS_B:
         if (kind == 0) {
-            if (pred) launch_b<ORDER, 1, false, true>(c, par);
-            else launch_b<ORDER, 1, false, false>(c, par);
+            if (pred) launch_b<ORDER, 1, false, true, DEP>(c, par, X, V);
+            else launch_b<ORDER, 1, false, false, DEP>(c, par, X, V);
         } else if (kind == 1) {
-            if (pred) launch_b<ORDER, 3, false, true>(c, par);
-            else launch_b<ORDER, 3, false, false>(c, par);
+            if (pred) launch_b<ORDER, 3, false, true, DEP>(c, par, X, V);
+            else launch_b<ORDER, 3, false, false, DEP>(c, par, X, V);
         } else {
-            launch_b<ORDER, 3, true, true>(c, par);
+            launch_b<ORDER, 3, true, true, DEP>(c, par, X, V);
         }
         break;
     case D_PREDEPOSIT:
@@ -240,17 +283,60 @@ void dispatch_order(pic_ctx *c, int what, int par, int64_t step)
         break;
     case D_RHO:
         hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(c->run.nblocks), dim3(c->threads),
-                           c->p.n_cells * 8, c->stream, c->run, c->wk, c->b.x);
+                           tile_width(&c->p) * 8, c->stream, c->run, c->wk, c->b.x);
         break;
     }
 }
 
-void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0)
+template <int ORDER>
+void dispatch_order(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
-    if (c->p.shape_order == 1)
-        dispatch_order<1>(c, what, par, step);
+    if (deposit_kind(&c->p))
+        dispatch_dep<ORDER, 1>(c, what, par, step, X, V);
     else
-        dispatch_order<2>(c, what, par, step);
+        dispatch_dep<ORDER, 0>(c, what, par, step, X, V);
+}
+
+void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0, const double *X = nullptr,
+              const double *V = nullptr)
+{
+    if (!X) {
+        X = c->b.x;
+        V = c->b.v;
+    }
+    if (c->p.shape_order == 1)
+        dispatch_order<1>(c, what, par, step, X, V);
+    else
+        dispatch_order<2>(c, what, par, step, X, V);
+}
+
+// Counting-sort rebin of the caller's state into the second buffers (x2, v2, id2, w2);
+// ids and weights are copied back at once, x and v are copied back by the next pass B.
+void rebin(pic_ctx *c)
+{
+    const int64_t n = rebin_len(&c->p);
+    int nseg;
+    int64_t seg;
+    scan_shape(n, &nseg, &seg);
+    const Run &r = c->run;
+    const Work &w = c->wk;
+    hipLaunchKernelGGL(k_rebin_count, dim3(r.nblocks), dim3(c->threads), lds_rebin(&c->p) / 2, c->stream,
+                       r, w, c->b.x, c->b.v);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(256), 0, c->stream, w.hist, n, seg, w.segsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, w.segsum, nseg);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nseg), dim3(256), 0, c->stream, w.hist, n, seg, w.segsum);
+    const int64_t *ids = (c->p.flags & PIC_F_TRACK_IDS) ? c->b.id : nullptr;
+    if (c->p.nv == 1)
+        hipLaunchKernelGGL((k_rebin_scatter<1>), dim3(r.nblocks), dim3(c->threads), lds_rebin(&c->p), c->stream,
+                           r, w, c->b.x, c->b.v, ids);
+    else
+        hipLaunchKernelGGL((k_rebin_scatter<3>), dim3(r.nblocks), dim3(c->threads), lds_rebin(&c->p), c->stream,
+                           r, w, c->b.x, c->b.v, ids);
+    const unsigned g = (unsigned)std::min<int64_t>((r.np + 255) / 256, 4096);
+    if (ids)
+        hipLaunchKernelGGL(k_copy_i64, dim3(g), dim3(256), 0, c->stream, c->b.id, w.id2, r.np);
+    if (w.wcur)
+        hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, c->stream, w.wcur, w.w2, r.np);
 }
 
 int grid_threads(const pic_ctx *c)
@@ -323,6 +409,12 @@ void collect(pic_ctx *c)
     c->timed.clear();
 }
 
+void fill_range(hipStream_t stream, double *p, int64_t n)
+{
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0,
+                       stream, p, n, 0.0);
+}
+
 void fill(pic_ctx *c, double *p, int64_t n, double v)
 {
     hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0,
@@ -379,11 +471,12 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
 
     Run &r = c->run;
     r.np = p->n_particles;
+    r.vstride = p->n_particles;
     r.ng = p->n_cells;
     r.nv = p->nv;
     r.nblocks = blocks_of(p, &r.chunk);
     r.scheme = p->scheme;
-    r.pad = 0;
+    r.tw = (int32_t)tile_width(p);
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -411,6 +504,19 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     w.spart = (double *)(ws + L.spart);
     w.st = (DevState *)(ws + L.st);
     w.rec = (DevRecord *)(ws + L.rec);
+    const bool rb = p->rebin_every > 0;
+    w.x2 = rb ? (double *)(ws + L.x2) : nullptr;
+    w.v2 = rb ? (double *)(ws + L.v2) : nullptr;
+    w.id2 = (rb && (p->flags & PIC_F_TRACK_IDS)) ? (int64_t *)(ws + L.id2) : nullptr;
+    w.wcur = (rb && b->w) ? (double *)(ws + L.wcur) : nullptr;
+    w.w2 = (rb && b->w) ? (double *)(ws + L.w2) : nullptr;
+    w.hist = rb ? (int64_t *)(ws + L.hist) : nullptr;
+    w.segsum = rb ? (int64_t *)(ws + L.segsum) : nullptr;
+    if (w.wcur) {
+        // the library permutes its own copy of the weights
+        hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, c->stream, w.wcur, b->w, r.np);
+        r.w = w.wcur;
+    }
 
     // clear the field and current buffers (fill kernels, no memset)
     fill(c, w.Ef[0], (int64_t)(L.cninv - L.Ef[0]) / 8, 0.0);
@@ -450,16 +556,25 @@ int pic_step(pic_ctx *c, int64_t n_steps)
         return PIC_ESTATE;
     if (n_steps < 0)
         return fail(&c->err, PIC_EINVAL, "n_steps must be >= 0");
+    const int K = c->p.rebin_every;
     for (int64_t s = 0; s < n_steps; ++s) {
         const int64_t n = c->steps_done;
         const int par = (int)(n & 1);
+        // after a rebin this step reads the sorted copy; pass B writes the caller's arrays
+        const double *X = c->b.x, *V = c->b.v;
+        if (K > 0 && n % K == 0) {
+            Timer t(c, PIC_K_REBIN);
+            rebin(c);
+            X = c->wk.x2;
+            V = c->wk.v2;
+        }
         {
             Timer t(c, PIC_K_PASS_A);
-            dispatch(c, D_PASS_A, par, n);
+            dispatch(c, D_PASS_A, par, n, X, V);
         }
         {
             Timer t(c, PIC_K_PASS_B);
-            dispatch(c, D_PASS_B, par, n);
+            dispatch(c, D_PASS_B, par, n, X, V);
         }
         c->steps_done = n + 1;
         if (c->profiling && c->timed.size() > 4096) {
@@ -517,6 +632,20 @@ int pic_sync_state(pic_ctx *c)
         return PIC_ESTATE;
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return check(c, "pic_sync_state");
+    return PIC_OK;
+}
+
+int pic_launch_shape(const pic_ctx *c, int32_t *block_threads, int32_t *grid_blocks,
+                     int64_t *chunk)
+{
+    if (!c)
+        return PIC_ESTATE;
+    if (block_threads)
+        *block_threads = c->threads;
+    if (grid_blocks)
+        *grid_blocks = c->run.nblocks;
+    if (chunk)
+        *chunk = c->run.chunk;
     return PIC_OK;
 }
 
@@ -587,6 +716,439 @@ const char *pic_last_error(const pic_ctx *c)
     if (c)
         return c->err.c_str();
     return g_last_error.c_str();
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// Batched ensemble form
+// =====================================================================================
+namespace {
+
+constexpr int kBatchDefaultRecords = 1024;
+
+struct BatchLayout {
+    std::vector<size_t> Ef0, Ef1, Bf0, Bf1, J10, J11, J20, J21, cninv;
+    size_t spart, st, rec, runs, items, stepc, total;
+    int nitems;
+};
+
+int batch_threads(const pic_batch_params *p) { return p->block_threads ? p->block_threads : 256; }
+
+int batch_chunk(const pic_batch_params *p)
+{
+    return p->chunk ? p->chunk : 16 * batch_threads(p);
+}
+
+int batch_records(const pic_batch_params *p)
+{
+    return p->record_capacity ? p->record_capacity : kBatchDefaultRecords;
+}
+
+// The per-run parameters as a single-run pic_params (for validation and LDS sizing).
+pic_params run_params(const pic_batch_params *p, int r)
+{
+    pic_params q;
+    std::memset(&q, 0, sizeof q);
+    q.abi_version = PIC_ABI_VERSION;
+    q.nv = p->nv;
+    q.scheme = p->scheme;
+    q.shape_order = p->shape_order;
+    q.n_particles = p->n_particles[r];
+    q.n_cells = p->n_cells[r];
+    q.length = p->length[r];
+    q.dt = p->dt;
+    q.c = p->c;
+    for (int i = 0; i < 3; ++i)
+        q.b_ext[i] = p->b_ext[i];
+    q.block_threads = p->block_threads;
+    return q;
+}
+
+int batch_validate(const pic_batch_params *p)
+{
+    if (!p)
+        return fail(nullptr, PIC_EINVAL, "params is NULL");
+    if (p->abi_version != PIC_ABI_VERSION)
+        return fail(nullptr, PIC_EINVAL, "abi_version %d != %d", p->abi_version, PIC_ABI_VERSION);
+    if (p->n_runs < 1 || !p->n_particles || !p->n_cells || !p->length)
+        return fail(nullptr, PIC_EINVAL, "n_runs >= 1 and the per-run arrays are required");
+    if (p->flags & ~(uint32_t)PIC_BF_INIT_GAUSS)
+        return fail(nullptr, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > 1024))
+        return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+    if (p->chunk < 0 || p->chunk % batch_threads(p))
+        return fail(nullptr, PIC_EINVAL, "chunk must be 0 or a positive multiple of block_threads");
+    if (p->grid_blocks < 0 || p->graph_steps < 0 || p->record_capacity < 0 || p->reserved)
+        return fail(nullptr, PIC_EINVAL, "grid_blocks, graph_steps, record_capacity >= 0, reserved 0");
+    int64_t items = 0;
+    for (int r = 0; r < p->n_runs; ++r) {
+        pic_params q = run_params(p, r);
+        const int rc = validate(&q, nullptr);
+        if (rc != PIC_OK)
+            return fail(nullptr, rc, "run %d: %s", r, g_last_error.c_str());
+        items += (q.n_particles + batch_chunk(p) - 1) / batch_chunk(p);
+    }
+    if (items > (int64_t)1 << 30)
+        return fail(nullptr, PIC_EUNSUPPORTED, "too many work items");
+    return PIC_OK;
+}
+
+BatchLayout batch_layout(const pic_batch_params *p)
+{
+    BatchLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, kAlign); return at; };
+    L.nitems = 0;
+    for (int r = 0; r < p->n_runs; ++r) {
+        const size_t ng = (size_t)p->n_cells[r];
+        L.Ef0.push_back(take(3 * ng * 8));
+        L.Ef1.push_back(take(3 * ng * 8));
+        L.Bf0.push_back(take(2 * ng * 8));
+        L.Bf1.push_back(take(2 * ng * 8));
+        L.J10.push_back(take(3 * ng * 8));
+        L.J11.push_back(take(3 * ng * 8));
+        L.J20.push_back(take(3 * ng * 8));
+        L.J21.push_back(take(3 * ng * 8));
+        L.cninv.push_back(take(ng * 8));
+        L.nitems += (int)((p->n_particles[r] + batch_chunk(p) - 1) / batch_chunk(p));
+    }
+    L.spart = take((size_t)L.nitems * kNS * 8);
+    L.st = take((size_t)p->n_runs * sizeof(DevState));
+    L.rec = take((size_t)p->n_runs * batch_records(p) * sizeof(DevRecord));
+    L.runs = take((size_t)p->n_runs * sizeof(BatchRun));
+    L.items = take((size_t)L.nitems * sizeof(BatchItem));
+    L.stepc = take(8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct pic_batch {
+    pic_batch_params p;
+    std::vector<int64_t> np;
+    std::vector<int32_t> ng;
+    std::vector<double> len;
+    pic_batch_buffers b;
+    hipStream_t stream;
+    Batch bt;
+    int threads, grid, kind;
+    size_t lds_a, lds_b, lds_dep, lds_gauss;
+    int64_t steps_done;
+    std::vector<int64_t> records_read;
+    std::vector<DevState *> st;
+    std::vector<DevRecord *> rec;
+    int rec_cap;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int poisoned;
+    std::string err;
+};
+
+namespace {
+
+int batch_check(pic_batch *c, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->poisoned = 1;
+        return fail(&c->err, PIC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+template <int ORDER, int NV, bool EM>
+void batch_step_kind(pic_batch *c)
+{
+    const bool pred = c->p.scheme != PIC_ESEC1;
+    hipLaunchKernelGGL((k_batch_pass_a<ORDER, NV, EM, 0>), dim3(c->grid), dim3(c->threads), c->lds_a,
+                       c->stream, c->bt);
+    if (pred)
+        hipLaunchKernelGGL((k_batch_pass_b<ORDER, NV, EM, true, 0>), dim3(c->grid), dim3(c->threads),
+                           c->lds_b, c->stream, c->bt);
+    else
+        hipLaunchKernelGGL((k_batch_pass_b<ORDER, NV, EM, false, 0>), dim3(c->grid), dim3(c->threads),
+                           c->lds_b, c->stream, c->bt);
+    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, c->stream, c->bt);
+}
+
+template <int ORDER>
+void batch_step_order(pic_batch *c)
+{
+    if (c->kind == 0) batch_step_kind<ORDER, 1, false>(c);
+    else if (c->kind == 1) batch_step_kind<ORDER, 3, false>(c);
+    else batch_step_kind<ORDER, 3, true>(c);
+}
+
+void batch_one_step(pic_batch *c)
+{
+    if (c->p.shape_order == 1)
+        batch_step_order<1>(c);
+    else
+        batch_step_order<2>(c);
+}
+
+template <int ORDER, int NV, bool EM>
+void batch_init_kind(pic_batch *c)
+{
+    hipLaunchKernelGGL((k_batch_init_particles<NV>), dim3(c->grid), dim3(c->threads), 0, c->stream, c->bt);
+    if (c->p.flags & PIC_BF_INIT_GAUSS) {
+        hipLaunchKernelGGL((k_batch_deposit_rho<ORDER>), dim3(c->grid), dim3(c->threads), c->lds_dep,
+                           c->stream, c->bt);
+        hipLaunchKernelGGL(k_batch_gauss, dim3(c->p.n_runs), dim3(512), c->lds_gauss, c->stream, c->bt);
+    }
+    if (EM)
+        hipLaunchKernelGGL(k_batch_cn_init, dim3(c->p.n_runs), dim3(512), 0, c->stream, c->bt);
+    if (c->p.scheme != PIC_ESEC1)
+        hipLaunchKernelGGL((k_batch_predeposit<ORDER, NV, EM>), dim3(c->grid), dim3(c->threads),
+                           c->lds_dep, c->stream, c->bt);
+    hipLaunchKernelGGL(k_batch_init_finish, dim3(c->p.n_runs), dim3(512), 0, c->stream, c->bt);
+}
+
+template <int ORDER>
+void batch_init_order(pic_batch *c)
+{
+    if (c->kind == 0) batch_init_kind<ORDER, 1, false>(c);
+    else if (c->kind == 1) batch_init_kind<ORDER, 3, false>(c);
+    else batch_init_kind<ORDER, 3, true>(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_batch_workspace_size(const pic_batch_params *p)
+{
+    if (batch_validate(p) != PIC_OK)
+        return 0;
+    return batch_layout(p).total;
+}
+
+int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *hip_stream,
+                   pic_batch **out)
+{
+    if (!out)
+        return fail(nullptr, PIC_EINVAL, "out is NULL");
+    int rc = batch_validate(p);
+    if (rc != PIC_OK)
+        return rc;
+    const bool em = p->scheme == PIC_EMEC_LI;
+    if (!b || !b->x || !b->v || !b->E || !b->workspace || (em && !b->B))
+        return fail(nullptr, PIC_EINVAL, "x, v, E, workspace (and B for EM) must be non-NULL");
+    if ((uintptr_t)b->workspace % kAlign)
+        return fail(nullptr, PIC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    const BatchLayout L = batch_layout(p);
+    if (b->workspace_bytes < L.total)
+        return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, L.total);
+
+    pic_batch *c = new (std::nothrow) pic_batch();
+    if (!c)
+        return fail(nullptr, PIC_ENOMEM, "out of host memory");
+    c->p = *p;
+    c->np.assign(p->n_particles, p->n_particles + p->n_runs);
+    c->ng.assign(p->n_cells, p->n_cells + p->n_runs);
+    c->len.assign(p->length, p->length + p->n_runs);
+    c->p.n_particles = c->np.data();
+    c->p.n_cells = c->ng.data();
+    c->p.length = c->len.data();
+    c->b = *b;
+    c->stream = (hipStream_t)hip_stream;
+    c->threads = batch_threads(p);
+    c->kind = em ? 2 : (p->nv == 3 ? 1 : 0);
+    c->steps_done = 0;
+    c->poisoned = 0;
+    c->graph = nullptr;
+    c->exec = nullptr;
+    c->rec_cap = batch_records(p);
+    c->records_read.assign(p->n_runs, 0);
+
+    int64_t ntot = 0;
+    int maxg = 0;
+    for (int r = 0; r < p->n_runs; ++r) {
+        ntot += p->n_particles[r];
+        maxg = std::max(maxg, p->n_cells[r]);
+    }
+    const int chunk = batch_chunk(p);
+    char *ws = (char *)b->workspace;
+    std::vector<BatchRun> runs(p->n_runs);
+    std::vector<BatchItem> items;
+    items.reserve(L.nitems);
+    int64_t poff = 0, goff = 0;
+    for (int r = 0; r < p->n_runs; ++r) {
+        const pic_params q = run_params(p, r);
+        BatchRun &br = runs[r];
+        std::memset(&br, 0, sizeof br);
+        Run &R = br.r;
+        R.np = q.n_particles;
+        R.vstride = ntot;
+        R.ng = q.n_cells;
+        R.nv = q.nv;
+        R.nblocks = (int32_t)((q.n_particles + chunk - 1) / chunk);
+        R.rec_cap = c->rec_cap;
+        R.chunk = chunk;
+        R.scheme = q.scheme;
+        R.tw = q.n_cells + 2 * kGhost;
+        R.L = q.length;
+        R.h = q.length / q.n_cells;
+        R.inv_h = q.n_cells / q.length;
+        R.dt = q.dt;
+        R.hdt = 0.5 * q.dt;
+        R.c2 = q.c * q.c;
+        R.qs = 1.0 / R.h;
+        R.wu = q.length / (double)q.n_particles;
+        for (int i = 0; i < 3; ++i)
+            R.bext[i] = q.nv == 3 ? q.b_ext[i] : 0.0;
+        R.w = b->w ? b->w + poff : nullptr;
+        Work &W = br.wk;
+        W.E = b->E + 3 * goff;
+        W.B = em ? b->B + 2 * goff : nullptr;
+        W.Ef[0] = (double *)(ws + L.Ef0[r]);
+        W.Ef[1] = (double *)(ws + L.Ef1[r]);
+        W.Bf[0] = (double *)(ws + L.Bf0[r]);
+        W.Bf[1] = (double *)(ws + L.Bf1[r]);
+        W.J1[0] = (double *)(ws + L.J10[r]);
+        W.J1[1] = (double *)(ws + L.J11[r]);
+        W.J2[0] = (double *)(ws + L.J20[r]);
+        W.J2[1] = (double *)(ws + L.J21[r]);
+        W.cninv = (double *)(ws + L.cninv[r]);
+        W.spart = (double *)(ws + L.spart) + (size_t)items.size() * kNS;
+        W.st = (DevState *)(ws + L.st) + r;
+        W.rec = (DevRecord *)(ws + L.rec) + (size_t)r * c->rec_cap;
+        br.poff = poff;
+        c->st.push_back(W.st);
+        c->rec.push_back(W.rec);
+        for (int k = 0; k < R.nblocks; ++k) {
+            BatchItem it;
+            it.run = r;
+            it.slot = k;
+            it.p0 = (int64_t)k * chunk;
+            it.p1 = std::min<int64_t>(q.n_particles, it.p0 + chunk);
+            items.push_back(it);
+        }
+        poff += q.n_particles;
+        goff += q.n_cells;
+    }
+    c->bt.runs = (const BatchRun *)(ws + L.runs);
+    c->bt.items = (const BatchItem *)(ws + L.items);
+    c->bt.nitems = (int32_t)items.size();
+    c->bt.nruns = p->n_runs;
+    c->bt.X = b->x;
+    c->bt.V = b->v;
+    c->bt.stepc = (int64_t *)(ws + L.stepc);
+    c->grid = p->grid_blocks ? p->grid_blocks : std::min<int>(c->bt.nitems, 2048);
+
+    const size_t tw = (size_t)maxg + 2 * kGhost;
+    const size_t ng = (size_t)maxg;
+    c->lds_a = em ? 8 * tw * 8 : 2 * tw * 8;
+    c->lds_b = em ? 13 * tw * 8 + 13 * ng * 8 : 3 * tw * 8 + ng * 8;
+    c->lds_dep = (em ? 3 : 1) * tw * 8;
+    c->lds_gauss = 3 * ng * 8;
+
+    if (hipMemcpy(ws + L.runs, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ws + L.items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess) {
+        rc = batch_check(c, "pic_batch_init table copy");
+        g_last_error = c->err;
+        delete c;
+        return rc == PIC_OK ? PIC_EDEVICE : rc;
+    }
+    // clear the per-run field and current buffers
+    fill_range(c->stream, (double *)(ws + L.Ef0[0]), (int64_t)(L.spart - L.Ef0[0]) / 8);
+    if (!em)
+        for (int r = 0; r < p->n_runs; ++r)
+            fill_range(c->stream, runs[r].wk.E + p->n_cells[r], 2 * (int64_t)p->n_cells[r]);
+    if (p->shape_order == 1)
+        batch_init_order<1>(c);
+    else
+        batch_init_order<2>(c);
+    rc = batch_check(c, "pic_batch_init launches");
+    if (rc != PIC_OK) {
+        g_last_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch *c, int64_t n_steps)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if (n_steps < 0)
+        return fail(&c->err, PIC_EINVAL, "n_steps must be >= 0");
+    const int G = c->p.graph_steps;
+    int64_t left = n_steps;
+    if (G > 0 && c->stream && left >= G) {
+        if (!c->exec) {
+            if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return batch_check(c, "pic_batch_step capture begin");
+            for (int s = 0; s < G; ++s)
+                batch_one_step(c);
+            if (hipStreamEndCapture(c->stream, &c->graph) != hipSuccess)
+                return batch_check(c, "pic_batch_step capture end");
+            if (hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0) != hipSuccess)
+                return batch_check(c, "pic_batch_step graph instantiate");
+        }
+        while (left >= G) {
+            if (hipGraphLaunch(c->exec, c->stream) != hipSuccess)
+                return batch_check(c, "pic_batch_step graph launch");
+            left -= G;
+        }
+    }
+    for (; left > 0; --left)
+        batch_one_step(c);
+    c->steps_done += n_steps;
+    if (n_steps > 0)
+        hipLaunchKernelGGL(k_batch_finish, dim3(c->p.n_runs), dim3(512), 0, c->stream, c->bt);
+    return batch_check(c, "pic_batch_step launches");
+}
+
+int pic_batch_diagnostics(pic_batch *c, int32_t run, pic_diag *out, int64_t max_records,
+                          int64_t *n_written)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if (run < 0 || run >= c->p.n_runs || !n_written || (max_records > 0 && !out))
+        return fail(&c->err, PIC_EINVAL, "bad run index or output pointers");
+    *n_written = 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return batch_check(c, "pic_batch_diagnostics sync");
+    DevState st;
+    if (hipMemcpy(&st, c->st[run], sizeof st, hipMemcpyDeviceToHost) != hipSuccess)
+        return batch_check(c, "pic_batch_diagnostics state copy");
+    const int64_t last = st.recorded;
+    int64_t first = c->records_read[run];
+    if (last - first + 1 > c->rec_cap)
+        first = last - c->rec_cap + 1;
+    const int64_t n = std::max<int64_t>(0, std::min<int64_t>(last - first + 1, max_records));
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t slot = (first + done) % c->rec_cap;
+        const int64_t len = std::min<int64_t>(n - done, c->rec_cap - slot);
+        if (hipMemcpy(out + done, c->rec[run] + slot, (size_t)len * sizeof(DevRecord),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return batch_check(c, "pic_batch_diagnostics record copy");
+        done += len;
+    }
+    int nonfinite = 0;
+    for (int64_t k = 0; k < n; ++k)
+        nonfinite |= out[k].nonfinite;
+    c->records_read[run] = first + n;
+    *n_written = n;
+    return nonfinite ? PIC_ENONFINITE : PIC_OK;
+}
+
+int pic_batch_destroy(pic_batch *c)
+{
+    if (!c)
+        return PIC_ESTATE;
+    if (c->exec)
+        (void)hipGraphExecDestroy(c->exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    delete c;
+    return PIC_OK;
 }
 
 }  // extern "C"

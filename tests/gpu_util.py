@@ -64,6 +64,8 @@ def run_pair(wl, steps, scheme=None, every=1, tol=TOL, **knobs):
     Returns (gpu records, oracle records, gpu Pic, oracle State)."""
     from paper_2411_09605_amd import Pic
     em = (scheme or wl.scheme) == "emec_li"
+    if knobs.get("rebin_every", 0) > 0:
+        knobs.setdefault("track_ids", True)
     gpu = Pic.from_workload(wl, scheme=scheme, **knobs)
     ost = oracle.State(wl, scheme=scheme)
     vscale = max(1.0, float(np.abs(wl.v).max()))

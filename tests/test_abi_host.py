@@ -37,7 +37,9 @@ def test_validation_accepts_and_sizes():
     import paper_2411_09605_amd as P
     for kw in [{}, dict(scheme="esec1"), dict(nv=3, scheme="emec_li", n_cells=256),
                dict(nv=3, b_ext=(1.0, 0.0, 0.0)), dict(shape_order=1, n_cells=3),
-               dict(n_particles=1), dict(block_threads=1024, grid_blocks=8192)]:
+               dict(n_particles=1), dict(block_threads=1024, grid_blocks=8192),
+               dict(rebin_every=10), dict(rebin_every=1, deposit_mode="lds_atomic"),
+               dict(deposit_mode="window")]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
@@ -60,6 +62,13 @@ def test_validation_rejects(kw, code):
     assert P.workspace_size(p) == 0
 
 
+def test_rebin_workspace_is_larger():
+    import paper_2411_09605_amd as P
+    a = P.workspace_size(_good(n_particles=100_000))
+    b = P.workspace_size(_good(n_particles=100_000, rebin_every=5))
+    assert b >= a + 100_000 * 16
+
+
 def test_abi_version_and_reserved_checked():
     import paper_2411_09605_amd as P
     p = _good()
@@ -80,3 +89,43 @@ def test_strerror_and_null_handling():
     assert lib.pic_destroy(None) == -4
     out = ctypes.c_void_p()
     assert lib.pic_init(None, None, None, ctypes.byref(out)) == -1
+
+
+def _batch(**kw):
+    import paper_2411_09605_amd.binding as B
+    base = dict(nv=1, scheme="esec2", shape_order=1, n_particles=[1000, 50, 70000],
+                n_cells=[64, 3, 512], length=[10.0, 3.0, 20.0], dt=0.1)
+    base.update(kw)
+    return B.make_batch_params(**base)
+
+
+def test_batch_validation_accepts_and_sizes():
+    import paper_2411_09605_amd.binding as B
+    for kw in [{}, dict(shape_order=2, n_cells=[64, 5, 512]), dict(block_threads=64, chunk=128),
+               dict(nv=3, scheme="emec_li", n_cells=[64, 5, 256]), dict(graph_steps=8),
+               dict(n_particles=[1], n_cells=[8], length=[1.0])]:
+        p = _batch(**kw)
+        assert B.batch_workspace_size(p) > 0, (kw, B.last_error())
+    # more work items, more workspace
+    assert B.batch_workspace_size(_batch(chunk=256)) > B.batch_workspace_size(_batch())
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_particles=[], n_cells=[], length=[]), dict(n_cells=[64, 2, 512]),
+    dict(n_particles=[1000, 0, 5]), dict(length=[10.0, -1.0, 1.0]), dict(chunk=100),
+    dict(block_threads=96), dict(graph_steps=-1), dict(nv=1, scheme="emec_li"),
+    dict(n_cells=[64, 3, 100000]), dict(dt=float("inf")),
+])
+def test_batch_validation_rejects(kw):
+    import paper_2411_09605_amd.binding as B
+    p = _batch(**kw)
+    assert B.batch_workspace_size(p) == 0
+    assert B.last_error()
+
+
+def test_batch_null_handling():
+    import paper_2411_09605_amd.binding as B
+    lib = B.lib
+    assert lib.pic_batch_step(None, 1) == -4
+    assert lib.pic_batch_destroy(None) == -4
+    assert lib.pic_batch_workspace_size(None) == 0

@@ -98,6 +98,11 @@ def test_launch_shapes_agree():
     wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
     for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
         gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
+    # default shape: 512 threads, min(ceil(N / 512), 512) workgroups, whole 4-particle
+    # batches per thread in every chunk
+    from paper_2411_09605_amd import Pic
+    t, g, c = Pic.from_workload(wl).launch_shape()
+    assert t == 512 and c % (4 * 512) == 0 and (g - 1) * c < wl.n_particles <= g * c
 
 
 def test_fast_particles_cross_several_cells():
@@ -200,5 +205,57 @@ def test_weibel_full_size_parity():
     wl = workloads.weibel()
     grec, orec, gpu, _ = gu.run_pair(wl, 1)
     gpu.step(50)
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+
+
+# ------------------------------------------------------- cell-sorted layout (rebin)
+@pytest.mark.parametrize("mode", ["window", "lds_atomic"])
+def test_rebin_landau_parity(mode):
+    """Counting-sort rebin every 3 steps (including step 0); particles are matched to the
+    oracle through their ids."""
+    _say(f"case: rebin landau, deposit {mode}")
+    wl = workloads.landau()
+    gu.run_pair(wl, 10, rebin_every=3, deposit_mode=mode)
+
+
+def test_rebin_two_stream_quadratic_parity():
+    _say("case: rebin two-stream 2e5 x 512")
+    wl = workloads.two_stream(n_particles=200_000, n_cells=512, steps=10)
+    gu.run_pair(wl, 10, rebin_every=4, block_threads=256, grid_blocks=97)
+
+
+def test_rebin_weights_3v_ragged_parity():
+    """Non-uniform weights are permuted with the particles."""
+    _say("case: rebin ES 3V weights")
+    n = 30_001
+    wl = workloads.landau(n_particles=n, n_cells=40, alpha=0.1, order=2)
+    wl.v = np.stack([wl.v[0], workloads.normals(9, 12, n), workloads.normals(9, 14, n)])
+    wl.nv = 3
+    wl.b_ext = (0.3, -0.6, 1.2)
+    wl.w = wl.length / n * (1.0 + 0.5 * workloads.uniforms(9, 20, n))
+    gu.run_pair(wl, 10, rebin_every=2)
+
+
+def test_rebin_em_parity():
+    _say("case: rebin EM weibel 1e5 x 256")
+    wl = workloads.weibel(n_particles=100_000, n_cells=256, steps=10)
+    wl.B0 *= 50.0
+    gu.run_pair(wl, 10, rebin_every=5)
+
+
+def test_window_deposit_unsorted_parity():
+    """The register-window deposit is correct (if slower) on unsorted particles."""
+    _say("case: window deposit without rebin")
+    wl = workloads.two_stream(n_particles=100_000, n_cells=64, steps=10)
+    gu.run_pair(wl, 10, deposit_mode="window")
+
+
+def test_rebin_full_size_two_stream():
+    _say("case: rebin two-stream FULL 1e7 x 512")
+    wl = workloads.two_stream()
+    grec, orec, gpu, _ = gu.run_pair(wl, 2, every=2, rebin_every=1, block_threads=512,
+                                     grid_blocks=512)
+    gpu.step(60)
     rec = gpu.diagnostics()
     assert rec["rel_energy_err"].max() < 1e-11
