@@ -175,3 +175,81 @@ def energy(state: State) -> np.void:
     lib().oracle_energy(ctypes.byref(state.cfg), _p(state.v), _p(state.w), _p(state.E),
                         _p(state.B), rec.ctypes.data)
     return rec[0]
+
+
+# ------------------------------------------------------------ tangent-linear derivative
+def _tlm_sig():
+    L = lib()
+    if not getattr(L, "_tlm_ready", False):
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_tlm_run.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, ctypes.c_int64,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp,
+                                     dp, dp, ctypes.c_void_p]
+        L.oracle_tlm_run.restype = ctypes.c_int
+        L.oracle_gauss_rho.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L._tlm_ready = True
+    return L
+
+
+def tlm_run(wl, nsteps: int, dx, dv, loss_weight: float, dE=None):
+    """Forward-mode derivative of an ESEC2 1D-1V run of ``nsteps`` steps.
+
+    ``dx``, ``dv``: [K, N_p] tangent directions of the initial positions and velocities;
+    ``dE`` ([K, N_g]) only when the workload does not start from the Gauss solve.  The
+    loss is ``loss_weight * sum_{n=1..N} W_E^n``.  Returns a dict with the loss ``J``,
+    ``dJ`` [K], the final state (``x``, ``v``, ``E``), the final tangents (``dx``, ``dv``,
+    ``dE``) and the records."""
+    K = int(np.asarray(dx).shape[0]) if np.asarray(dx).ndim == 2 else 0
+    n, ng = wl.n_particles, wl.n_cells
+    cfg = make_cfg(1, "esec2", wl.order, ng, n, wl.length, wl.dt)
+    x = np.ascontiguousarray(wl.x, dtype=np.float64).copy()
+    v = np.ascontiguousarray(wl.v, dtype=np.float64).reshape(-1).copy()
+    E = np.zeros(ng) if wl.E0 is None else \
+        np.ascontiguousarray(np.asarray(wl.E0, dtype=np.float64).reshape(3, -1)[0]).copy()
+    tx = np.ascontiguousarray(np.asarray(dx, dtype=np.float64).reshape(K, n)).copy()
+    tv = np.ascontiguousarray(np.asarray(dv, dtype=np.float64).reshape(K, n)).copy()
+    tE = np.zeros((K, ng)) if dE is None else \
+        np.ascontiguousarray(np.asarray(dE, dtype=np.float64).reshape(K, ng)).copy()
+    J = ctypes.c_double()
+    dJ = np.zeros(max(K, 1))
+    rec = np.zeros(nsteps + 1, dtype=DIAG_DTYPE)
+    w = None if wl.w is None else np.ascontiguousarray(wl.w, dtype=np.float64).copy()
+    rc = _tlm_sig().oracle_tlm_run(ctypes.byref(cfg), _p(x), _p(v), _p(w), _p(E), nsteps,
+                                   int(wl.init_gauss), loss_weight, K, _p(tx), _p(tv), _p(tE),
+                                   ctypes.cast(ctypes.byref(J), ctypes.POINTER(ctypes.c_double)),
+                                   _p(dJ), rec.ctypes.data)
+    if rc != 0:
+        raise ValueError("tangent-linear run supports ESEC2 1D-1V only")
+    return dict(J=J.value, dJ=dJ[:K], x=x, v=v, E=E, dx=tx, dv=tv, dE=tE, records=rec)
+
+
+def density_mode_tangents(x, modes):
+    """Derivative of inverse-CDF positions with respect to each mode amplitude.
+
+    The positions solve F(x) = x + sum_j (alpha_j / k_j) sin(k_j x) = u L for the
+    density 1 + sum_j alpha_j cos(k_j x); differentiating that identity at fixed u gives
+    dx / d alpha_m = -sin(k_m x) / (k_m (1 + sum_j alpha_j cos(k_j x)))."""
+    x = np.asarray(x, dtype=np.float64)
+    dens = np.ones_like(x)
+    for k, a in modes:
+        dens = dens + a * np.cos(k * x)
+    return np.stack([-np.sin(k * x) / (k * dens) for k, _ in modes])
+
+
+def two_stream_gradient(wl, nsteps: int):
+    """Reference gradient of J = dt sum_{n=1..N} W_E^n with respect to the mode
+    amplitudes, the beam speed and the beam spread of a two-stream workload built by
+    ``workloads.adjoint_two_stream`` (velocities v_b s_p + v_spread g_p): one
+    tangent-linear run with one direction per parameter."""
+    modes = wl.meta["modes"]
+    n = wl.n_particles
+    sign = np.asarray(wl.meta["sign"], dtype=np.float64)
+    g = np.asarray(wl.meta["g"], dtype=np.float64)
+    K = len(modes) + 2
+    dx = np.zeros((K, n))
+    dv = np.zeros((K, n))
+    dx[:len(modes)] = density_mode_tangents(wl.x, modes)
+    dv[len(modes)] = sign
+    dv[len(modes) + 1] = g
+    out = tlm_run(wl, nsteps, dx, dv, wl.dt)
+    return out["J"], out["dJ"], out

@@ -160,16 +160,10 @@ static double mean(const double *a, int n)
 
 /* dE/dx = rho - 1 solved spectrally on the nodes (Poisson form, section 2.1): with
  * DFT coefficients rho_m, E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2;
- * the mean mode and (even N) the Nyquist mode of E are zero. */
-void oracle_gauss(int order, int64_t np, const double *x, const double *w, int ng,
-                  double L, double *E)
+ * the mean mode and (even N) the Nyquist mode of E are zero.  The map rho -> E is
+ * linear (the constant background only enters the mean mode). */
+void oracle_gauss_rho(int ng, double L, const double *rho, double *E)
 {
-    double h = L / ng;
-    double *rho = (double *)malloc(sizeof(double) * (size_t)ng);
-    double *ones = (double *)malloc(sizeof(double) * (size_t)np);
-    for (int64_t p = 0; p < np; ++p)
-        ones[p] = 1.0;
-    oracle_deposit(order, np, x, w, ones, ng, h, 0.0, rho);
     double *ere = (double *)calloc((size_t)ng, sizeof(double));
     double *eim = (double *)calloc((size_t)ng, sizeof(double));
     for (int m = 1; m < ng; ++m) {
@@ -196,6 +190,18 @@ void oracle_gauss(int order, int64_t np, const double *x, const double *w, int n
     }
     free(ere);
     free(eim);
+}
+
+void oracle_gauss(int order, int64_t np, const double *x, const double *w, int ng,
+                  double L, double *E)
+{
+    double h = L / ng;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)ng);
+    double *ones = (double *)malloc(sizeof(double) * (size_t)np);
+    for (int64_t p = 0; p < np; ++p)
+        ones[p] = 1.0;
+    oracle_deposit(order, np, x, w, ones, ng, h, 0.0, rho);
+    oracle_gauss_rho(ng, L, rho, E);
     free(ones);
     free(rho);
 }
@@ -562,4 +568,240 @@ int oracle_run(const ocfg *cfg, double *x, double *v, const double *w, double *E
                double *B, int64_t nsteps, int init_gauss, odiag *rec)
 {
     return oracle_run_gamma(cfg, x, v, w, E, B, nsteps, init_gauss, rec, NULL);
+}
+
+/* ====================================================================================
+ * Tangent-linear (forward-mode) derivative of an ESEC2 run, 1D-1V electrostatic.
+ *
+ * The run is the map (x^0, v^0) -> (x^n, v^n, E^n), n = 1..N, of eq. (good_translation)
+ * with (doublestardef), with E^0 from the Gauss solve of the initial particles, and the
+ * loss J = lw * sum_{n=1..N} W_E^n with W_E = (h/2) sum_i E_i^2 (section 5.1).  This
+ * function propagates K tangent directions (dx^0, dv^0) alongside the state by the
+ * chain rule applied to each of S0-S13 in turn, and accumulates dJ for each direction.
+ * It is the plain definition of the derivative written out; the fallback branch Gamma
+ * := 1 (section 3.2) is a constant, so its derivative is zero.
+ * ==================================================================================== */
+
+/* Derivative of bspline(order, t) with respect to t (zero at the tent's kinks). */
+static double dbspline(int order, double t)
+{
+    double a = fabs(t), sg = t > 0.0 ? 1.0 : (t < 0.0 ? -1.0 : 0.0);
+    if (order == 1)
+        return a < 1.0 ? -sg : 0.0;
+    if (a < 0.5)
+        return -2.0 * t;
+    if (a < 1.5)
+        return -(1.5 - a) * sg;
+    return 0.0;
+}
+
+/* Nodes of a particle at position pos with the weight S(x_j - pos) and its derivative
+ * with respect to pos: d/dpos bspline(j - pos/h) = -bspline'(j - pos/h) / h. */
+static int stencil_d(int order, double pos, double h, int ng, int64_t *idx, double *wt,
+                     double *dwt)
+{
+    double xi = pos / h;
+    int64_t j0 = (int64_t)floor(xi);
+    int n = 0;
+    for (int64_t j = j0 - 1; j <= j0 + 2; ++j) {
+        double s = bspline(order, (double)j - xi);
+        double ds = -dbspline(order, (double)j - xi) / h;
+        if (s != 0.0 || ds != 0.0) {
+            idx[n] = pmod(j, ng);
+            wt[n] = s;
+            dwt[n] = ds;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* d j_i = (1/h) sum_p w_p [du_p S(x_i - x_p) + u_p dS/dx_p dx_p]; out zeroed first. */
+static void tlm_deposit(int order, int64_t np, const double *x, const double *dx,
+                        const double *w, const double *u, const double *du, int ng, double h,
+                        double *out)
+{
+    int64_t idx[4];
+    double wt[4], dwt[4];
+    memset(out, 0, sizeof(double) * (size_t)ng);
+    for (int64_t p = 0; p < np; ++p) {
+        int n = stencil_d(order, x[p], h, ng, idx, wt, dwt);
+        for (int k = 0; k < n; ++k)
+            out[idx[k]] += w[p] * (du[p] * wt[k] + u[p] * dwt[k] * dx[p]) / h;
+    }
+}
+
+/* d G_p = sum_i [dF_i S(x_i - x_p) + F_i dS/dx_p dx_p]. */
+static void tlm_gather(int order, int64_t np, const double *x, const double *dx,
+                       const double *F, const double *dF, int ng, double h, double *out)
+{
+    int64_t idx[4];
+    double wt[4], dwt[4];
+    for (int64_t p = 0; p < np; ++p) {
+        int n = stencil_d(order, x[p], h, ng, idx, wt, dwt);
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k)
+            acc += dF[idx[k]] * wt[k] + F[idx[k]] * dwt[k] * dx[p];
+        out[p] = acc;
+    }
+}
+
+/* Run N steps of ESEC2 (cfg: nv 1, scheme 0) from (x, v) with K tangent directions.
+ *   x, v      [np]: initial state in, final state out (x wrapped first)
+ *   E         [ng]: E^0 in when !init_gauss (else computed), E^N out
+ *   dx, dv  [K][np]: initial tangents in, final tangents out
+ *   dE      [K][ng]: tangent of E^0 in when !init_gauss (else computed), of E^N out
+ *   loss, dloss[K]: J and dJ for each direction
+ *   rec     [N+1] : diagnostics (as oracle_run), or NULL
+ * Returns 0, or -1 for an unsupported configuration. */
+int oracle_tlm_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
+                   int64_t nsteps, int init_gauss, double lw, int K, double *dx, double *dv,
+                   double *dE, double *loss, double *dloss, odiag *rec)
+{
+    if (oracle_check(cfg) || cfg->nv != 1 || cfg->scheme != 0 || K < 0)
+        return -1;
+    const int64_t np = cfg->n_particles;
+    const int ng = cfg->n_cells, ord = cfg->order;
+    const double L = cfg->length, h = L / ng, dt = cfg->dt;
+    const size_t P = sizeof(double) * (size_t)np, G = sizeof(double) * (size_t)ng;
+    double *wv = malloc(P), *xs = malloc(P), *x1 = malloc(P), *xh = malloc(P);
+    double *vs = malloc(P), *gs = malloc(P), *gb = malloc(P);
+    double *J1 = malloc(G), *J2 = malloc(G), *Es = malloc(G), *En = malloc(G), *Eb = malloc(G);
+    double *dxs = malloc(P), *dx1 = malloc(P), *dxh = malloc(P), *dvs = malloc(P);
+    double *dgs = malloc(P), *dgb = malloc(P), *zero = calloc((size_t)np, sizeof(double));
+    double *ones = malloc(P);
+    double *dJ1 = malloc(G), *dJ2 = malloc(G), *dEs = malloc(G), *dEn = malloc(G), *dEb = malloc(G);
+    double *vd = malloc(P), *num = malloc(P), *den = malloc(P), *gam = malloc(P);
+    int *ok = malloc(sizeof(int) * (size_t)np);
+    const double wu = L / (double)np;
+    for (int64_t p = 0; p < np; ++p) {
+        wv[p] = w ? w[p] : wu;
+        ones[p] = 1.0;
+        x[p] = wrap(x[p], L);
+    }
+    /* S0: E^0 from rho(x^0); its tangent from d rho = (1/h) sum w dS/dx dx */
+    if (init_gauss) {
+        double *rho = malloc(G);
+        oracle_deposit(ord, np, x, wv, ones, ng, h, 0.0, rho);
+        oracle_gauss_rho(ng, L, rho, E);
+        for (int k = 0; k < K; ++k) {
+            tlm_deposit(ord, np, x, dx + (size_t)k * np, wv, ones, zero, ng, h, rho);
+            oracle_gauss_rho(ng, L, rho, dE + (size_t)k * ng);
+        }
+        free(rho);
+    }
+    nsum J = {0.0, 0.0};
+    nsum *dJ = calloc((size_t)(K > 0 ? K : 1), sizeof(nsum));
+    if (rec) {
+        memset(&rec[0], 0, sizeof(odiag));
+        oracle_energy(cfg, v, w, E, NULL, &rec[0]);
+    }
+    for (int64_t n = 0; n < nsteps; ++n) {
+        /* ---- the step itself (as in step(), kept for the tangents) ---- */
+        for (int64_t p = 0; p < np; ++p)
+            xs[p] = x[p] + 0.5 * dt * v[p];                                     /* S1 */
+        oracle_deposit(ord, np, xs, wv, v, ng, h, 0.0, J1);                     /* S2 */
+        double m1 = mean(J1, ng);
+        for (int i = 0; i < ng; ++i)
+            Es[i] = E[i] - 0.5 * dt * (J1[i] - m1);                             /* S3 */
+        oracle_gather(ord, np, xs, Es, ng, h, 0.0, gs);                         /* S4 */
+        for (int64_t p = 0; p < np; ++p) {
+            vs[p] = v[p] + 0.5 * dt * gs[p];                                    /* S5 */
+            x1[p] = x[p] + dt * vs[p];                                          /* S6 */
+            xh[p] = 0.5 * (x[p] + x1[p]);
+        }
+        oracle_deposit(ord, np, xh, wv, vs, ng, h, 0.0, J2);                    /* S7 */
+        double m2 = mean(J2, ng);
+        for (int i = 0; i < ng; ++i) {
+            En[i] = E[i] - dt * (J2[i] - m2);                                   /* S8 */
+            Eb[i] = 0.5 * (E[i] + En[i]);
+        }
+        oracle_gather(ord, np, xh, Eb, ng, h, 0.0, gb);                         /* S9 */
+        int64_t fb = 0;
+        double gmax = 0.0;
+        for (int64_t p = 0; p < np; ++p) {
+            vd[p] = v[p] + dt * gb[p];                                          /* S10 */
+            num[p] = (vs[p] - 0.5 * (vd[p] + v[p])) * (vd[p] - v[p]);           /* S11 */
+            den[p] = vd[p] * vd[p];
+            double r = 1.0 + 2.0 * num[p] / den[p];
+            ok[p] = r >= 0.0 && isfinite(r);                                    /* S12 */
+            gam[p] = ok[p] ? sqrt(r) : 1.0;
+            if (!ok[p])
+                ++fb;
+            if (fabs(gam[p] - 1.0) > gmax)
+                gmax = fabs(gam[p] - 1.0);
+        }
+        /* ---- tangents, direction by direction ---- */
+        for (int k = 0; k < K; ++k) {
+            double *tx = dx + (size_t)k * np, *tv = dv + (size_t)k * np;
+            double *tE = dE + (size_t)k * ng;
+            for (int64_t p = 0; p < np; ++p)
+                dxs[p] = tx[p] + 0.5 * dt * tv[p];
+            tlm_deposit(ord, np, xs, dxs, wv, v, tv, ng, h, dJ1);
+            double dm1 = mean(dJ1, ng);
+            for (int i = 0; i < ng; ++i)
+                dEs[i] = tE[i] - 0.5 * dt * (dJ1[i] - dm1);
+            tlm_gather(ord, np, xs, dxs, Es, dEs, ng, h, dgs);
+            for (int64_t p = 0; p < np; ++p) {
+                dvs[p] = tv[p] + 0.5 * dt * dgs[p];
+                dx1[p] = tx[p] + dt * dvs[p];
+                dxh[p] = 0.5 * (tx[p] + dx1[p]);
+            }
+            tlm_deposit(ord, np, xh, dxh, wv, vs, dvs, ng, h, dJ2);
+            double dm2 = mean(dJ2, ng);
+            for (int i = 0; i < ng; ++i) {
+                dEn[i] = tE[i] - dt * (dJ2[i] - dm2);
+                dEb[i] = 0.5 * (tE[i] + dEn[i]);
+            }
+            tlm_gather(ord, np, xh, dxh, Eb, dEb, ng, h, dgb);
+            for (int64_t p = 0; p < np; ++p) {
+                double dvd = tv[p] + dt * dgb[p];
+                double a = vs[p] - 0.5 * (vd[p] + v[p]), b = vd[p] - v[p];
+                double dnum = (dvs[p] - 0.5 * (dvd + tv[p])) * b + a * (dvd - tv[p]);
+                double dden = 2.0 * vd[p] * dvd;
+                double dg = 0.0;
+                if (ok[p]) {
+                    /* Gamma = sqrt(1 + 2 num / den) */
+                    double drho = 2.0 * dnum / den[p] - 2.0 * num[p] * dden / (den[p] * den[p]);
+                    dg = drho / (2.0 * gam[p]);
+                }
+                tv[p] = dg * vd[p] + gam[p] * dvd;                                 /* S13 */
+                tx[p] = dx1[p];                                  /* wrap: a translation */
+            }
+            memcpy(tE, dEn, G);
+        }
+        /* ---- state update and loss ---- */
+        for (int64_t p = 0; p < np; ++p) {
+            v[p] = gam[p] * vd[p];
+            x[p] = wrap(x1[p], L);
+        }
+        memcpy(E, En, G);
+        nsum we = {0.0, 0.0};
+        for (int i = 0; i < ng; ++i)
+            nadd(&we, 0.5 * h * E[i] * E[i]);
+        nadd(&J, lw * (we.s + we.c));
+        for (int k = 0; k < K; ++k) {
+            const double *tE = dE + (size_t)k * ng;
+            nsum d = {0.0, 0.0};
+            for (int i = 0; i < ng; ++i)
+                nadd(&d, h * E[i] * tE[i]);
+            nadd(&dJ[k], lw * (d.s + d.c));
+        }
+        if (rec) {
+            memset(&rec[n + 1], 0, sizeof(odiag));
+            oracle_energy(cfg, v, w, E, NULL, &rec[n + 1]);
+            rec[n + 1].fallbacks = fb;
+            rec[n + 1].max_gamma_dev = gmax;
+        }
+    }
+    *loss = J.s + J.c;
+    for (int k = 0; k < K; ++k)
+        dloss[k] = dJ[k].s + dJ[k].c;
+    free(dJ);
+    free(wv); free(xs); free(x1); free(xh); free(vs); free(gs); free(gb);
+    free(J1); free(J2); free(Es); free(En); free(Eb);
+    free(dxs); free(dx1); free(dxh); free(dvs); free(dgs); free(dgb); free(zero); free(ones);
+    free(dJ1); free(dJ2); free(dEs); free(dEn); free(dEb);
+    free(vd); free(num); free(den); free(gam); free(ok);
+    return 0;
 }

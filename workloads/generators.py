@@ -181,7 +181,7 @@ def two_stream(n_particles: int = 10_000_000, n_cells: int = 512, k: float = 0.2
     return Workload(name="two_stream", nv=1, scheme=scheme, order=order,
                     n_cells=n_cells, length=length, dt=dt, steps=steps, x=x, v=v,
                     meta=dict(k=k, alpha=alpha, v_beam=v_beam, v_spread=v_spread,
-                              seed=seed, quiet=quiet))
+                              seed=seed, quiet=quiet, u=u, g=g, sign=sign))
 
 
 def weibel(n_particles: int = 20_000_000, n_cells: int = 256, k0: float = 0.5,
@@ -248,8 +248,8 @@ def adjoint_two_stream(n_particles: int = 1_000_000, n_cells: int = 256, k: floa
                        order: int = 2, seed: int = 5) -> Workload:
     """Two-stream with density ``1 + sum_m alpha_m cos(m k x)``, ``m = 1 .. len(alphas)``.
 
-    ``meta`` keeps the beam signs and the uniform/normal draws so that the same
-    particles can be regenerated for perturbed parameters (finite differences).
+    ``meta`` keeps the beam signs and the uniform/normal draws (``sign``, ``u``, ``g``)
+    so that the same particles can be regenerated for other parameters.
     """
     modes = [((m + 1) * k, a) for m, a in enumerate(alphas)]
     wl = two_stream(n_particles=n_particles, n_cells=n_cells, k=k, v_beam=v_beam,
