@@ -10,6 +10,10 @@ timed region (HIP events on the library's stream) covers only the steps.
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel (pass B,
 measured with HIP events around its launches), and the oracle timed on the host cores.
 
+``--form adjoint`` times the adjoint form on the two-stream gradient workload (1e6
+particles, 256 cells, 500 steps, 8 density modes): the loss forward with checkpoints
+every 50 steps plus the reverse sweep, against the plain forward step on the same run.
+
 ``--form batched`` instead times the batched ensemble (512 Landau runs of 10^4 .. 10^6
 particles, about 1.1e8 in all) advanced together from a replayed hipGraph, with the launch
 shape picked by the autotuner, against the plain step run sequentially over the same
@@ -136,6 +140,72 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Adjoint form: (forward + backward) time against the forward-only plain step."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2411_09605_amd import Pic, PicAdjoint
+
+    wl = workloads.by_name("adjoint_two_stream_256c_1M")
+    m = wl.meta
+    n, N = wl.n_particles, wl.steps
+    every = 50
+    adj = PicAdjoint.from_workload(wl, checkpoint_every=every)
+    theta = (m["alphas"], m["v_beam"], m["v_spread"])
+    for _ in range(2):                                   # warm-up
+        adj.forward(*theta)
+        adj.backward(1.0)
+    torch.cuda.synchronize()
+    reps = 3
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    f_ms, b_ms = [], []
+    for _ in range(reps):
+        ev[0].record(adj.stream)
+        adj.forward(*theta, sync=False)
+        ev[1].record(adj.stream)
+        adj.backward(1.0, sync=False)
+        ev[2].record(adj.stream)
+        torch.cuda.synchronize()
+        f_ms.append(ev[0].elapsed_time(ev[1]))
+        b_ms.append(ev[1].elapsed_time(ev[2]))
+    J = float(adj.loss.cpu()[0])
+    grad = adj.grad.cpu().numpy().tolist()
+    recs = adj.records()
+    adj.destroy()
+    # the plain step on the same run (same sampled particles as the generator's)
+    gpu = Pic.from_workload(wl, device="cuda:0", record_capacity=N + 8)
+    gpu.step(20)
+    gpu.diagnostics()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(gpu.stream)
+    gpu.step(N)
+    e1.record(gpu.stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    gpu.destroy()
+    fb = float(np.median(f_ms))
+    bb = float(np.median(b_ms))
+    total = fb + bb
+    out = {
+        "metric": "adjoint (forward + backward) time vs forward-only plain step, two-stream "
+                  "gradient workload (FP64)",
+        "value": n * N / (total * 1e-3), "unit": "particle-steps/s (forward + backward)",
+        "n_gpus": 1, "steps": N, "warmup": 2, "ms_per_step": total / N,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint_two_stream_256c_1M", "n_particles": n,
+                   "n_cells": wl.n_cells, "shape_order": wl.order, "dt": wl.dt,
+                   "n_modes": len(m["alphas"]), "checkpoint_every": every},
+        "forward_ms": fb, "backward_ms": bb, "plain_forward_ms": plain_ms,
+        "ratio_to_plain_forward": total / plain_ms,
+        "loss": J, "grad": grad,
+        "energy": energy_report(recs),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def workload_for(name):
     import workloads
     return workloads.by_name(name)
@@ -154,7 +224,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="oracle steps of the same workload for the CPU baseline (0: skip)")
-    ap.add_argument("--form", choices=("plain", "batched"), default="plain")
+    ap.add_argument("--form", choices=("plain", "batched", "adjoint"), default="plain")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batched form: steps per captured hipGraph")
     ap.add_argument("--seq-steps", type=int, default=20,
@@ -169,6 +239,8 @@ def main():
 
     if args.form == "batched":
         return bench_batched(args)
+    if args.form == "adjoint":
+        return bench_adjoint(args)
 
     import numpy as np
     import torch

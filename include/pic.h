@@ -100,8 +100,9 @@ typedef struct {
     uint32_t flags;        /* enum pic_flag bits                                         */
     int32_t block_threads; /* threads per workgroup of the particle passes: 0 = default
                               (512), else a multiple of 64 in [64, 1024]                  */
-    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default,
-                              min(ceil(N_p / block_threads), 512)                         */
+    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default, with
+                              m = ceil(N_p / block_threads): min(max(ceil(m / 8),
+                              min(m, 64)), 512)                                           */
     int32_t deposit_mode;  /* enum pic_deposit_mode                                      */
     int32_t record_capacity; /* per-step diagnostic records kept on the device: 0 = 4096 */
     int32_t reserved;      /* must be 0                                                  */
@@ -257,6 +258,74 @@ int pic_batch_diagnostics(pic_batch *ctx, int32_t run, pic_diag *out, int64_t ma
                           int64_t *n_written);
 
 int pic_batch_destroy(pic_batch *ctx);
+
+/* ----------------------------------------------------------------- adjoint form
+ * Reverse-mode derivative of an ESEC2 run (1D-1V electrostatic, started from the Gauss
+ * solve) with respect to the parameters of its initial condition, for the loss
+ *     J = loss_weight * sum_{n=1..N} W_E^n,   W_E = (h/2) sum_i E_i^2  (section 5.1).
+ * The initial condition is the one of the paper's Landau / two-stream problems
+ * (section 5): positions from the density 1 + sum_m alpha_m cos(k_m x) by inverse-CDF
+ * sampling of given uniforms u_p (Newton to 1e-15 L), velocities v_b s_p + v_s g_p for
+ * given factors s_p (beam signs) and draws g_p.  The gradient is taken with respect to
+ * (alpha_1 .. alpha_M, v_b, v_s); the sampling is differentiated implicitly,
+ * dx_p/dalpha_m = -sin(k_m x_p) / (k_m (1 + sum_j alpha_j cos(k_j x_p))).
+ *
+ * pic_adj_forward samples, initialises and runs N steps exactly as pic_init + pic_step,
+ * storing the state (x, v, E) every checkpoint_every steps; pic_adj_backward recomputes
+ * each segment from its checkpoint and runs the reverse of the steps, of the Gauss
+ * solve and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in
+ * the derivative. */
+#define PIC_ADJ_MAX_MODES 16
+
+typedef struct {
+    int32_t abi_version;         /* PIC_ABI_VERSION                                       */
+    int32_t shape_order;         /* 1 or 2                                                */
+    int64_t n_particles;         /* >= 1                                                  */
+    int32_t n_cells;             /* as pic_params                                         */
+    int32_t n_steps;             /* N >= 1                                                */
+    int32_t checkpoint_every;    /* K >= 1: stored states at steps 0, K, 2K, ...          */
+    int32_t n_modes;             /* M in [0, PIC_ADJ_MAX_MODES]                           */
+    double  length, dt;
+    double  loss_weight;         /* usually dt (time integral of W_E)                     */
+    double  k[PIC_ADJ_MAX_MODES];/* mode wavenumbers, each a multiple of 2 pi / L         */
+    int32_t block_threads;       /* as pic_params (0 = default)                           */
+    int32_t grid_blocks;         /* as pic_params (0 = default)                           */
+    int32_t reserved[2];         /* 0                                                     */
+} pic_adj_params;
+
+typedef struct {                 /* DEVICE pointers, caller-owned, [N_p] unless stated    */
+    const double *u;             /* uniforms in (0, 1)                                    */
+    const double *s;             /* beam factors s_p                                      */
+    const double *g;             /* spread draws g_p                                      */
+    double *x, *v;               /* state: x^N, v^N after pic_adj_forward                 */
+    double *E;                   /* [3][N_g]: E^N after pic_adj_forward (E_x used)        */
+    double *loss;                /* [1]: J, written by pic_adj_forward                    */
+    double *grad;                /* [M + 2]: dJ/d(alpha_1..alpha_M, v_b, v_s) times
+                                    loss_bar, written by pic_adj_backward                  */
+    void    *workspace;          /* >= pic_adj_workspace_size bytes, 256-byte aligned     */
+    size_t   workspace_bytes;
+} pic_adj_buffers;
+
+typedef struct pic_adj pic_adj;
+
+/* Workspace bytes (0 if the parameters are invalid; pic_last_error(NULL) says why).
+ * About (2 ceil(N / K) + 2 K + 2) * 8 N_p bytes: checkpoints, one segment of states
+ * and the adjoint state. */
+size_t pic_adj_workspace_size(const pic_adj_params *p);
+
+int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_stream,
+                 pic_adj **out);
+
+/* Enqueue the forward run for these parameter values (host arrays/values). */
+int pic_adj_forward(pic_adj *ctx, const double *alpha, double v_beam, double v_spread);
+
+/* Enqueue the reverse sweep for the last forward run; loss_bar scales the gradient. */
+int pic_adj_backward(pic_adj *ctx, double loss_bar);
+
+/* Synchronise and copy the records (as pic_diag, steps 0..N) of the last forward run. */
+int pic_adj_records(pic_adj *ctx, pic_diag *out, int64_t max_records, int64_t *n_written);
+
+int pic_adj_destroy(pic_adj *ctx);
 
 /* Last error message of a context, or of the calling thread's last failed
  * validation/init when ctx is NULL. */

@@ -488,3 +488,200 @@ class PicBatch:
             self.destroy()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------- adjoint form
+ADJ_MAX_MODES = 16
+
+
+class PicAdjParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("shape_order", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("n_cells", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
+                ("n_modes", ctypes.c_int32), ("length", ctypes.c_double),
+                ("dt", ctypes.c_double), ("loss_weight", ctypes.c_double),
+                ("k", ctypes.c_double * ADJ_MAX_MODES), ("block_threads", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class PicAdjBuffers(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("s", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("E", ctypes.c_void_p),
+                ("loss", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+ADJ_EXPORTS = ("pic_adj_workspace_size", "pic_adj_init", "pic_adj_forward", "pic_adj_backward",
+               "pic_adj_records", "pic_adj_destroy")
+
+
+def _load_adj(L):
+    vp = ctypes.c_void_p
+    AP = ctypes.POINTER(PicAdjParams)
+    L.pic_adj_workspace_size.argtypes = [AP]
+    L.pic_adj_workspace_size.restype = ctypes.c_size_t
+    L.pic_adj_init.argtypes = [AP, ctypes.POINTER(PicAdjBuffers), vp, ctypes.POINTER(vp)]
+    L.pic_adj_init.restype = ctypes.c_int
+    L.pic_adj_forward.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                  ctypes.c_double]
+    L.pic_adj_forward.restype = ctypes.c_int
+    L.pic_adj_backward.argtypes = [vp, ctypes.c_double]
+    L.pic_adj_backward.restype = ctypes.c_int
+    L.pic_adj_records.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.pic_adj_records.restype = ctypes.c_int
+    L.pic_adj_destroy.argtypes = [vp]
+    L.pic_adj_destroy.restype = ctypes.c_int
+
+
+_load_adj(lib)
+EXPORTS = EXPORTS + ADJ_EXPORTS
+
+
+def make_adj_params(shape_order, n_particles, n_cells, length, dt, n_steps, checkpoint_every,
+                    ks=(), loss_weight=None, block_threads=0, grid_blocks=0) -> PicAdjParams:
+    p = PicAdjParams()
+    p.abi_version = ABI_VERSION
+    p.shape_order = shape_order
+    p.n_particles, p.n_cells = n_particles, n_cells
+    p.n_steps, p.checkpoint_every = n_steps, checkpoint_every
+    if len(ks) > ADJ_MAX_MODES:
+        raise ValueError(f"at most {ADJ_MAX_MODES} modes")
+    p.n_modes = len(ks)
+    p.length, p.dt = length, dt
+    p.loss_weight = dt if loss_weight is None else loss_weight
+    for m, k in enumerate(ks):
+        p.k[m] = k
+    p.block_threads, p.grid_blocks = block_threads, grid_blocks
+    p.reserved[0] = p.reserved[1] = 0
+    return p
+
+
+def adj_workspace_size(p: PicAdjParams) -> int:
+    return int(lib.pic_adj_workspace_size(ctypes.byref(p)))
+
+
+class PicAdjoint:
+    """Loss J = loss_weight * sum_{n=1..N} W_E^n of an ESEC2 1D-1V run started from the
+    Gauss solve, and its gradient with respect to (alpha_1..alpha_M, v_beam, v_spread).
+
+    ``u``, ``s``, ``g`` ([N_p]) are the uniforms of the inverse-CDF positions, the beam
+    factors and the spread draws (numpy arrays or float64 CUDA tensors)."""
+
+    def __init__(self, shape_order, n_cells, length, dt, n_steps, ks, u, s, g,
+                 checkpoint_every=50, loss_weight=None, block_threads=0, grid_blocks=0,
+                 device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        f64 = dict(dtype=torch.float64, device=device)
+
+        def dev(a):
+            t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a, dtype=np.float64))
+            return t.to(**f64).contiguous()
+        self.u, self.s, self.g = dev(u), dev(s), dev(g)
+        n = self.u.numel()
+        if self.s.numel() != n or self.g.numel() != n:
+            raise ValueError("u, s and g must have the same length")
+        self.n_modes = len(ks)
+        p = make_adj_params(shape_order, n, n_cells, length, dt, n_steps, checkpoint_every,
+                            ks, loss_weight, block_threads, grid_blocks)
+        self.params = p
+        nbytes = adj_workspace_size(p)
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, last_error())
+        self.x = torch.empty(n, **f64)
+        self.v = torch.empty(n, **f64)
+        self.E = torch.zeros(3 * n_cells, **f64)
+        self.loss = torch.zeros(1, **f64)
+        self.grad = torch.zeros(self.n_modes + 2, **f64)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.x.device)
+        torch.cuda.synchronize(self.x.device)
+        b = PicAdjBuffers()
+        b.u, b.s, b.g = self.u.data_ptr(), self.s.data_ptr(), self.g.data_ptr()
+        b.x, b.v, b.E = self.x.data_ptr(), self.v.data_ptr(), self.E.data_ptr()
+        b.loss, b.grad = self.loss.data_ptr(), self.grad.data_ptr()
+        b.workspace, b.workspace_bytes = aligned, nbytes
+        self._buf = b
+        ctx = ctypes.c_void_p()
+        _check(lib.pic_adj_init(ctypes.byref(p), ctypes.byref(b),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    @classmethod
+    def from_workload(cls, wl, checkpoint_every=50, **kw):
+        """For a workload of ``workloads.adjoint_two_stream`` (its draws are in meta)."""
+        m = wl.meta
+        return cls(wl.order, wl.n_cells, wl.length, wl.dt, wl.steps, [k for k, _ in m["modes"]],
+                   m["u"], m["sign"], m["g"], checkpoint_every=checkpoint_every, **kw)
+
+    def forward(self, alpha, v_beam, v_spread, sync=True):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        if a.size != self.n_modes:
+            raise ValueError("one amplitude per mode")
+        rc = lib.pic_adj_forward(self.ctx, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 float(v_beam), float(v_spread))
+        _check(rc)
+        if sync:
+            self.stream.synchronize()
+            return float(self.loss.cpu()[0])
+        return None
+
+    def backward(self, loss_bar=1.0, sync=True):
+        _check(lib.pic_adj_backward(self.ctx, float(loss_bar)))
+        if sync:
+            self.stream.synchronize()
+            return self.grad.cpu().numpy().copy()
+        return None
+
+    def records(self) -> np.ndarray:
+        out = np.zeros(self.params.n_steps + 1, dtype=DIAG_DTYPE)
+        nw = ctypes.c_int64()
+        _check(lib.pic_adj_records(self.ctx, out.ctypes.data, out.size, ctypes.byref(nw)))
+        return out[:nw.value]
+
+    def destroy(self):
+        if getattr(self, "ctx", None):
+            lib.pic_adj_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _make_loss_function():
+    import torch
+
+    class TwoStreamLoss(torch.autograd.Function):
+        """J(theta) with theta = (alpha_1..alpha_M, v_beam, v_spread) as a float64 tensor;
+        the forward runs pic_adj_forward, the backward pic_adj_backward (checkpointed)."""
+
+        @staticmethod
+        def forward(ctx, theta, adj):
+            th = theta.detach().to("cpu", torch.float64).numpy()
+            M = adj.n_modes
+            J = adj.forward(th[:M], th[M], th[M + 1])
+            ctx.adj = adj
+            ctx.theta_device = theta.device
+            return torch.tensor(J, dtype=torch.float64, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g = ctx.adj.backward(float(gJ.detach().cpu()))
+            return torch.as_tensor(g, dtype=torch.float64, device=ctx.theta_device), None
+
+    return TwoStreamLoss
+
+
+def two_stream_loss(theta, adj: PicAdjoint):
+    """Differentiable J(theta) through the hand-written adjoint."""
+    global _LOSS_FN
+    if _LOSS_FN is None:
+        _LOSS_FN = _make_loss_function()
+    return _LOSS_FN.apply(theta, adj)
+
+
+_LOSS_FN = None

@@ -1,0 +1,385 @@
+// Device code of the adjoint (reverse-mode derivative) of an ESEC2 run, 1D-1V
+// electrostatic, for the loss J = lw * sum_{n=1..N} W_E^n (W_E of section 5.1) with
+// respect to the parameters of the initial condition.
+//
+// Reverse of one step n (state n -> n+1), with x*, v*, x^{n+1/2}, E*, E-bar and Gamma
+// recomputed from the stored state of step n and its grids (E^n, j^{n,*}, j^{*,n+1/2}):
+//
+//   R1: per particle, the adjoint of v-dagger from the adjoint of v^{n+1} through
+//       v^{n+1} = Gamma v-dagger and Gamma = sqrt(1 + 2 num / den) (eq. (opt_solution);
+//       a fallback particle has the constant Gamma = 1); deposit dt * vdagger_bar at
+//       x^{n+1/2} into G1 (the adjoint of the averaged field E-bar).
+//   R2: every workgroup forms the adjoint of E^{n+1} (from step n+1, the loss term
+//       lw h E^{n+1} and G1 / 2) and from it the adjoint of the centred current,
+//       jbar2 = -dt (lambda - mean lambda) (Ampere update with its mean removed); per
+//       particle, the adjoints of x^{n+1/2}, v*, x^{n+1} and the predictor gather;
+//       deposit dt/2 * vstar_bar at x* into G2 (the adjoint of E*).
+//   R3: every workgroup forms jbar1 = -dt/2 (G2 - mean G2); per particle, the adjoints
+//       of x* and of the predictor deposit; write the adjoint of (x^n, v^n).  The lead
+//       workgroup stores the adjoint of E^n = lambda' + G1 / 2 + G2 for step n - 1 and
+//       clears the other parity's G1, G2.
+//
+// Gathers and deposits are the forward's (same stencils); their derivatives with
+// respect to the particle position use the derivative of the B-spline weights.
+#pragma once
+
+#include "pic_device.hpp"
+
+namespace pic {
+
+constexpr int kAdjMaxModes = 16;
+
+struct AdjParams {
+    int32_t n_modes;
+    int32_t nparam;        // n_modes + 2 (amplitudes, beam speed, beam spread)
+    double k[kAdjMaxModes], alpha[kAdjMaxModes];
+    double v_beam, v_spread;
+    double lbw;            // loss_bar * lw * h: weight of E^{n+1} in the adjoint of E^{n+1}
+};
+
+struct AdjWork {
+    double *ax, *av;       // [N_p] adjoint of the particle state
+    double *lam[2];        // [N_g] adjoint of E^{n+1} from the later steps (by parity)
+    double *G1[2], *G2[2]; // [N_g] deposits of R1, R2 (by parity)
+    double *rhobar;        // [N_g] Gauss solve of the final lambda (see k_adj_rhobar)
+    double *gpart;         // [nblocks][nparam] per-workgroup gradient partial sums
+};
+
+// Derivative of the B-spline weights of stencil<ORDER> with respect to xi, on the same
+// nodes (first unchanged).
+template <int ORDER> __device__ __forceinline__ Stencil<ORDER> dstencil(double xi);
+
+template <> __device__ __forceinline__ Stencil<1> dstencil<1>(double xi)
+{
+    Stencil<1> s;
+    s.first = (int)floor(xi);
+    s.w[0] = -1.0;
+    s.w[1] = 1.0;
+    return s;
+}
+
+template <> __device__ __forceinline__ Stencil<2> dstencil<2>(double xi)
+{
+    const double f = floor(xi + 0.5);
+    const double d = xi - f;
+    Stencil<2> s;
+    s.first = (int)f - 1;
+    s.w[0] = d - 0.5;
+    s.w[1] = -2.0 * d;
+    s.w[2] = 0.5 + d;
+    return s;
+}
+
+// Gamma and its branch: ok = the root is real (no fallback).
+__device__ __forceinline__ double adj_gamma(double num, double den, double &rho, bool &ok)
+{
+    rho = 2.0 * num / den;
+    const double rr = 1.0 + rho;
+    ok = rr >= 0.0 && isfinite(rr);
+    return ok ? sqrt(rr) : 1.0;
+}
+
+// Everything a reverse pass needs about one particle.  STAGE 1: the adjoint of the
+// averaged-field gather (ebar_b); 2: also the adjoint of the predictor gather (ehat_b)
+// and the partial adjoints of x, v; 3: the complete adjoint of (x^n, v^n).
+template <int ORDER, int STAGE>
+struct AdjOut {
+    Stencil<ORDER> ss, sh;
+    Slots<ORDER> ns, nh;
+    double ebar_b, ehat_b, xb, vb;
+};
+
+// es, eb: predictor and averaged fields; jb2, jb1: current adjoints (ghost-padded LDS
+// tiles).  x, v: state n; axp, avp: adjoint of state n+1; q: w_p / h.
+template <int ORDER, int STAGE>
+__device__ __forceinline__ AdjOut<ORDER, STAGE> adj_particle(const Run &r, double x, double v,
+                                                            double axp, double avp, double q,
+                                                            const double *es, const double *eb,
+                                                            const double *jb2, const double *jb1)
+{
+    AdjOut<ORDER, STAGE> o;
+    // forward recompute (the operations of pass A / pass B)
+    const double xs = fma(r.hdt, v, x);
+    o.ss = stencil<ORDER>(xs * r.inv_h);
+    o.ns = slots_of<ORDER>(o.ss, r.ng);
+    const double vs = fma(r.hdt, gather1<ORDER>(es, o.ss, o.ns), v);
+    const double x1 = fma(r.dt, vs, x);
+    const double xh = 0.5 * (x + x1);
+    o.sh = stencil<ORDER>(xh * r.inv_h);
+    o.nh = slots_of<ORDER>(o.sh, r.ng);
+    const double vd = fma(r.dt, gather1<ORDER>(eb, o.sh, o.nh), v);
+    const double a = vs - 0.5 * (vd + v), b = vd - v;
+    const double num = a * b, den = vd * vd;
+    double rho;
+    bool ok;
+    const double gam = adj_gamma(num, den, rho, ok);
+
+    // v^{n+1} = Gamma vd
+    double vdb = gam * avp;
+    const double gb = avp * vd;
+    double numb = 0.0, denb = 0.0;
+    if (ok) {
+        const double rhob = gb / (2.0 * gam);
+        numb = 2.0 * rhob / den;
+        denb = -rho * rhob / den;
+    }
+    const double ab = numb * b, bb = numb * a;
+    double vsb = ab;
+    vdb += -0.5 * ab + bb + 2.0 * vd * denb;
+    double vb = -0.5 * ab - bb + vdb;           // vd = v + dt Ebar_p
+    o.ebar_b = r.dt * vdb;
+    o.ehat_b = 0.0;
+    o.xb = 0.0;
+    o.vb = vb;
+    if constexpr (STAGE >= 2) {
+        // x^{n+1/2}: averaged-field gather and centred deposit
+        const Stencil<ORDER> dh = dstencil<ORDER>(xh * r.inv_h);
+        const double xhb = r.inv_h * (o.ebar_b * gather1<ORDER>(eb, dh, o.nh)
+                                      + q * vs * gather1<ORDER>(jb2, dh, o.nh));
+        vsb = fma(q, gather1<ORDER>(jb2, o.sh, o.nh), vsb);
+        double x1b = axp + 0.5 * xhb;            // x^{n+1} = wrap(x1): a translation
+        double xb = 0.5 * xhb + x1b;             // x1 = x + dt v*
+        vsb = fma(r.dt, x1b, vsb);
+        vb += vsb;                               // v* = v + dt/2 E-hat
+        o.ehat_b = r.hdt * vsb;
+        o.xb = xb;
+        o.vb = vb;
+        if constexpr (STAGE >= 3) {
+            // x*: predictor gather and predictor deposit
+            const Stencil<ORDER> ds = dstencil<ORDER>(xs * r.inv_h);
+            const double xsb = r.inv_h * (o.ehat_b * gather1<ORDER>(es, ds, o.ns)
+                                          + q * v * gather1<ORDER>(jb1, ds, o.ns));
+            vb = fma(q, gather1<ORDER>(jb1, o.ss, o.ns), vb);
+            o.xb = xb + xsb;
+            o.vb = fma(r.hdt, xsb, vb);
+        }
+    }
+    return o;
+}
+
+// The forward fields of step n in LDS: es (E*), eb (E-bar) ghost-padded, e1 (E^{n+1}).
+__device__ __forceinline__ void adj_fields(const Run &r, const Work &wk, const double *En,
+                                           const double *J1, const double *J2, double *es,
+                                           double *eb, double *e1, double *red)
+{
+    // electrostatic: the magnetic tiles and the Crank-Nicolson scratch are not touched
+    predictor_fields(r, En, nullptr, J1, es, es, red);
+    field_update(r, wk, En, nullptr, J2, e1, e1, eb, eb, e1, red);
+    __syncthreads();
+    ghost_fill(es, 1, r.ng, r.tw);
+    ghost_fill(eb, 1, r.ng, r.tw);
+}
+
+// lt = lambda + lbw E^{n+1} + G1 / 2 into lt (LDS [ng]); jb2 = -dt (lt - mean lt) into
+// the tile interior.  e1 must be visible.
+__device__ __forceinline__ void adj_current2(const Run &r, const AdjParams &ap, const double *lam,
+                                             const double *G1, const double *e1, double *lt,
+                                             double *jb2, double *red)
+{
+    const int ng = r.ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        lt[i] = fma(ap.lbw, e1[i], lam[i]) + 0.5 * G1[i];
+    __syncthreads();
+    const double m = block_mean(lt, ng, red);
+    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        jb2[kGhost + i] = -r.dt * (lt[i] - m);
+}
+
+// LDS of the reverse passes: es | eb | jb2 | jb1-or-tile (tw each) | e1 | lt (ng each)
+__host__ __device__ constexpr size_t adj_lds_doubles(int tw, int ng) { return 4 * (size_t)tw + 2 * (size_t)ng; }
+
+template <int ORDER, int STAGE>
+__global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw, AdjParams ap,
+                                                      int q, const double *__restrict__ X,
+                                                      const double *__restrict__ V,
+                                                      const double *__restrict__ En,
+                                                      const double *__restrict__ J1,
+                                                      const double *__restrict__ J2)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int ng = r.ng, tw = r.tw;
+    double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
+    double *e1 = t4 + tw, *lt = e1 + ng;
+    adj_fields(r, wk, En, J1, J2, es, eb, e1, red);
+    if constexpr (STAGE >= 2) {
+        __syncthreads();
+        adj_current2(r, ap, aw.lam[q], aw.G1[q], e1, lt, jb2, red);
+    }
+    if constexpr (STAGE == 3) {
+        const double m = block_mean(aw.G2[q], ng, red);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            t4[kGhost + i] = -r.hdt * (aw.G2[q][i] - m);
+        if (blockIdx.x == 0) {
+            // adjoint of E^n for step n - 1; clear the deposits of the next reverse step
+            for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+                aw.lam[q ^ 1][i] = lt[i] + 0.5 * aw.G1[q][i] + aw.G2[q][i];
+                aw.G1[q ^ 1][i] = 0.0;
+                aw.G2[q ^ 1][i] = 0.0;
+            }
+        }
+    } else {
+        tile_zero(t4, tw);
+    }
+    __syncthreads();
+    if constexpr (STAGE >= 2)
+        ghost_fill(jb2, 1, ng, tw);
+    if constexpr (STAGE == 3)
+        ghost_fill(t4, 1, ng, tw);
+    __syncthreads();
+
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    Depo<ORDER, 1, 0> dep;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double x = X[p], v = V[p], axp = aw.ax[p], avp = aw.av[p];
+        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+        const AdjOut<ORDER, STAGE> o =
+            adj_particle<ORDER, STAGE>(r, x, v, axp, avp, q, es, eb, jb2, t4);
+        if constexpr (STAGE == 1) {
+            const double c[1] = {o.ebar_b};
+            dep.add(t4, tw, ng, o.sh, c);
+        } else if constexpr (STAGE == 2) {
+            const double c[1] = {o.ehat_b};
+            dep.add(t4, tw, ng, o.ss, c);
+        } else {
+            aw.ax[p] = o.xb;
+            aw.av[p] = o.vb;
+        }
+    }
+    if constexpr (STAGE < 3) {
+        __syncthreads();
+        tile_flush(t4, STAGE == 1 ? aw.G1[q] : aw.G2[q], 1, ng, tw);
+    }
+}
+
+// Inverse-CDF positions for the density 1 + sum_m alpha_m cos(k_m x) on [0, L): Newton
+// on x + sum_m (alpha_m / k_m) sin(k_m x) = u L from x = u L, to 1e-15 L; velocities
+// v_b s_p + v_s g_p.
+__global__ __launch_bounds__(1024) void k_adj_sample(Run r, AdjParams ap, const double *__restrict__ U,
+                                                     const double *__restrict__ S,
+                                                     const double *__restrict__ Gn, double *X,
+                                                     double *V)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < r.np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const double target = U[p] * r.L;
+        double x = target;
+        for (int it = 0; it < 60 && ap.n_modes > 0; ++it) {
+            double f = x - target, d = 1.0;
+            for (int m = 0; m < ap.n_modes; ++m) {
+                double sn, cs;
+                sincos(ap.k[m] * x, &sn, &cs);
+                f += ap.alpha[m] / ap.k[m] * sn;
+                d += ap.alpha[m] * cs;
+            }
+            const double step = f / d;
+            x -= step;
+            if (fabs(step) < 1e-15 * r.L)
+                break;
+        }
+        if (x >= r.L)
+            x -= r.L;
+        if (x < 0.0)
+            x += r.L;
+        X[p] = x;
+        V[p] = fma(ap.v_beam, S[p], ap.v_spread * Gn[p]);
+    }
+}
+
+// rhobar = Gauss solve of lambda^0 (one workgroup): the Gauss map rho -> E is a real
+// circulant whose eigenvalues 1 / (i k_m) are imaginary, so its transpose is its
+// negative and the adjoint of rho is -rhobar.
+__global__ __launch_bounds__(1024) void k_adj_rhobar(Run r, Work wk, AdjWork aw, int q)
+{
+    extern __shared__ double smem[];
+    Work t = wk;
+    t.J2[0] = aw.lam[q];
+    t.E = aw.rhobar;
+    gauss_body(r, t, smem);
+}
+
+// Per workgroup: the adjoint of x^0 gets the Gauss start's term, then the partial sums
+// of the gradient: amplitudes (implicit differentiation of the inverse CDF:
+// dx/dalpha_m = -sin(k_m x) / (k_m (1 + sum_j alpha_j cos(k_j x)))), beam speed
+// (sum vbar s), beam spread (sum vbar g).
+template <int ORDER>
+__global__ __launch_bounds__(1024) void k_adj_grad(Run r, AdjWork aw, AdjParams ap,
+                                                   const double *__restrict__ X0,
+                                                   const double *__restrict__ S,
+                                                   const double *__restrict__ Gn)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int ng = r.ng, tw = r.tw;
+    double *rb = smem;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        rb[kGhost + i] = -aw.rhobar[i];
+    __syncthreads();
+    ghost_fill(rb, 1, ng, tw);
+    __syncthreads();
+    double acc[kAdjMaxModes + 2];
+    for (int m = 0; m < ap.nparam; ++m)
+        acc[m] = 0.0;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double x = X0[p];
+        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+        const Stencil<ORDER> s = stencil<ORDER>(x * r.inv_h);
+        const Slots<ORDER> n = slots_of<ORDER>(s, ng);
+        const Stencil<ORDER> d = dstencil<ORDER>(x * r.inv_h);
+        const double xb = aw.ax[p] + q * r.inv_h * gather1<ORDER>(rb, d, n);
+        double dens = 1.0;
+        for (int m = 0; m < ap.n_modes; ++m)
+            dens += ap.alpha[m] * cos(ap.k[m] * x);
+        for (int m = 0; m < ap.n_modes; ++m)
+            acc[m] -= xb * sin(ap.k[m] * x) / (ap.k[m] * dens);
+        acc[ap.n_modes] = fma(aw.av[p], S[p], acc[ap.n_modes]);
+        acc[ap.n_modes + 1] = fma(aw.av[p], Gn[p], acc[ap.n_modes + 1]);
+    }
+    for (int m = 0; m < ap.nparam; ++m) {
+        const double t = block_sum(acc[m], red);
+        if (threadIdx.x == 0)
+            aw.gpart[(size_t)blockIdx.x * ap.nparam + m] = t;
+    }
+}
+
+// Gradient = sum of the workgroup partials in workgroup order (one workgroup).
+__global__ void k_adj_grad_final(AdjWork aw, int nblocks, int nparam, double *grad)
+{
+    __shared__ double red[16];
+    for (int m = 0; m < nparam; ++m) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+            s += aw.gpart[(size_t)b * nparam + m];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0)
+            grad[m] = s;
+    }
+}
+
+// J = lw * sum_{n=1..N} W_E^n from the record ring (one workgroup, fixed order).
+__global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, double *loss)
+{
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t n = 1 + threadIdx.x; n <= nsteps; n += blockDim.x)
+        s += wk.rec[n % rec_cap].field_e;
+    s = block_sum(s, red);
+    if (threadIdx.x == 0)
+        *loss = lw * s;
+}
+
+// Copy of the fields of one step into the segment store: E^n, j^{n,*}, j^{*,n+1/2}.
+__global__ void k_adj_save_grids(const double *E, const double *J1, const double *J2, int ng,
+                                 double *dst)
+{
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        dst[i] = E[i];
+        dst[ng + i] = J1[i];
+        dst[2 * ng + i] = J2[i];
+    }
+}
+
+}  // namespace pic

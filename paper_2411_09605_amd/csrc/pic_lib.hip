@@ -13,6 +13,7 @@
 
 #include "../../include/pic.h"
 #include "pic_device.hpp"
+#include "pic_adjoint.hpp"
 
 using namespace pic;
 
@@ -43,7 +44,13 @@ int records_of(const pic_params *p) { return p->record_capacity ? p->record_capa
 int blocks_of(const pic_params *p, int64_t *chunk_out)
 {
     const int t = threads_of(p);
-    int64_t nb = p->grid_blocks ? p->grid_blocks : std::min<int64_t>((p->n_particles + t - 1) / t, kDefaultGrid);
+    // default: about 8 batches of particles per thread, at least min(N / t, 64) and at
+    // most kDefaultGrid workgroups (fewer workgroups, fewer prologues and tile flushes)
+    const int64_t per_thread = (p->n_particles + t - 1) / t;
+    int64_t nb = p->grid_blocks ? p->grid_blocks
+                                : std::min<int64_t>(std::max<int64_t>((per_thread + 7) / 8,
+                                                                      std::min<int64_t>(per_thread, 64)),
+                                                    kDefaultGrid);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid));
     // chunks are whole multiples of the batch a workgroup loads at once (4 particles
     // per thread), so only the last workgroup has a ragged tail
@@ -339,6 +346,52 @@ void rebin(pic_ctx *c)
         hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, c->stream, w.wcur, w.w2, r.np);
 }
 
+// Scalars and workspace arrays of one run (pic_init and the adjoint form).
+void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, char *ws, Run &r,
+                   Work &w)
+{
+    r.np = p->n_particles;
+    r.vstride = p->n_particles;
+    r.ng = p->n_cells;
+    r.nv = p->nv;
+    r.nblocks = blocks_of(p, &r.chunk);
+    r.scheme = p->scheme;
+    r.tw = (int32_t)tile_width(p);
+    r.rec_cap = records_of(p);
+    r.L = p->length;
+    r.h = p->length / p->n_cells;
+    r.inv_h = p->n_cells / p->length;
+    r.dt = p->dt;
+    r.hdt = 0.5 * p->dt;
+    r.c2 = p->c * p->c;
+    r.qs = 1.0 / r.h;
+    r.wu = p->length / (double)p->n_particles;
+    for (int i = 0; i < 3; ++i)
+        r.bext[i] = p->nv == 3 ? p->b_ext[i] : 0.0;
+    r.w = b->w;
+
+    w.E = b->E;
+    w.B = b->B;
+    for (int k = 0; k < 2; ++k) {
+        w.Ef[k] = (double *)(ws + L.Ef[k]);
+        w.Bf[k] = (double *)(ws + L.Bf[k]);
+        w.J1[k] = (double *)(ws + L.J1[k]);
+        w.J2[k] = (double *)(ws + L.J2[k]);
+    }
+    w.cninv = (double *)(ws + L.cninv);
+    w.spart = (double *)(ws + L.spart);
+    w.st = (DevState *)(ws + L.st);
+    w.rec = (DevRecord *)(ws + L.rec);
+    const bool rb = p->rebin_every > 0;
+    w.x2 = rb ? (double *)(ws + L.x2) : nullptr;
+    w.v2 = rb ? (double *)(ws + L.v2) : nullptr;
+    w.id2 = (rb && (p->flags & PIC_F_TRACK_IDS)) ? (int64_t *)(ws + L.id2) : nullptr;
+    w.wcur = (rb && b->w) ? (double *)(ws + L.wcur) : nullptr;
+    w.w2 = (rb && b->w) ? (double *)(ws + L.w2) : nullptr;
+    w.hist = rb ? (int64_t *)(ws + L.hist) : nullptr;
+    w.segsum = rb ? (int64_t *)(ws + L.segsum) : nullptr;
+}
+
 int grid_threads(const pic_ctx *c)
 {
     int t = 64;
@@ -469,49 +522,9 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
         c->prof_n[k] = 0;
     }
 
+    bind_run_work(p, b, L, (char *)b->workspace, c->run, c->wk);
     Run &r = c->run;
-    r.np = p->n_particles;
-    r.vstride = p->n_particles;
-    r.ng = p->n_cells;
-    r.nv = p->nv;
-    r.nblocks = blocks_of(p, &r.chunk);
-    r.scheme = p->scheme;
-    r.tw = (int32_t)tile_width(p);
-    r.rec_cap = records_of(p);
-    r.L = p->length;
-    r.h = p->length / p->n_cells;
-    r.inv_h = p->n_cells / p->length;
-    r.dt = p->dt;
-    r.hdt = 0.5 * p->dt;
-    r.c2 = p->c * p->c;
-    r.qs = 1.0 / r.h;
-    r.wu = p->length / (double)p->n_particles;
-    for (int i = 0; i < 3; ++i)
-        r.bext[i] = p->nv == 3 ? p->b_ext[i] : 0.0;
-    r.w = b->w;
-
-    char *ws = (char *)b->workspace;
     Work &w = c->wk;
-    w.E = b->E;
-    w.B = b->B;
-    for (int k = 0; k < 2; ++k) {
-        w.Ef[k] = (double *)(ws + L.Ef[k]);
-        w.Bf[k] = (double *)(ws + L.Bf[k]);
-        w.J1[k] = (double *)(ws + L.J1[k]);
-        w.J2[k] = (double *)(ws + L.J2[k]);
-    }
-    w.cninv = (double *)(ws + L.cninv);
-    w.spart = (double *)(ws + L.spart);
-    w.st = (DevState *)(ws + L.st);
-    w.rec = (DevRecord *)(ws + L.rec);
-    const bool rb = p->rebin_every > 0;
-    w.x2 = rb ? (double *)(ws + L.x2) : nullptr;
-    w.v2 = rb ? (double *)(ws + L.v2) : nullptr;
-    w.id2 = (rb && (p->flags & PIC_F_TRACK_IDS)) ? (int64_t *)(ws + L.id2) : nullptr;
-    w.wcur = (rb && b->w) ? (double *)(ws + L.wcur) : nullptr;
-    w.w2 = (rb && b->w) ? (double *)(ws + L.w2) : nullptr;
-    w.hist = rb ? (int64_t *)(ws + L.hist) : nullptr;
-    w.segsum = rb ? (int64_t *)(ws + L.segsum) : nullptr;
     if (w.wcur) {
         // the library permutes its own copy of the weights
         hipLaunchKernelGGL(k_copy_f64, dim3(1024), dim3(256), 0, c->stream, w.wcur, b->w, r.np);
@@ -1147,6 +1160,398 @@ int pic_batch_destroy(pic_batch *c)
         (void)hipGraphExecDestroy(c->exec);
     if (c->graph)
         (void)hipGraphDestroy(c->graph);
+    delete c;
+    return PIC_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// Adjoint form
+// =====================================================================================
+namespace {
+
+struct AdjLayout {
+    Layout fwd;                      // the forward run's workspace (first)
+    size_t ckx, ckv, ckE;            // checkpoints [ncp][N_p], [ncp][N_p], [ncp][N_g]
+    size_t segx, segv, segg;         // one segment: [K][N_p] x2, [K][3][N_g]
+    size_t ax, av, lam, G1, G2, rhobar, gpart;
+    size_t total;
+    int ncp;
+};
+
+pic_params adj_forward_params(const pic_adj_params *p)
+{
+    pic_params q;
+    std::memset(&q, 0, sizeof q);
+    q.abi_version = PIC_ABI_VERSION;
+    q.nv = 1;
+    q.scheme = PIC_ESEC2;
+    q.shape_order = p->shape_order;
+    q.n_particles = p->n_particles;
+    q.n_cells = p->n_cells;
+    q.length = p->length;
+    q.dt = p->dt;
+    q.c = 1.0;
+    q.flags = PIC_F_INIT_GAUSS;
+    q.block_threads = p->block_threads;
+    q.grid_blocks = p->grid_blocks;
+    q.record_capacity = p->n_steps + 1;
+    return q;
+}
+
+size_t adj_lds(const pic_params *q)
+{
+    return adj_lds_doubles((int)tile_width(q), q->n_cells) * 8;
+}
+
+int adj_validate(const pic_adj_params *p)
+{
+    if (!p)
+        return fail(nullptr, PIC_EINVAL, "params is NULL");
+    if (p->n_steps < 1 || p->checkpoint_every < 1)
+        return fail(nullptr, PIC_EINVAL, "n_steps and checkpoint_every must be >= 1");
+    if (p->n_modes < 0 || p->n_modes > PIC_ADJ_MAX_MODES)
+        return fail(nullptr, PIC_EINVAL, "n_modes must be in [0, %d]", PIC_ADJ_MAX_MODES);
+    for (int m = 0; m < p->n_modes; ++m)
+        if (!std::isfinite(p->k[m]) || p->k[m] == 0.0)
+            return fail(nullptr, PIC_EINVAL, "mode wavenumbers must be finite and non-zero");
+    if (!std::isfinite(p->loss_weight))
+        return fail(nullptr, PIC_EINVAL, "loss_weight must be finite");
+    if (p->reserved[0] || p->reserved[1])
+        return fail(nullptr, PIC_EINVAL, "reserved must be 0");
+    const pic_params q = adj_forward_params(p);
+    int rc = validate(&q, nullptr);
+    if (rc != PIC_OK)
+        return rc;
+    if (adj_lds(&q) > kMaxLds)
+        return fail(nullptr, PIC_EUNSUPPORTED, "n_cells = %d is too large for the reverse passes",
+                    p->n_cells);
+    return PIC_OK;
+}
+
+AdjLayout adj_layout(const pic_adj_params *p)
+{
+    AdjLayout A;
+    const pic_params q = adj_forward_params(p);
+    A.fwd = layout_of(&q);
+    size_t o = A.fwd.total;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, kAlign); return at; };
+    const size_t np = (size_t)p->n_particles, ng = (size_t)p->n_cells;
+    const size_t K = (size_t)std::min(p->checkpoint_every, p->n_steps);
+    A.ncp = (p->n_steps + p->checkpoint_every - 1) / p->checkpoint_every;
+    A.ckx = take((size_t)A.ncp * np * 8);
+    A.ckv = take((size_t)A.ncp * np * 8);
+    A.ckE = take((size_t)A.ncp * ng * 8);
+    A.segx = take(K * np * 8);
+    A.segv = take(K * np * 8);
+    A.segg = take(K * 3 * ng * 8);
+    A.ax = take(np * 8);
+    A.av = take(np * 8);
+    A.lam = take(2 * ng * 8);
+    A.G1 = take(2 * ng * 8);
+    A.G2 = take(2 * ng * 8);
+    A.rhobar = take(ng * 8);
+    A.gpart = take((size_t)blocks_of(&q, nullptr) * (PIC_ADJ_MAX_MODES + 2) * 8);
+    A.total = o;
+    return A;
+}
+
+}  // namespace
+
+struct pic_adj {
+    pic_adj_params p;
+    pic_adj_buffers b;
+    pic_params q;                 // the forward run
+    hipStream_t stream;
+    AdjLayout A;
+    Run run;
+    Work wk;
+    AdjWork aw;
+    AdjParams ap;
+    int threads;
+    int forward_done;
+    int poisoned;
+    std::string err;
+    double *ckx, *ckv, *ckE, *segx, *segv, *segg;
+};
+
+namespace {
+
+int adj_check(pic_adj *c, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->poisoned = 1;
+        return fail(&c->err, PIC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+void adj_copy(pic_adj *c, double *dst, const double *src, int64_t n)
+{
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
+                       c->stream, dst, src, n);
+}
+
+template <int ORDER>
+void adj_pass_a(pic_adj *c, int par, int64_t step, const double *X, const double *V)
+{
+    hipLaunchKernelGGL((k_pass_a<ORDER, 1, false, 0>), dim3(c->run.nblocks), dim3(c->threads),
+                       lds_pass_a(&c->q), c->stream, c->run, c->wk, par, step, X, V);
+}
+
+template <int ORDER>
+void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *Xo, double *Vo)
+{
+    hipLaunchKernelGGL((k_pass_b<ORDER, 1, false, true, 0>), dim3(c->run.nblocks), dim3(c->threads),
+                       lds_pass_b(&c->q), c->stream, c->run, c->wk, par, X, V, Xo, Vo);
+}
+
+template <int ORDER>
+void adj_predeposit(pic_adj *c, const double *X, const double *V)
+{
+    hipLaunchKernelGGL((k_predeposit<ORDER, 1, false>), dim3(c->run.nblocks), dim3(c->threads),
+                       tile_width(&c->q) * 8, c->stream, c->run, c->wk, X, V);
+}
+
+template <int ORDER, int STAGE>
+void adj_rev(pic_adj *c, int q, const double *X, const double *V, const double *g)
+{
+    const int ng = c->p.n_cells;
+    hipLaunchKernelGGL((k_adj_reverse<ORDER, STAGE>), dim3(c->run.nblocks), dim3(c->threads), adj_lds(&c->q),
+                       c->stream, c->run, c->wk, c->aw, c->ap, q, X, V, g, g + ng, g + 2 * ng);
+}
+
+int grid_threads_of(int ng)
+{
+    int t = 64;
+    while (t < ng && t < 1024)
+        t *= 2;
+    return std::max(t, 256);
+}
+
+template <int ORDER>
+void adj_forward_launches(pic_adj *c)
+{
+    const Run &r = c->run;
+    const Work &w = c->wk;
+    const int ng = c->p.n_cells, gt = grid_threads_of(ng);
+    double *X = c->b.x, *V = c->b.v;
+    const unsigned sg = (unsigned)std::min<int64_t>((r.np + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_adj_sample, dim3(sg), dim3(256), 0, c->stream, r, c->ap, c->b.u, c->b.s, c->b.g,
+                       X, V);
+    // as pic_init: clear fields and currents, wrap, Gauss start, predictor deposit
+    fill_range(c->stream, w.Ef[0], (int64_t)(c->A.fwd.cninv - c->A.fwd.Ef[0]) / 8);
+    fill_range(c->stream, c->b.E + ng, 2 * (int64_t)ng);
+    hipLaunchKernelGGL((k_init_particles<1>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w, X, V);
+    hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(r.nblocks), dim3(c->threads), tile_width(&c->q) * 8,
+                       c->stream, r, w, X);
+    hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w);
+    adj_predeposit<ORDER>(c, X, V);
+    hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
+    const int K = c->p.checkpoint_every;
+    for (int64_t n = 0; n < c->p.n_steps; ++n) {
+        const int par = (int)(n & 1);
+        if (n % K == 0) {
+            const int64_t cp = n / K;
+            adj_copy(c, c->ckx + cp * r.np, X, r.np);
+            adj_copy(c, c->ckv + cp * r.np, V, r.np);
+            adj_copy(c, c->ckE + cp * ng, w.Ef[par], ng);
+        }
+        adj_pass_a<ORDER>(c, par, n, X, V);
+        adj_pass_b<ORDER>(c, par, X, V, X, V);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(gt), 0, c->stream, r, w, (int)(c->p.n_steps & 1),
+                       (int64_t)c->p.n_steps);
+    hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(256), 0, c->stream, w, r.rec_cap, (int64_t)c->p.n_steps,
+                       c->p.loss_weight, c->b.loss);
+}
+
+template <int ORDER>
+void adj_backward_launches(pic_adj *c)
+{
+    const Run &r = c->run;
+    const Work &w = c->wk;
+    const int ng = c->p.n_cells, N = c->p.n_steps, K = c->p.checkpoint_every;
+    fill_range(c->stream, c->aw.ax, r.np);
+    fill_range(c->stream, c->aw.av, r.np);
+    fill_range(c->stream, c->aw.lam[0], 2 * (int64_t)ng);    // both parities
+    fill_range(c->stream, c->aw.G1[0], 2 * (int64_t)ng);
+    fill_range(c->stream, c->aw.G2[0], 2 * (int64_t)ng);
+    int q = 0;
+    for (int cp = c->A.ncp - 1; cp >= 0; --cp) {
+        const int s0 = cp * K, len = std::min(K, N - s0);
+        // recompute the segment from its checkpoint, keeping every state and grid
+        adj_copy(c, c->segx, c->ckx + (int64_t)cp * r.np, r.np);
+        adj_copy(c, c->segv, c->ckv + (int64_t)cp * r.np, r.np);
+        adj_copy(c, w.Ef[0], c->ckE + (int64_t)cp * ng, ng);
+        fill_range(c->stream, w.J1[0], ng);
+        fill_range(c->stream, w.J2[0], ng);
+        adj_predeposit<ORDER>(c, c->segx, c->segv);
+        for (int j = 0; j < len; ++j) {
+            const int par = j & 1;
+            double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
+            adj_pass_a<ORDER>(c, par, -1, Xj, Vj);          // step -1: no record
+            hipLaunchKernelGGL(k_adj_save_grids, dim3(1), dim3(256), 0, c->stream, w.Ef[par], w.J1[par],
+                               w.J2[par], ng, c->segg + (int64_t)j * 3 * ng);
+            if (j + 1 < len)
+                adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np);
+        }
+        // reverse steps of the segment
+        for (int j = len - 1; j >= 0; --j) {
+            const double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
+            const double *g = c->segg + (int64_t)j * 3 * ng;
+            adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
+            adj_rev<ORDER, 2>(c, q, Xj, Vj, g);
+            adj_rev<ORDER, 3>(c, q, Xj, Vj, g);
+            q ^= 1;
+        }
+    }
+    // reverse of the Gauss start and of the sampling
+    const int gt = grid_threads_of(ng);
+    hipLaunchKernelGGL(k_adj_rhobar, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w, c->aw, q);
+    hipLaunchKernelGGL((k_adj_grad<ORDER>), dim3(r.nblocks), dim3(c->threads), tile_width(&c->q) * 8,
+                       c->stream, r, c->aw, c->ap, c->ckx, c->b.s, c->b.g);
+    hipLaunchKernelGGL(k_adj_grad_final, dim3(1), dim3(256), 0, c->stream, c->aw, r.nblocks, c->ap.nparam,
+                       c->b.grad);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_adj_workspace_size(const pic_adj_params *p)
+{
+    if (adj_validate(p) != PIC_OK)
+        return 0;
+    return adj_layout(p).total;
+}
+
+int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_stream, pic_adj **out)
+{
+    if (!out)
+        return fail(nullptr, PIC_EINVAL, "out is NULL");
+    int rc = adj_validate(p);
+    if (rc != PIC_OK)
+        return rc;
+    if (!b || !b->u || !b->s || !b->g || !b->x || !b->v || !b->E || !b->loss || !b->grad ||
+        !b->workspace)
+        return fail(nullptr, PIC_EINVAL, "every buffer must be non-NULL");
+    if ((uintptr_t)b->workspace % kAlign)
+        return fail(nullptr, PIC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    const AdjLayout A = adj_layout(p);
+    if (b->workspace_bytes < A.total)
+        return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, A.total);
+    pic_adj *c = new (std::nothrow) pic_adj();
+    if (!c)
+        return fail(nullptr, PIC_ENOMEM, "out of host memory");
+    c->p = *p;
+    c->b = *b;
+    c->q = adj_forward_params(p);
+    c->stream = (hipStream_t)hip_stream;
+    c->A = A;
+    c->threads = threads_of(&c->q);
+    c->forward_done = 0;
+    c->poisoned = 0;
+    char *ws = (char *)b->workspace;
+    pic_buffers fb;
+    std::memset(&fb, 0, sizeof fb);
+    fb.x = b->x;
+    fb.v = b->v;
+    fb.E = b->E;
+    fb.workspace = b->workspace;
+    fb.workspace_bytes = A.fwd.total;
+    bind_run_work(&c->q, &fb, A.fwd, ws, c->run, c->wk);
+    c->ckx = (double *)(ws + A.ckx);
+    c->ckv = (double *)(ws + A.ckv);
+    c->ckE = (double *)(ws + A.ckE);
+    c->segx = (double *)(ws + A.segx);
+    c->segv = (double *)(ws + A.segv);
+    c->segg = (double *)(ws + A.segg);
+    AdjWork &aw = c->aw;
+    const int ng = p->n_cells;
+    aw.ax = (double *)(ws + A.ax);
+    aw.av = (double *)(ws + A.av);
+    for (int k = 0; k < 2; ++k) {
+        aw.lam[k] = (double *)(ws + A.lam) + k * ng;
+        aw.G1[k] = (double *)(ws + A.G1) + k * ng;
+        aw.G2[k] = (double *)(ws + A.G2) + k * ng;
+    }
+    aw.rhobar = (double *)(ws + A.rhobar);
+    aw.gpart = (double *)(ws + A.gpart);
+    std::memset(&c->ap, 0, sizeof c->ap);
+    c->ap.n_modes = p->n_modes;
+    c->ap.nparam = p->n_modes + 2;
+    for (int m = 0; m < p->n_modes; ++m)
+        c->ap.k[m] = p->k[m];
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_adj_forward(pic_adj *c, const double *alpha, double v_beam, double v_spread)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if ((c->p.n_modes > 0 && !alpha) || !std::isfinite(v_beam) || !std::isfinite(v_spread))
+        return fail(&c->err, PIC_EINVAL, "alpha must be given and the speeds finite");
+    double asum = 0.0;
+    for (int m = 0; m < c->p.n_modes; ++m) {
+        if (!std::isfinite(alpha[m]))
+            return fail(&c->err, PIC_EINVAL, "alpha must be finite");
+        asum += std::fabs(alpha[m]);
+        c->ap.alpha[m] = alpha[m];
+    }
+    if (asum >= 1.0)
+        return fail(&c->err, PIC_EINVAL, "sum |alpha_m| must be < 1 (positive density)");
+    c->ap.v_beam = v_beam;
+    c->ap.v_spread = v_spread;
+    if (c->p.shape_order == 1)
+        adj_forward_launches<1>(c);
+    else
+        adj_forward_launches<2>(c);
+    c->forward_done = 1;
+    return adj_check(c, "pic_adj_forward launches");
+}
+
+int pic_adj_backward(pic_adj *c, double loss_bar)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if (!c->forward_done)
+        return fail(&c->err, PIC_ESTATE, "pic_adj_backward needs a forward run first");
+    if (!std::isfinite(loss_bar))
+        return fail(&c->err, PIC_EINVAL, "loss_bar must be finite");
+    c->ap.lbw = loss_bar * c->p.loss_weight * c->run.h;
+    if (c->p.shape_order == 1)
+        adj_backward_launches<1>(c);
+    else
+        adj_backward_launches<2>(c);
+    return adj_check(c, "pic_adj_backward launches");
+}
+
+int pic_adj_records(pic_adj *c, pic_diag *out, int64_t max_records, int64_t *n_written)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if (!n_written || (max_records > 0 && !out))
+        return fail(&c->err, PIC_EINVAL, "out and n_written must be non-NULL");
+    *n_written = 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return adj_check(c, "pic_adj_records sync");
+    if (!c->forward_done)
+        return PIC_OK;
+    const int64_t n = std::min<int64_t>(c->p.n_steps + 1, max_records);
+    if (n > 0 && hipMemcpy(out, c->wk.rec, (size_t)n * sizeof(DevRecord), hipMemcpyDeviceToHost) != hipSuccess)
+        return adj_check(c, "pic_adj_records copy");
+    *n_written = n;
+    return PIC_OK;
+}
+
+int pic_adj_destroy(pic_adj *c)
+{
+    if (!c)
+        return PIC_ESTATE;
     delete c;
     return PIC_OK;
 }

@@ -129,3 +129,39 @@ def test_batch_null_handling():
     assert lib.pic_batch_step(None, 1) == -4
     assert lib.pic_batch_destroy(None) == -4
     assert lib.pic_batch_workspace_size(None) == 0
+
+
+def _adj(**kw):
+    import paper_2411_09605_amd.binding as B
+    base = dict(shape_order=2, n_particles=10_000, n_cells=64, length=31.4, dt=0.05,
+                n_steps=100, checkpoint_every=10, ks=[0.2 * m for m in range(1, 9)])
+    base.update(kw)
+    return B.make_adj_params(**base)
+
+
+def test_adjoint_validation_and_workspace():
+    import paper_2411_09605_amd.binding as B
+    for kw in [{}, dict(shape_order=1), dict(checkpoint_every=1), dict(checkpoint_every=1000),
+               dict(ks=[]), dict(n_steps=1)]:
+        assert B.adj_workspace_size(_adj(**kw)) > 0, (kw, B.last_error())
+    # checkpoints every step cost more than every 10 steps; one segment of 100 states too
+    assert B.adj_workspace_size(_adj(checkpoint_every=1)) > B.adj_workspace_size(_adj())
+    assert B.adj_workspace_size(_adj(checkpoint_every=100)) > B.adj_workspace_size(_adj())
+    for kw in [dict(n_steps=0), dict(checkpoint_every=0), dict(ks=[0.0]),
+               dict(shape_order=3), dict(n_cells=2), dict(dt=-1.0), dict(n_particles=0),
+               dict(loss_weight=float("nan"))]:
+        assert B.adj_workspace_size(_adj(**kw)) == 0, kw
+        assert B.last_error()
+    p = _adj()
+    p.reserved[1] = 3
+    assert B.adj_workspace_size(p) == 0
+    p = _adj()
+    p.n_modes = 17
+    assert B.adj_workspace_size(p) == 0
+
+
+def test_adjoint_null_handling():
+    import paper_2411_09605_amd.binding as B
+    assert B.lib.pic_adj_forward(None, None, 0.0, 0.0) == -4
+    assert B.lib.pic_adj_backward(None, 1.0) == -4
+    assert B.lib.pic_adj_destroy(None) == -4

@@ -98,8 +98,7 @@ def test_launch_shapes_agree():
     wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
     for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
         gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
-    # default shape: 512 threads, min(ceil(N / 512), 512) workgroups, whole 4-particle
-    # batches per thread in every chunk
+    # default shape: 512 threads, whole 4-particle batches per thread in every chunk
     from paper_2411_09605_amd import Pic
     t, g, c = Pic.from_workload(wl).launch_shape()
     assert t == 512 and c % (4 * 512) == 0 and (g - 1) * c < wl.n_particles <= g * c
