@@ -76,9 +76,13 @@ enum pic_flag {
 enum pic_deposit_mode {
     PIC_DEPOSIT_AUTO = 0,         /* WINDOW when rebin_every > 0, else LDS_ATOMIC         */
     PIC_DEPOSIT_LDS_ATOMIC = 1,   /* every particle adds its stencil with LDS atomics     */
-    PIC_DEPOSIT_WINDOW = 2        /* each thread sums its particles' stencils in registers
+    PIC_DEPOSIT_WINDOW = 2,       /* each thread sums its particles' stencils in registers
                                      over a few nodes and adds them when the window moves;
                                      pays off when particles are cell-sorted             */
+    PIC_DEPOSIT_WAVE = 3          /* each lane sums its stencils in registers over a window
+                                     shared by the wavefront (anchored at its first
+                                     particle); the window is summed across the wavefront
+                                     (DPP) before one LDS add; for cell-sorted particles   */
 };
 
 typedef struct {

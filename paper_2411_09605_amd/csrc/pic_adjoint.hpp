@@ -163,8 +163,9 @@ __device__ __forceinline__ void adj_fields(const Run &r, const Work &wk, const d
                                            double *eb, double *e1, double *red)
 {
     // electrostatic: the magnetic tiles and the Crank-Nicolson scratch are not touched
-    predictor_fields(r, En, nullptr, J1, es, es, red);
-    field_update(r, wk, En, nullptr, J2, e1, e1, eb, eb, e1, red);
+    // the stored grids of a step are single (replicas already summed)
+    predictor_fields(r, En, nullptr, J1, es, es, red, 1);
+    field_update(r, wk, En, nullptr, J2, e1, e1, eb, eb, e1, red, 1);
     __syncthreads();
     ghost_fill(es, 1, r.ng, r.tw);
     ghost_fill(eb, 1, r.ng, r.tw);
@@ -296,7 +297,9 @@ __global__ __launch_bounds__(1024) void k_adj_rhobar(Run r, Work wk, AdjWork aw,
     Work t = wk;
     t.J2[0] = aw.lam[q];
     t.E = aw.rhobar;
-    gauss_body(r, t, smem);
+    Run r1 = r;
+    r1.nrep = 1;
+    gauss_body(r1, t, smem);
 }
 
 // Per workgroup: the adjoint of x^0 gets the Gauss start's term, then the partial sums
@@ -371,14 +374,15 @@ __global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, doub
         *loss = lw * s;
 }
 
-// Copy of the fields of one step into the segment store: E^n, j^{n,*}, j^{*,n+1/2}.
+// Copy of the fields of one step into the segment store: E^n, j^{n,*}, j^{*,n+1/2} (the
+// currents' replicas summed).
 __global__ void k_adj_save_grids(const double *E, const double *J1, const double *J2, int ng,
-                                 double *dst)
+                                 int nrep, double *dst)
 {
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
         dst[i] = E[i];
-        dst[ng + i] = J1[i];
-        dst[2 * ng + i] = J2[i];
+        dst[ng + i] = rep_sum(J1, i, nrep, 3 * ng);
+        dst[2 * ng + i] = rep_sum(J2, i, nrep, 3 * ng);
     }
 }
 

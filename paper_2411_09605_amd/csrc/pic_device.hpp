@@ -42,6 +42,36 @@ constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
 template <int NV> constexpr int kUnrollA = NV == 1 ? 4 : 2;
 template <int NV> constexpr int kUnrollB = NV == 1 ? 4 : 2;
 
+// A thread's batch of U particles, base + u * blockDim.x (u < U), loaded together.  The
+// particle loops keep the next batch's loads in flight while they compute on the current
+// one (and the first batch's loads in flight during the field prologue), so HBM latency
+// overlaps LDS and ALU work.
+template <int U, int NV> struct PBatch {
+    double x[U], v[U][NV];
+};
+
+template <int U, int NV>
+__device__ __forceinline__ void load_batch(PBatch<U, NV> &b, const double *__restrict__ X,
+                                           const double *__restrict__ V, int64_t vstride,
+                                           int64_t base, int64_t p1)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t p = base + (int64_t)u * blockDim.x;
+        if (p < p1) {
+            b.x[u] = X[p];
+#pragma unroll
+            for (int c = 0; c < NV; ++c)
+                b.v[u][c] = V[c * vstride + p];
+        } else {
+            b.x[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < NV; ++c)
+                b.v[u][c] = 0.0;
+        }
+    }
+}
+
 // Per-step record, laid out exactly like pic_diag.
 struct DevRecord {
     int64_t step;
@@ -70,6 +100,8 @@ struct Run {
     int64_t chunk;         // particles per workgroup
     int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI)
     int32_t tw;            // LDS tile width: ng + 2 kGhost
+    int32_t nrep;          // replicas of the current accumulators (see Work::J1)
+    int32_t pad0;
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -82,8 +114,11 @@ struct Work {
     double *E, *B;         // caller fields: E[3][ng], B[2][ng] (B null for ES)
     double *Ef[2];         // [3][ng] E^n (Ef[n & 1])
     double *Bf[2];         // [2][ng] B^n
-    double *J1[2];         // [3][ng] predictor current j^{n,*} (J1[n & 1])
-    double *J2[2];         // [3][ng] centred current j^{*,n+1/2} (J2[n & 1])
+    // Currents are accumulated with device-scope atomics from every workgroup.  To keep
+    // the chain of atomics on each address short, they go to nrep replicas [nrep][3][ng]
+    // (workgroup b adds into replica b mod nrep); readers sum the replicas in order.
+    double *J1[2];         // [nrep][3][ng] predictor current j^{n,*} (J1[n & 1])
+    double *J2[2];         // [nrep][3][ng] centred current j^{*,n+1/2} (J2[n & 1])
     double *cninv;         // [ng] first row of the Crank-Nicolson inverse
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
     DevState *st;
@@ -200,7 +235,7 @@ template <int ORDER, int NC, int DEP> struct Depo;
 template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
     __device__ __forceinline__ void init() {}
     __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
-                                        const double (&q)[NC])
+                                        const double (&q)[NC], bool = true, bool = true)
     {
         const Slots<ORDER> sl = slots_of<ORDER>(s, ng);
 #pragma unroll
@@ -246,7 +281,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
         clear();
     }
     __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
-                                        const double (&q)[NC])
+                                        const double (&q)[NC], bool = true, bool = true)
     {
         int d = s.first - anchor;
         if (!live || d < 0 || d > W - ORDER - 1) {
@@ -265,6 +300,126 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 acc[c][j] = fma(q[c], a, acc[c][j]);
+        }
+    }
+    __device__ __forceinline__ void finish(double *jt, int tw, int ng) { flush(jt, tw, ng); }
+};
+
+// Cross-lane move within rows of 16 lanes (DPP), for a double.
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active): butterflies within rows of 16
+// with DPP (quad permutations, half-row and row mirrors), then across rows.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_mov<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);    // row_half_mirror
+    v += dpp_mov<0x140>(v);    // row_mirror
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// DEP = 2 (particles cell-sorted; every lane of the wavefront calls add, with `valid`
+// false past the end of the range): each lane sums its contributions in registers over a
+// window of ORDER + 3 nodes shared by the whole wavefront.  The window is placed one node
+// left of the stencil of the wavefront's first particle and stays put while that stencil
+// remains inside it (sub-cell wobble does not move it); when it leaves, the window is
+// summed across the wavefront (DPP) and one lane adds it to the LDS tile.  A run of
+// sorted particles thus costs a few LDS atomics per wavefront instead of ORDER + 1 per
+// particle.  A lane whose stencil is outside the window adds it with LDS atomics.  The
+// window may move only at calls with `may_move` (the first particle of each batch), so
+// the reduction code appears once in the unrolled particle loop.
+template <int ORDER, int NC> struct Depo<ORDER, NC, 2> {
+    static constexpr int W = ORDER + 3;
+    int anchor;            // the same in every lane of the wavefront
+    bool live;
+    double acc[NC][W];
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                acc[c][j] = 0.0;
+    }
+    __device__ __forceinline__ void init()
+    {
+        live = false;
+        anchor = 0;
+        clear();
+    }
+    // all lanes of the wavefront active
+    __device__ __forceinline__ void flush(double *jt, int tw, int ng)
+    {
+        if (!live)
+            return;
+        const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int slot = slot_of_node(anchor + j, ng);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double t = wave_sum_dpp(acc[c][j]);
+                if (lead && t != 0.0)
+                    atomicAdd(&jt[c * tw + slot], t);
+            }
+        }
+        clear();
+    }
+    __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
+                                        const double (&q)[NC], bool valid, bool may_move)
+    {
+        if (may_move) {
+            // lane 0 holds the wavefront's lowest particle index; invalid lanes are the
+            // highest ones, so an invalid lane 0 means the whole wavefront is past the end
+            const int f0 = __builtin_amdgcn_readfirstlane(s.first);
+            const int v0 = __builtin_amdgcn_readfirstlane((int)valid);
+            const int d0 = f0 - anchor;
+            if (v0 && (!live || d0 < 0 || d0 > W - ORDER - 1)) {
+                flush(jt, tw, ng);
+                anchor = f0 - 1;
+                live = true;
+            }
+        }
+        if (!valid)
+            return;
+        if (!live) {
+            // (only before the first window is placed) add directly
+            const Slots<ORDER> sl = slots_of<ORDER>(s, ng);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int k = 0; k <= ORDER; ++k)
+                    atomicAdd(&jt[c * tw + sl.n[k]], q[c] * s.w[k]);
+            return;
+        }
+        const int d = s.first - anchor;
+        if (d >= 0 && d <= W - ORDER - 1) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k <= ORDER; ++k)
+                    if (j - k >= 0 && j - k <= W - ORDER - 1)
+                        a = (d == j - k) ? s.w[k] : a;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[c][j] = fma(q[c], a, acc[c][j]);
+            }
+        } else {
+            const Slots<ORDER> sl = slots_of<ORDER>(s, ng);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int k = 0; k <= ORDER; ++k)
+                    atomicAdd(&jt[c * tw + sl.n[k]], q[c] * s.w[k]);
         }
     }
     __device__ __forceinline__ void finish(double *jt, int tw, int ng) { flush(jt, tw, ng); }
@@ -347,6 +502,44 @@ __device__ __forceinline__ double block_mean(const double *a, int n, double *red
     return block_sum(s, red) / n;
 }
 
+constexpr int kMaxRep = 16;      // upper bound on the replicas of the currents
+
+// Component value J[i] summed over nrep <= kMaxRep replicas of stride rs, in replica
+// order; the loads are issued together.
+__device__ __forceinline__ double rep_sum(const double *J, int i, int nrep, int rs)
+{
+    double a[kMaxRep];
+#pragma unroll
+    for (int k = 0; k < kMaxRep; ++k)
+        a[k] = k < nrep ? J[(size_t)k * rs + i] : 0.0;
+    double s = a[0];
+#pragma unroll
+    for (int k = 1; k < kMaxRep; ++k)
+        s += a[k];
+    return s;
+}
+
+// Sum of the replicas of the first n values of J into dst (LDS or global).
+__device__ __forceinline__ void rep_gather(double *dst, const double *J, int n, int nrep, int rs)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        dst[i] = rep_sum(J, i, nrep, rs);
+}
+
+// Zero every replica of the first n values of J.
+__device__ __forceinline__ void rep_zero(double *J, int n, int nrep, int rs)
+{
+    for (int k = 0; k < nrep; ++k)
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            J[(size_t)k * rs + i] = 0.0;
+}
+
+// The replica a workgroup adds into.
+__device__ __forceinline__ double *rep_slot(double *J, int nrep, int ng)
+{
+    return J + (size_t)(blockIdx.x % nrep) * 3 * ng;
+}
+
 __device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -413,9 +606,9 @@ __device__ __forceinline__ double dminus(const double *g, int i, int ng, double 
 //   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
 // In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
 __device__ void predictor_fields(const Run &r, const double *E, const double *B,
-                                 const double *J, double *es, double *bs, double *red)
+                                 const double *J, double *es, double *bs, double *red, int nrep)
 {
-    const int ng = r.ng, tw = r.tw;
+    const int ng = r.ng, tw = r.tw, rs = 3 * ng;
     double *e0 = es + kGhost, *b0 = bs + kGhost;
     if (r.scheme == 1) {
         for (int i = threadIdx.x; i < ng; i += blockDim.x)
@@ -423,17 +616,20 @@ __device__ void predictor_fields(const Run &r, const double *E, const double *B,
         return;
     }
     if (r.scheme == 0) {
-        const double mean = block_mean(J, ng, red);
+        // the summed current goes through the tile (each thread rereads its own entries)
         for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            e0[i] = E[i] - r.hdt * (J[i] - mean);
+            e0[i] = rep_sum(J, i, nrep, rs);
+        const double mean = block_mean(e0, ng, red);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            e0[i] = E[i] - r.hdt * (e0[i] - mean);
         return;
     }
     const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
     const double *By = B, *Bz = B + ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        e0[i] = Ex[i] - r.hdt * J[i];
-        e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - J[ng + i]);
-        e0[2 * tw + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - J[2 * ng + i]);
+        e0[i] = Ex[i] - r.hdt * rep_sum(J, i, nrep, rs);
+        e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - rep_sum(J, ng + i, nrep, rs));
+        e0[2 * tw + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - rep_sum(J, 2 * ng + i, nrep, rs));
         b0[i] = By[i] + r.hdt * dplus(Ez, i, ng, r.inv_h);
         b0[tw + i] = Bz[i] - r.hdt * dplus(Ey, i, ng, r.inv_h);
     }
@@ -451,14 +647,17 @@ __device__ void predictor_fields(const Run &r, const double *E, const double *B,
 // scratch: EM only, 8 N_g doubles of LDS (E^n, B^n, right-hand sides, g).
 __device__ void field_update(const Run &r, const Work &wk, const double *E, const double *B,
                              const double *J, double *e1, double *b1, double *eb, double *bb,
-                             double *scratch, double *red)
+                             double *scratch, double *red, int nrep)
 {
-    const int ng = r.ng, tw = r.tw;
+    const int ng = r.ng, tw = r.tw, rs = 3 * ng;
     if (r.scheme != 2) {
-        const double mean = block_mean(J, ng, red);
+        // the summed current goes through e1 (each thread rereads its own entries)
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            e1[i] = rep_sum(J, i, nrep, rs);
+        const double mean = block_mean(e1, ng, red);
         for (int i = threadIdx.x; i < ng; i += blockDim.x) {
             const double e0 = E[i];
-            const double en = e0 - r.dt * (J[i] - mean);
+            const double en = e0 - r.dt * (e1[i] - mean);
             e1[i] = en;
             eb[kGhost + i] = 0.5 * (e0 + en);
         }
@@ -476,11 +675,11 @@ __device__ void field_update(const Run &r, const Work &wk, const double *E, cons
     const double *Ey = E0 + ng, *Ez = E0 + 2 * ng, *By = B0, *Bz = B0 + ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
         const int ip = i + 1 == ng ? 0 : i + 1, im = i == 0 ? ng - 1 : i - 1;
-        e1[i] = E0[i] - r.dt * J[i];
+        e1[i] = E0[i] - r.dt * rep_sum(J, i, nrep, rs);
         R[i] = Ey[i] + s * (Ey[ip] - 2.0 * Ey[i] + Ey[im]) * ih2
-               - r.dt * r.c2 * dminus(Bz, i, ng, r.inv_h) - r.dt * J[ng + i];
+               - r.dt * r.c2 * dminus(Bz, i, ng, r.inv_h) - r.dt * rep_sum(J, ng + i, nrep, rs);
         R[ng + i] = Ez[i] + s * (Ez[ip] - 2.0 * Ez[i] + Ez[im]) * ih2
-                    + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * J[2 * ng + i];
+                    + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * rep_sum(J, 2 * ng + i, nrep, rs);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
@@ -662,17 +861,21 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
                                             int64_t p1, bool lead, double *smem, double *red)
 {
     using T = TileSizes<NV, EM>;
+    constexpr int U = kUnrollA<NV>;
     const int ng = r.ng, tw = r.tw;
     double *jt = smem;
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
-    predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red);
+    PBatch<U, NV> cur, nxt;
+    int64_t base = p0 + threadIdx.x;
+    const int64_t stride = (int64_t)U * blockDim.x;
+    load_batch(cur, X, V, r.vstride, base, p1);
+    predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
     tile_zero(jt, T::ncur * tw);
     if (lead) {
         // the predictor current of the next step accumulates into the other buffer
         if (r.scheme != 1)
-            for (int i = threadIdx.x; i < T::ncur * ng; i += blockDim.x)
-                wk.J1[par ^ 1][i] = 0.0;
+            rep_zero(wk.J1[par ^ 1], T::ncur * ng, r.nrep, 3 * ng);
         // the record of the state this step starts from, if not written yet
         if (step > wk.st->recorded)
             write_record(r, wk, step, red);
@@ -685,37 +888,32 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
 
     Depo<ORDER, T::ncur, DEP> dep;
     dep.init();
-    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollA<NV> * blockDim.x) {
-        // issue the loads of kUnrollA particles before any arithmetic (memory-level
-        // parallelism), then process them one by one
-        double xr[kUnrollA<NV>], vr[kUnrollA<NV>][NV];
+    // the trip count is the same for every thread of the workgroup (DEP = 2 needs whole
+    // wavefronts in its deposit); particles past the end are masked with `valid`
+    for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
+        if (b0 + stride < p1)
+            load_batch(nxt, X, V, r.vstride, base + stride, p1);
 #pragma unroll
-        for (int u = 0; u < kUnrollA<NV>; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t p = base + (int64_t)u * blockDim.x;
-            if (p < p1) {
-                xr[u] = X[p];
-#pragma unroll
-                for (int c = 0; c < NV; ++c)
-                    vr[u][c] = V[c * r.vstride + p];
+            const bool valid = p < p1;
+            if constexpr (DEP != 2) {
+                if (!valid)
+                    break;
             }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnrollA<NV>; ++u) {
-            const int64_t p = base + (int64_t)u * blockDim.x;
-            if (p >= p1)
-                break;
-            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], vr[u], es, bs);
-            const double q = (r.w ? r.w[p] : r.wu) * r.qs;
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], cur.v[u], es, bs);
+            const double q = valid ? (r.w ? r.w[p] : r.wu) * r.qs : 0.0;
             double qv[T::ncur];
 #pragma unroll
             for (int c = 0; c < T::ncur; ++c)
                 qv[c] = q * hs.vs[c];
-            dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv);
+            dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv, valid, u == 0);
         }
+        cur = nxt;
     }
     dep.finish(jt, tw, ng);
     __syncthreads();
-    tile_flush(jt, wk.J2[par], T::ncur, ng, tw);
+    tile_flush(jt, rep_slot(wk.J2[par], r.nrep, ng), T::ncur, ng, tw);
 }
 
 template <int ORDER, int NV, bool EM, int DEP>
@@ -743,7 +941,12 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                                             double *smem, double *red)
 {
     using T = TileSizes<NV, EM>;
+    constexpr int U = kUnrollB<NV>;
     const int ng = r.ng, tw = r.tw;
+    PBatch<U, NV> cur, nxt;
+    int64_t base = p0 + threadIdx.x;
+    const int64_t stride = (int64_t)U * blockDim.x;
+    load_batch(cur, X, V, r.vstride, base, p1);
     double *jt = smem;
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
@@ -754,8 +957,8 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double *scratch = b1 + T::nb * ng;
     const double *En = wk.Ef[par];
     const double *Bn = EM ? wk.Bf[par] : nullptr;
-    predictor_fields(r, En, Bn, wk.J1[par], es, bs, red);
-    field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red);
+    predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
+    field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red, r.nrep);
     if constexpr (PRED)
         tile_zero(jt, T::ncur * tw);
     __syncthreads();
@@ -772,8 +975,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
         if constexpr (EM)
             for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
                 wk.Bf[par ^ 1][i] = b1[i];
-        for (int i = threadIdx.x; i < T::ncur * ng; i += blockDim.x)
-            wk.J2[par ^ 1][i] = 0.0;
+        rep_zero(wk.J2[par ^ 1], T::ncur * ng, r.nrep, 3 * ng);
         double we, wb;
         field_energies(r, e1, b1, &we, &wb, red);
         if (threadIdx.x == 0) {
@@ -787,25 +989,19 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     dep.init();
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
-    for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kUnrollB<NV> * blockDim.x) {
-        double xr[kUnrollB<NV>], vr[kUnrollB<NV>][NV];
+    for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
+        if (b0 + stride < p1)
+            load_batch(nxt, X, V, r.vstride, base + stride, p1);
 #pragma unroll
-        for (int u = 0; u < kUnrollB<NV>; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t p = base + (int64_t)u * blockDim.x;
-            if (p < p1) {
-                xr[u] = X[p];
-#pragma unroll
-                for (int c = 0; c < NV; ++c)
-                    vr[u][c] = V[c * r.vstride + p];
+            const bool valid = p < p1;
+            if constexpr (DEP != 2) {
+                if (!valid)
+                    break;
             }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnrollB<NV>; ++u) {
-            const int64_t p = base + (int64_t)u * blockDim.x;
-            if (p >= p1)
-                break;
-            const double *v = vr[u];
-            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, xr[u], v, es, bs);
+            const double *v = cur.v[u];
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], v, es, bs);
             const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
             const Slots<ORDER> n = slots_of<ORDER>(s, ng);
             double vd[NV];
@@ -840,31 +1036,38 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                 num = fma(hs.vs[c] - 0.5 * (vd[c] + v[c]), vd[c] - v[c], num);
                 den = fma(vd[c], vd[c], den);
             }
-            const double g = gamma_factor(num, den, fb);
-            gdev = fmax(gdev, fabs(g - 1.0));
+            int fbp = 0;
+            const double g = gamma_factor(num, den, fbp);
             double vn[NV];
             double v2 = 0.0;
 #pragma unroll
             for (int c = 0; c < NV; ++c) {
                 vn[c] = g * vd[c];
                 v2 = fma(vn[c], vn[c], v2);
-                Vo[c * r.vstride + p] = vn[c];
             }
             const double xw = wrap_pos(hs.x1, r.L);
-            Xo[p] = xw;
-            const double wp = r.w ? r.w[p] : r.wu;
-            ke = fma(wp, v2, ke);
-            if (!isfinite(v2) || !isfinite(hs.x1))
-                nonfinite = 1;
+            const double wp = valid ? (r.w ? r.w[p] : r.wu) : 0.0;
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < NV; ++c)
+                    Vo[c * r.vstride + p] = vn[c];
+                Xo[p] = xw;
+                fb += fbp;
+                gdev = fmax(gdev, fabs(g - 1.0));
+                ke = fma(wp, v2, ke);
+                if (!isfinite(v2) || !isfinite(hs.x1))
+                    nonfinite = 1;
+            }
             if constexpr (PRED) {
                 const double q = wp * r.qs;
                 double qv[T::ncur];
 #pragma unroll
                 for (int c = 0; c < T::ncur; ++c)
                     qv[c] = q * vn[c];
-                dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h), qv);
+                dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h), qv, valid, u == 0);
             }
         }
+        cur = nxt;
     }
     if constexpr (PRED)
         dep.finish(jt, tw, ng);
@@ -880,7 +1083,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     }
     if constexpr (PRED) {
         __syncthreads();
-        tile_flush(jt, wk.J1[par ^ 1], T::ncur, ng, tw);
+        tile_flush(jt, rep_slot(wk.J1[par ^ 1], r.nrep, ng), T::ncur, ng, tw);
     }
 }
 
@@ -936,7 +1139,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
     }
     __syncthreads();
-    tile_flush(jt, wk.J1[0], T::ncur, r.ng, r.tw);
+    tile_flush(jt, rep_slot(wk.J1[0], r.nrep, r.ng), T::ncur, r.ng, r.tw);
 }
 
 template <int ORDER, int NV, bool EM>
@@ -963,7 +1166,7 @@ __device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
     }
     __syncthreads();
-    tile_flush(jt, wk.J2[0], 1, r.ng, r.tw);
+    tile_flush(jt, rep_slot(wk.J2[0], r.nrep, r.ng), 1, r.ng, r.tw);
 }
 
 template <int ORDER>
@@ -1159,7 +1362,7 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem)
 {
     const int ng = r.ng;
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
-    tile_load(rho, wk.J2[0], ng);
+    rep_gather(rho, wk.J2[0], ng, r.nrep, 3 * ng);
     __syncthreads();
     for (int m = threadIdx.x; m < ng; m += blockDim.x) {
         double re = 0.0, im = 0.0;
@@ -1236,8 +1439,7 @@ __device__ void init_finish_body(const Run &r, const Work &wk, double *red)
         wk.st->recorded = -1;
     }
     // the charge scratch must be zero before the first centred deposit
-    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
-        wk.J2[0][i] = 0.0;
+    rep_zero(wk.J2[0], 3 * ng, r.nrep, 3 * ng);
     __syncthreads();
     write_record(r, wk, 0, red);
 }

@@ -92,6 +92,13 @@ size_t lds_need(const pic_params *p)
     return m;
 }
 
+// Replicas of the current accumulators: about 32 workgroups' atomics per address.
+int nrep_of(const pic_params *p)
+{
+    const int nb = blocks_of(p, nullptr);
+    return std::min(kMaxRep, std::max(1, (nb + 31) / 32));
+}
+
 int64_t rebin_len(const pic_params *p) { return (int64_t)kVBins * p->n_cells * blocks_of(p, nullptr); }
 
 void scan_shape(int64_t n, int *nseg, int64_t *seg)
@@ -107,6 +114,8 @@ int deposit_kind(const pic_params *p)
         return 0;
     if (p->deposit_mode == PIC_DEPOSIT_WINDOW)
         return 1;
+    if (p->deposit_mode == PIC_DEPOSIT_WAVE)
+        return 2;
     return p->rebin_every > 0 ? 1 : 0;
 }
 
@@ -119,8 +128,8 @@ Layout layout_of(const pic_params *p)
     for (int k = 0; k < 2; ++k) {
         L.Ef[k] = take(3 * ng * 8);
         L.Bf[k] = take(2 * ng * 8);
-        L.J1[k] = take(3 * ng * 8);
-        L.J2[k] = take(3 * ng * 8);
+        L.J1[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
+        L.J2[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
     }
     L.cninv = take(ng * 8);
     L.spart = take((size_t)blocks_of(p, nullptr) * kNS * 8);
@@ -198,7 +207,7 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (p->grid_blocks < 0 || p->grid_blocks > kMaxGrid)
         return fail(err, PIC_EINVAL, "grid_blocks must be in [0, %d]", kMaxGrid);
-    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_WINDOW)
+    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_WAVE)
         return fail(err, PIC_EINVAL, "unknown deposit_mode %d", p->deposit_mode);
     if (p->record_capacity < 0)
         return fail(err, PIC_EINVAL, "record_capacity must be >= 0");
@@ -298,10 +307,11 @@ void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, 
 template <int ORDER>
 void dispatch_order(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
-    if (deposit_kind(&c->p))
-        dispatch_dep<ORDER, 1>(c, what, par, step, X, V);
-    else
-        dispatch_dep<ORDER, 0>(c, what, par, step, X, V);
+    switch (deposit_kind(&c->p)) {
+    case 2: dispatch_dep<ORDER, 2>(c, what, par, step, X, V); break;
+    case 1: dispatch_dep<ORDER, 1>(c, what, par, step, X, V); break;
+    default: dispatch_dep<ORDER, 0>(c, what, par, step, X, V); break;
+    }
 }
 
 void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0, const double *X = nullptr,
@@ -357,6 +367,8 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.nblocks = blocks_of(p, &r.chunk);
     r.scheme = p->scheme;
     r.tw = (int32_t)tile_width(p);
+    r.nrep = nrep_of(p);
+    r.pad0 = 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -1002,6 +1014,8 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
         R.chunk = chunk;
         R.scheme = q.scheme;
         R.tw = q.n_cells + 2 * kGhost;
+        R.nrep = 1;
+        R.pad0 = 0;
         R.L = q.length;
         R.h = q.length / q.n_cells;
         R.inv_h = q.n_cells / q.length;
@@ -1386,15 +1400,15 @@ void adj_backward_launches(pic_adj *c)
         adj_copy(c, c->segx, c->ckx + (int64_t)cp * r.np, r.np);
         adj_copy(c, c->segv, c->ckv + (int64_t)cp * r.np, r.np);
         adj_copy(c, w.Ef[0], c->ckE + (int64_t)cp * ng, ng);
-        fill_range(c->stream, w.J1[0], ng);
-        fill_range(c->stream, w.J2[0], ng);
+        fill_range(c->stream, w.J1[0], (int64_t)r.nrep * 3 * ng);
+        fill_range(c->stream, w.J2[0], (int64_t)r.nrep * 3 * ng);
         adj_predeposit<ORDER>(c, c->segx, c->segv);
         for (int j = 0; j < len; ++j) {
             const int par = j & 1;
             double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
             adj_pass_a<ORDER>(c, par, -1, Xj, Vj);          // step -1: no record
             hipLaunchKernelGGL(k_adj_save_grids, dim3(1), dim3(256), 0, c->stream, w.Ef[par], w.J1[par],
-                               w.J2[par], ng, c->segg + (int64_t)j * 3 * ng);
+                               w.J2[par], ng, r.nrep, c->segg + (int64_t)j * 3 * ng);
             if (j + 1 < len)
                 adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np);
         }

@@ -39,7 +39,7 @@ def test_validation_accepts_and_sizes():
                dict(nv=3, b_ext=(1.0, 0.0, 0.0)), dict(shape_order=1, n_cells=3),
                dict(n_particles=1), dict(block_threads=1024, grid_blocks=8192),
                dict(rebin_every=10), dict(rebin_every=1, deposit_mode="lds_atomic"),
-               dict(deposit_mode="window")]:
+               dict(deposit_mode="window"), dict(rebin_every=8, deposit_mode="wave")]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0

@@ -209,7 +209,7 @@ def test_weibel_full_size_parity():
 
 
 # ------------------------------------------------------- cell-sorted layout (rebin)
-@pytest.mark.parametrize("mode", ["window", "lds_atomic"])
+@pytest.mark.parametrize("mode", ["window", "lds_atomic", "wave"])
 def test_rebin_landau_parity(mode):
     """Counting-sort rebin every 3 steps (including step 0); particles are matched to the
     oracle through their ids."""
@@ -218,43 +218,50 @@ def test_rebin_landau_parity(mode):
     gu.run_pair(wl, 10, rebin_every=3, deposit_mode=mode)
 
 
-def test_rebin_two_stream_quadratic_parity():
-    _say("case: rebin two-stream 2e5 x 512")
+@pytest.mark.parametrize("mode", ["window", "wave"])
+def test_rebin_two_stream_quadratic_parity(mode):
+    _say(f"case: rebin two-stream 2e5 x 512, deposit {mode}")
     wl = workloads.two_stream(n_particles=200_000, n_cells=512, steps=10)
-    gu.run_pair(wl, 10, rebin_every=4, block_threads=256, grid_blocks=97)
+    gu.run_pair(wl, 10, rebin_every=4, block_threads=256, grid_blocks=97, deposit_mode=mode)
 
 
-def test_rebin_weights_3v_ragged_parity():
+@pytest.mark.parametrize("mode", ["window", "wave"])
+def test_rebin_weights_3v_ragged_parity(mode):
     """Non-uniform weights are permuted with the particles."""
-    _say("case: rebin ES 3V weights")
+    _say(f"case: rebin ES 3V weights, deposit {mode}")
     n = 30_001
     wl = workloads.landau(n_particles=n, n_cells=40, alpha=0.1, order=2)
     wl.v = np.stack([wl.v[0], workloads.normals(9, 12, n), workloads.normals(9, 14, n)])
     wl.nv = 3
     wl.b_ext = (0.3, -0.6, 1.2)
     wl.w = wl.length / n * (1.0 + 0.5 * workloads.uniforms(9, 20, n))
-    gu.run_pair(wl, 10, rebin_every=2)
+    gu.run_pair(wl, 10, rebin_every=2, deposit_mode=mode)
 
 
-def test_rebin_em_parity():
-    _say("case: rebin EM weibel 1e5 x 256")
+@pytest.mark.parametrize("mode", ["window", "wave"])
+def test_rebin_em_parity(mode):
+    _say(f"case: rebin EM weibel 1e5 x 256, deposit {mode}")
     wl = workloads.weibel(n_particles=100_000, n_cells=256, steps=10)
     wl.B0 *= 50.0
-    gu.run_pair(wl, 10, rebin_every=5)
+    gu.run_pair(wl, 10, rebin_every=5, deposit_mode=mode)
 
 
-def test_window_deposit_unsorted_parity():
-    """The register-window deposit is correct (if slower) on unsorted particles."""
-    _say("case: window deposit without rebin")
-    wl = workloads.two_stream(n_particles=100_000, n_cells=64, steps=10)
-    gu.run_pair(wl, 10, deposit_mode="window")
+@pytest.mark.parametrize("mode", ["window", "wave"])
+def test_register_deposits_unsorted_parity(mode):
+    """The register deposits are correct (if slower) on unsorted particles, also with a
+    ragged last workgroup and small workgroups."""
+    _say(f"case: {mode} deposit without rebin")
+    wl = workloads.two_stream(n_particles=100_003, n_cells=64, steps=10)
+    gu.run_pair(wl, 10, deposit_mode=mode)
+    gu.run_pair(wl, 3, deposit_mode=mode, block_threads=64, grid_blocks=37)
 
 
-def test_rebin_full_size_two_stream():
-    _say("case: rebin two-stream FULL 1e7 x 512")
+@pytest.mark.parametrize("mode", ["window", "wave"])
+def test_rebin_full_size_two_stream(mode):
+    _say(f"case: rebin two-stream FULL 1e7 x 512, deposit {mode}")
     wl = workloads.two_stream()
     grec, orec, gpu, _ = gu.run_pair(wl, 2, every=2, rebin_every=1, block_threads=512,
-                                     grid_blocks=512)
+                                     grid_blocks=512, deposit_mode=mode)
     gpu.step(60)
     rec = gpu.diagnostics()
     assert rec["rel_energy_err"].max() < 1e-11
