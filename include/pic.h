@@ -75,14 +75,18 @@ enum pic_flag {
  * give the same sums up to floating-point summation order. */
 enum pic_deposit_mode {
     PIC_DEPOSIT_AUTO = 0,         /* WINDOW when rebin_every > 0, else LDS_ATOMIC         */
-    PIC_DEPOSIT_LDS_ATOMIC = 1,   /* every particle adds its stencil with LDS atomics     */
+    PIC_DEPOSIT_LDS_ATOMIC = 1,   /* every particle adds its stencil with 64-bit integer
+                                     LDS atomics on a fixed-point tile (scale chosen per
+                                     run so no entry overflows; out-of-range contributions
+                                     go to an FP64 side tile); workgroup sums are exact     */
     PIC_DEPOSIT_WINDOW = 2,       /* each thread sums its particles' stencils in registers
                                      over a few nodes and adds them when the window moves;
                                      pays off when particles are cell-sorted             */
-    PIC_DEPOSIT_WAVE = 3          /* each lane sums its stencils in registers over a window
+    PIC_DEPOSIT_WAVE = 3,         /* each lane sums its stencils in registers over a window
                                      shared by the wavefront (anchored at its first
                                      particle); the window is summed across the wavefront
                                      (DPP) before one LDS add; for cell-sorted particles   */
+    PIC_DEPOSIT_LDS_F64 = 4       /* every particle adds its stencil with FP64 LDS atomics */
 };
 
 typedef struct {

@@ -19,7 +19,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUN
     0, -1, -2, -3, -4, -5, -6
 SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
 F_INIT_GAUSS, F_TRACK_IDS = 1, 2
-DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3}
+DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3, "lds_f64": 4}
 ABI_VERSION = 1
 
 

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
 
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    Depo<ORDER, 1, 0> dep;
+    Depo<ORDER, 1, 3> dep;          // adjoint values: FP64 atomics (no fixed-point scale)
+    dep.init(nullptr, r);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double x = X[p], v = V[p], axp = aw.ax[p], avp = aw.av[p];
         const double q = (r.w ? r.w[p] : r.wu) * r.qs;

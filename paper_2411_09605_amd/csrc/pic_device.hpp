@@ -39,8 +39,13 @@ constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
 
 // Particles whose loads each thread issues together before computing on them, per pass
 // (more loads in flight against fewer waves per SIMD from the extra registers).
-template <int NV> constexpr int kUnrollA = NV == 1 ? 4 : 2;
-template <int NV> constexpr int kUnrollB = NV == 1 ? 4 : 2;
+template <int NV> constexpr int kUnrollA = 2;
+template <int NV> constexpr int kUnrollB = 2;
+// Minimum wavefronts per SIMD the particle passes are compiled for: 6 for 1D-1V (at most 80
+// VGPRs, so memory, LDS and ALU work of more wavefronts overlap); 1D-3V keeps its registers.
+template <int NV> constexpr int kWavesPerEU = NV == 1 ? 6 : 1;
+// Largest workgroup of the particle passes.
+template <int NV> constexpr int kMaxThreads = 1024;
 
 // A thread's batch of U particles, base + u * blockDim.x (u < U), loaded together.  The
 // particle loops keep the next batch's loads in flight while they compute on the current
@@ -105,6 +110,9 @@ struct Run {
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
+    double fx_scale;       // 2^S: fixed-point scale of the LDS current tiles (Depo<., ., 0>)
+    double fx_inv;         // 2^-S
+    double fx_lim;         // contributions with |c| 2^S >= fx_lim go to the FP64 side tile
     double bext[3];
     const double *w;       // [N_p] weights or nullptr (uniform)
 };
@@ -225,15 +233,73 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
 }
 
 // Deposit accumulator of one thread for NC current components (tile stride tw).
-// DEP = 0: each particle adds its ORDER + 1 contributions with LDS atomics.
+// DEP = 0: each particle adds its ORDER + 1 contributions with LDS atomics on a 64-bit
+//          fixed-point tile (below).
 // DEP = 1 (particles cell-sorted, so a thread's successive particles share a cell or
-// two): contributions are summed in registers over a window of ORDER + 3 nodes anchored
-// one node left of the stencil that opened it, and added to the tile only when a
-// particle's stencil leaves the window, and at the end.
+//          two): contributions are summed in registers over a window of ORDER + 3 nodes
+//          anchored one node left of the stencil that opened it, and added to the tile
+//          only when a particle's stencil leaves the window, and at the end.
+// DEP = 2: a register window shared by the wavefront (below).
+// DEP = 3: each particle adds its contributions with FP64 LDS atomics.
+// Every kind has init(side, run), add(...), finish(tile, tw, ng); after the workgroup has
+// synchronised, to_double(tile, n) leaves the tile as doubles (ready for tile_flush).
 template <int ORDER, int NC, int DEP> struct Depo;
 
+// DEP = 0.  A contribution c is stored as round(c 2^S): one FMA against 1.5 2^52 rounds
+// c 2^S to an integer exactly while |c 2^S| < 2^51, and the integer is added with
+// ds_add_u64, which runs at about twice the rate of FP64 LDS atomics on random addresses.
+// Sums inside a workgroup are then exact and independent of the order of the adds.  S is
+// chosen per run (Run::fx_*) so that no tile entry can overflow: each entry receives at most
+// one contribution per particle of the workgroup.  A contribution at or beyond the bound
+// (or not finite) is added to an FP64 side tile instead, so any input is deposited.
+constexpr double kFxMagic = 6755399441055744.0;   // 1.5 * 2^52
+
 template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
-    __device__ __forceinline__ void init() {}
+    double *side;
+    double scale, lim, inv;
+    __device__ __forceinline__ void init(double *side_tile, const Run &r)
+    {
+        side = side_tile;
+        scale = r.fx_scale;
+        lim = r.fx_lim;
+        inv = r.fx_inv;
+    }
+    __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
+                                        const double (&q)[NC], bool = true, bool = true)
+    {
+        const Slots<ORDER> sl = slots_of<ORDER>(s, ng);
+        unsigned long long *ti = reinterpret_cast<unsigned long long *>(jt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double qs = q[c] * scale;
+            if (fabs(qs) < lim) {
+#pragma unroll
+                for (int k = 0; k <= ORDER; ++k) {
+                    const double m = fma(qs, s.w[k], kFxMagic);
+                    const long long iv = __double_as_longlong(m) - __double_as_longlong(kFxMagic);
+                    atomicAdd(&ti[c * tw + sl.n[k]], (unsigned long long)iv);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k <= ORDER; ++k)
+                    atomicAdd(&side[c * tw + sl.n[k]], q[c] * s.w[k]);
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(double *, int, int) {}
+    // tile entries (n of them) back to doubles: integer sum times 2^-S plus the side tile
+    __device__ __forceinline__ void to_double(double *jt, int n)
+    {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const long long iv = __double_as_longlong(jt[i]);
+            jt[i] = (double)iv * inv + side[i];
+        }
+        __syncthreads();
+    }
+};
+
+template <int ORDER, int NC> struct Depo<ORDER, NC, 3> {
+    __device__ __forceinline__ void init(double *, const Run &) {}
     __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
                                         const double (&q)[NC], bool = true, bool = true)
     {
@@ -245,7 +311,9 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
                 atomicAdd(&jt[c * tw + sl.n[k]], q[c] * s.w[k]);
     }
     __device__ __forceinline__ void finish(double *, int, int) {}
+    __device__ __forceinline__ void to_double(double *, int) {}
 };
+
 
 template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
     static constexpr int W = ORDER + 3;
@@ -260,12 +328,13 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
             for (int j = 0; j < W; ++j)
                 acc[c][j] = 0.0;
     }
-    __device__ __forceinline__ void init()
+    __device__ __forceinline__ void init(double *, const Run &)
     {
         live = false;
         anchor = 0;
         clear();
     }
+    __device__ __forceinline__ void to_double(double *, int) {}
     __device__ __forceinline__ void flush(double *jt, int tw, int ng)
     {
         if (!live)
@@ -349,12 +418,13 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 2> {
             for (int j = 0; j < W; ++j)
                 acc[c][j] = 0.0;
     }
-    __device__ __forceinline__ void init()
+    __device__ __forceinline__ void init(double *, const Run &)
     {
         live = false;
         anchor = 0;
         clear();
     }
+    __device__ __forceinline__ void to_double(double *, int) {}
     // all lanes of the wavefront active
     __device__ __forceinline__ void flush(double *jt, int tw, int ng)
     {
@@ -866,12 +936,14 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     double *jt = smem;
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
+    double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
     PBatch<U, NV> cur, nxt;
     int64_t base = p0 + threadIdx.x;
     const int64_t stride = (int64_t)U * blockDim.x;
     load_batch(cur, X, V, r.vstride, base, p1);
     predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
     tile_zero(jt, T::ncur * tw);
+    tile_zero(side, T::ncur * tw);
     if (lead) {
         // the predictor current of the next step accumulates into the other buffer
         if (r.scheme != 1)
@@ -887,7 +959,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     __syncthreads();
 
     Depo<ORDER, T::ncur, DEP> dep;
-    dep.init();
+    dep.init(side, r);
     // the trip count is the same for every thread of the workgroup (DEP = 2 needs whole
     // wavefronts in its deposit); particles past the end are masked with `valid`
     for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
@@ -913,11 +985,13 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     }
     dep.finish(jt, tw, ng);
     __syncthreads();
+    dep.to_double(jt, T::ncur * tw);
     tile_flush(jt, rep_slot(wk.J2[par], r.nrep, ng), T::ncur, ng, tw);
 }
 
 template <int ORDER, int NV, bool EM, int DEP>
-__global__ __launch_bounds__(1024) void k_pass_a(Run r, Work wk, int par, int64_t step,
+__global__ __launch_bounds__(kMaxThreads<NV>) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NV>)))
+void k_pass_a(Run r, Work wk, int par, int64_t step,
                                                  const double *__restrict__ X,
                                                  const double *__restrict__ V)
 {
@@ -955,12 +1029,15 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double *e1 = bb + T::nb * tw;
     double *b1 = e1 + T::ne * ng;
     double *scratch = b1 + T::nb * ng;
+    double *side = scratch + (EM ? 8 * ng : 0);   // [ncur][tw] FP64 side tile of the deposit
     const double *En = wk.Ef[par];
     const double *Bn = EM ? wk.Bf[par] : nullptr;
     predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
     field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red, r.nrep);
-    if constexpr (PRED)
+    if constexpr (PRED) {
         tile_zero(jt, T::ncur * tw);
+        tile_zero(side, T::ncur * tw);
+    }
     __syncthreads();
     ghost_fill(es, T::ne, ng, tw);
     ghost_fill(eb, T::ne, ng, tw);
@@ -986,7 +1063,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     __syncthreads();
 
     Depo<ORDER, T::ncur, DEP> dep;
-    dep.init();
+    dep.init(side, r);
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
     for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
@@ -1083,12 +1160,14 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     }
     if constexpr (PRED) {
         __syncthreads();
+        dep.to_double(jt, T::ncur * tw);
         tile_flush(jt, rep_slot(wk.J1[par ^ 1], r.nrep, ng), T::ncur, ng, tw);
     }
 }
 
 template <int ORDER, int NV, bool EM, bool PRED, int DEP>
-__global__ __launch_bounds__(1024) void k_pass_b(Run r, Work wk, int par, const double *X,
+__global__ __launch_bounds__(kMaxThreads<NV>) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NV>)))
+void k_pass_b(Run r, Work wk, int par, const double *X,
                                                  const double *V, double *Xo, double *Vo)
 {
     extern __shared__ double smem[];
@@ -1127,9 +1206,11 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
 {
     using T = TileSizes<NV, EM>;
     double *jt = smem;
-    tile_zero(jt, T::ncur * r.tw);
+    double *side = jt + T::ncur * r.tw;
+    tile_zero(jt, 2 * T::ncur * r.tw);
     __syncthreads();
     Depo<ORDER, T::ncur, 0> dep;
+    dep.init(side, r);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double q = (r.w ? r.w[p] : r.wu) * r.qs;
         double qv[T::ncur];
@@ -1139,6 +1220,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
     }
     __syncthreads();
+    dep.to_double(jt, T::ncur * r.tw);
     tile_flush(jt, rep_slot(wk.J1[0], r.nrep, r.ng), T::ncur, r.ng, r.tw);
 }
 
@@ -1158,14 +1240,17 @@ __device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
                                                  int64_t p1, double *smem)
 {
     double *jt = smem;
-    tile_zero(jt, r.tw);
+    double *side = jt + r.tw;
+    tile_zero(jt, 2 * r.tw);
     __syncthreads();
     Depo<ORDER, 1, 0> dep;
+    dep.init(side, r);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double q[1] = {(r.w ? r.w[p] : r.wu) * r.qs};
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
     }
     __syncthreads();
+    dep.to_double(jt, r.tw);
     tile_flush(jt, rep_slot(wk.J2[0], r.nrep, r.ng), 1, r.ng, r.tw);
 }
 

@@ -69,16 +69,19 @@ size_t tile_width(const pic_params *p) { return (size_t)p->n_cells + 2 * kGhost;
 
 size_t lds_pass_a(const pic_params *p)
 {
-    // jt | es | bs   (ghost-padded tiles)
+    // jt | es | bs | deposit side tile   (ghost-padded tiles)
     const size_t tw = tile_width(p);
-    return is_em(p) ? (3 + 3 + 2) * tw * 8 : 2 * tw * 8;
+    return is_em(p) ? (3 + 3 + 2 + 3) * tw * 8 : 3 * tw * 8;
 }
+
+// Deposit-only kernels (initial predictor deposit, charge deposit): tile + side tile.
+size_t lds_deposit(const pic_params *p) { return 2 * (is_em(p) ? 3 : 1) * tile_width(p) * 8; }
 
 size_t lds_pass_b(const pic_params *p)
 {
-    // jt | es | bs | eb | bb (padded) | e1 | b1 | (EM) Crank-Nicolson scratch
+    // jt | es | bs | eb | bb (padded) | e1 | b1 | (EM) Crank-Nicolson scratch | side tile
     const size_t tw = tile_width(p), ng = p->n_cells;
-    return is_em(p) ? (3 + 3 + 2 + 3 + 2) * tw * 8 + (3 + 2 + 8) * ng * 8 : 3 * tw * 8 + ng * 8;
+    return is_em(p) ? (3 + 3 + 2 + 3 + 2 + 3) * tw * 8 + (3 + 2 + 8) * ng * 8 : 4 * tw * 8 + ng * 8;
 }
 
 size_t lds_rebin(const pic_params *p) { return (size_t)kVBins * p->n_cells * 8; }
@@ -87,9 +90,25 @@ size_t lds_need(const pic_params *p)
 {
     size_t m = std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
+    m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
         m = std::max(m, lds_rebin(p));
     return m;
+}
+
+// Fixed-point scale of the LDS current tiles (Depo<., ., 0>): every tile entry receives at
+// most one contribution per particle of a workgroup (chunk of them), so contributions
+// below lim = min(2^50, 2^62 / chunk) cannot overflow 64 bits; 2^S puts the contribution
+// (w/h)|v| of a particle with uniform weight and |v| = 16 at lim / 16.
+void fixed_point_of(int64_t n_particles, int n_cells, int64_t chunk, Run &r)
+{
+    const double lim = std::min(std::ldexp(1.0, 50),
+                                std::ldexp(1.0, 62) / (double)std::max<int64_t>(chunk, 1));
+    const double qref = (double)n_cells / (double)n_particles * 16.0;
+    const int S = (int)std::floor(std::log2(lim / qref)) - 4;
+    r.fx_scale = std::ldexp(1.0, S);
+    r.fx_inv = std::ldexp(1.0, -S);
+    r.fx_lim = lim;
 }
 
 // Replicas of the current accumulators: about 32 workgroups' atomics per address.
@@ -116,6 +135,8 @@ int deposit_kind(const pic_params *p)
         return 1;
     if (p->deposit_mode == PIC_DEPOSIT_WAVE)
         return 2;
+    if (p->deposit_mode == PIC_DEPOSIT_LDS_F64)
+        return 3;
     return p->rebin_every > 0 ? 1 : 0;
 }
 
@@ -207,7 +228,7 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (p->grid_blocks < 0 || p->grid_blocks > kMaxGrid)
         return fail(err, PIC_EINVAL, "grid_blocks must be in [0, %d]", kMaxGrid);
-    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_WAVE)
+    if (p->deposit_mode < PIC_DEPOSIT_AUTO || p->deposit_mode > PIC_DEPOSIT_LDS_F64)
         return fail(err, PIC_EINVAL, "unknown deposit_mode %d", p->deposit_mode);
     if (p->record_capacity < 0)
         return fail(err, PIC_EINVAL, "record_capacity must be >= 0");
@@ -265,7 +286,7 @@ template <int ORDER, int NV, bool EM>
 void launch_pre(pic_ctx *c)
 {
     hipLaunchKernelGGL((k_predeposit<ORDER, NV, EM>), dim3(c->run.nblocks), dim3(c->threads),
-                       (EM ? 3 : 1) * tile_width(&c->p) * 8, c->stream, c->run, c->wk, c->b.x, c->b.v);
+                       lds_deposit(&c->p), c->stream, c->run, c->wk, c->b.x, c->b.v);
 }
 
 enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO };
@@ -299,7 +320,7 @@ void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, 
         break;
     case D_RHO:
         hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(c->run.nblocks), dim3(c->threads),
-                           tile_width(&c->p) * 8, c->stream, c->run, c->wk, c->b.x);
+                           lds_deposit(&c->p), c->stream, c->run, c->wk, c->b.x);
         break;
     }
 }
@@ -308,6 +329,7 @@ template <int ORDER>
 void dispatch_order(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
     switch (deposit_kind(&c->p)) {
+    case 3: dispatch_dep<ORDER, 3>(c, what, par, step, X, V); break;
     case 2: dispatch_dep<ORDER, 2>(c, what, par, step, X, V); break;
     case 1: dispatch_dep<ORDER, 1>(c, what, par, step, X, V); break;
     default: dispatch_dep<ORDER, 0>(c, what, par, step, X, V); break;
@@ -381,6 +403,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     for (int i = 0; i < 3; ++i)
         r.bext[i] = p->nv == 3 ? p->b_ext[i] : 0.0;
     r.w = b->w;
+    fixed_point_of(p->n_particles, p->n_cells, r.chunk, r);
 
     w.E = b->E;
     w.B = b->B;
@@ -1024,6 +1047,7 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
         R.c2 = q.c * q.c;
         R.qs = 1.0 / R.h;
         R.wu = q.length / (double)q.n_particles;
+        fixed_point_of(q.n_particles, q.n_cells, chunk, R);
         for (int i = 0; i < 3; ++i)
             R.bext[i] = q.nv == 3 ? q.b_ext[i] : 0.0;
         R.w = b->w ? b->w + poff : nullptr;
@@ -1067,9 +1091,9 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
 
     const size_t tw = (size_t)maxg + 2 * kGhost;
     const size_t ng = (size_t)maxg;
-    c->lds_a = em ? 8 * tw * 8 : 2 * tw * 8;
-    c->lds_b = em ? 13 * tw * 8 + 13 * ng * 8 : 3 * tw * 8 + ng * 8;
-    c->lds_dep = (em ? 3 : 1) * tw * 8;
+    c->lds_a = em ? 11 * tw * 8 : 3 * tw * 8;
+    c->lds_b = em ? 16 * tw * 8 + 13 * ng * 8 : 4 * tw * 8 + ng * 8;
+    c->lds_dep = 2 * (em ? 3 : 1) * tw * 8;
     c->lds_gauss = 3 * ng * 8;
 
     if (hipMemcpy(ws + L.runs, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1326,7 +1350,7 @@ template <int ORDER>
 void adj_predeposit(pic_adj *c, const double *X, const double *V)
 {
     hipLaunchKernelGGL((k_predeposit<ORDER, 1, false>), dim3(c->run.nblocks), dim3(c->threads),
-                       tile_width(&c->q) * 8, c->stream, c->run, c->wk, X, V);
+                       lds_deposit(&c->q), c->stream, c->run, c->wk, X, V);
 }
 
 template <int ORDER, int STAGE>
@@ -1359,7 +1383,7 @@ void adj_forward_launches(pic_adj *c)
     fill_range(c->stream, w.Ef[0], (int64_t)(c->A.fwd.cninv - c->A.fwd.Ef[0]) / 8);
     fill_range(c->stream, c->b.E + ng, 2 * (int64_t)ng);
     hipLaunchKernelGGL((k_init_particles<1>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w, X, V);
-    hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(r.nblocks), dim3(c->threads), tile_width(&c->q) * 8,
+    hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(r.nblocks), dim3(c->threads), lds_deposit(&c->q),
                        c->stream, r, w, X);
     hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w);
     adj_predeposit<ORDER>(c, X, V);

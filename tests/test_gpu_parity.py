@@ -113,6 +113,18 @@ def test_fast_particles_cross_several_cells():
     gu.run_pair(wl, 10)
 
 
+def test_fixed_point_side_tile_and_f64_mode():
+    """Velocities far beyond the fixed-point range of the LDS current tile (the side-tile
+    path, and positions wrapping several periods per step), and the FP64-atomic mode."""
+    _say("case: huge velocities (side tile), FP64 LDS mode")
+    wl = workloads.landau(n_particles=5000, n_cells=16, dt=0.01, alpha=0.1, order=2)
+    wl.v = wl.v.copy()
+    wl.v[0, ::50] *= 2000.0
+    gu.run_pair(wl, 10)
+    wl2 = workloads.two_stream(n_particles=100_003, n_cells=64, steps=10)
+    gu.run_pair(wl2, 10, deposit_mode="lds_f64")
+
+
 def test_boris_limit_on_gpu():
     _say("case: Boris limit")
     from paper_2411_09605_amd import Pic
