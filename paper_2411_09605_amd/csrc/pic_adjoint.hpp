@@ -40,7 +40,7 @@ struct AdjParams {
 struct AdjWork {
     double *ax, *av;       // [N_p] adjoint of the particle state
     double *lam[2];        // [N_g] adjoint of E^{n+1} from the later steps (by parity)
-    double *G1[2], *G2[2]; // [N_g] deposits of R1, R2 (by parity)
+    double *G1[2], *G2[2]; // [nrep][N_g] deposits of R1, R2 (by parity, replicated)
     double *rhobar;        // [N_g] Gauss solve of the final lambda (see k_adj_rhobar)
     double *gpart;         // [nblocks][nparam] per-workgroup gradient partial sums
 };
@@ -171,61 +171,89 @@ __device__ __forceinline__ void adj_fields(const Run &r, const Work &wk, const d
     ghost_fill(eb, 1, r.ng, r.tw);
 }
 
+// The replica of the grid-adjoint deposits a workgroup adds into (replica stride ng).
+__device__ __forceinline__ double *g_slot(double *G, int nrep, int ng)
+{
+    return G + (size_t)(blockIdx.x % nrep) * ng;
+}
+
 // lt = lambda + lbw E^{n+1} + G1 / 2 into lt (LDS [ng]); jb2 = -dt (lt - mean lt) into
-// the tile interior.  e1 must be visible.
+// the tile interior.  e1 must be visible.  G1 has nrep replicas.
 __device__ __forceinline__ void adj_current2(const Run &r, const AdjParams &ap, const double *lam,
                                              const double *G1, const double *e1, double *lt,
                                              double *jb2, double *red)
 {
     const int ng = r.ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x)
-        lt[i] = fma(ap.lbw, e1[i], lam[i]) + 0.5 * G1[i];
+        lt[i] = fma(ap.lbw, e1[i], lam[i]) + 0.5 * rep_sum(G1, i, r.nrep, ng);
     __syncthreads();
     const double m = block_mean(lt, ng, red);
     for (int i = threadIdx.x; i < ng; i += blockDim.x)
         jb2[kGhost + i] = -r.dt * (lt[i] - m);
 }
 
-// LDS of the reverse passes: es | eb | jb2 | jb1-or-tile (tw each) | e1 | lt (ng each)
-__host__ __device__ constexpr size_t adj_lds_doubles(int tw, int ng) { return 4 * (size_t)tw + 2 * (size_t)ng; }
+// LDS of the reverse passes: es | eb | jb2 | jb1-or-tile (tw each) | e1 | lt (ng each), and
+// for the fused pass (STAGE 4) the previous step's es | eb | tile (tw each) | e1 (ng).
+__host__ __device__ constexpr size_t adj_lds_doubles(int tw, int ng, int stage)
+{
+    return stage == 4 ? 7 * (size_t)tw + 3 * (size_t)ng : 4 * (size_t)tw + 2 * (size_t)ng;
+}
 
+// Reverse pass of step n.  STAGE 1, 2, 3 as described at the top; STAGE 4 is R3 of step n
+// fused with R1 of step n - 1: with the adjoint of (x^n, v^n) just computed, the same
+// thread recomputes step n - 1 of its particle (Xm, Vm, grids gm) and deposits its
+// E-bar adjoint into the other parity's G1.  G1 and G2 have nrep replicas.
 template <int ORDER, int STAGE>
 __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw, AdjParams ap,
                                                       int q, const double *__restrict__ X,
                                                       const double *__restrict__ V,
-                                                      const double *__restrict__ En,
-                                                      const double *__restrict__ J1,
-                                                      const double *__restrict__ J2)
+                                                      const double *__restrict__ g,
+                                                      const double *__restrict__ Xm,
+                                                      const double *__restrict__ Vm,
+                                                      const double *__restrict__ gm)
 {
     extern __shared__ double smem[];
     __shared__ double red[16];
-    const int ng = r.ng, tw = r.tw;
+    const int ng = r.ng, tw = r.tw, nrep = r.nrep;
     double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
     double *e1 = t4 + tw, *lt = e1 + ng;
-    adj_fields(r, wk, En, J1, J2, es, eb, e1, red);
+    double *esm = lt + ng, *ebm = esm + tw, *tm = ebm + tw, *e1m = tm + tw;   // STAGE 4
+    adj_fields(r, wk, g, g + ng, g + 2 * ng, es, eb, e1, red);
+    if constexpr (STAGE == 4) {
+        __syncthreads();
+        adj_fields(r, wk, gm, gm + ng, gm + 2 * ng, esm, ebm, e1m, red);
+    }
     if constexpr (STAGE >= 2) {
         __syncthreads();
         adj_current2(r, ap, aw.lam[q], aw.G1[q], e1, lt, jb2, red);
     }
-    if constexpr (STAGE == 3) {
-        const double m = block_mean(aw.G2[q], ng, red);
+    if constexpr (STAGE == 2) {
+        // the next reverse step deposits into the other parity's G1 (in the pass after this)
+        if (blockIdx.x == 0)
+            rep_zero(aw.G1[q ^ 1], ng, nrep, ng);
+    }
+    if constexpr (STAGE >= 3) {
         for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            t4[kGhost + i] = -r.hdt * (aw.G2[q][i] - m);
+            t4[kGhost + i] = rep_sum(aw.G2[q], i, nrep, ng);
+        const double m = block_mean(t4 + kGhost, ng, red);
         if (blockIdx.x == 0) {
-            // adjoint of E^n for step n - 1; clear the deposits of the next reverse step
-            for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-                aw.lam[q ^ 1][i] = lt[i] + 0.5 * aw.G1[q][i] + aw.G2[q][i];
-                aw.G1[q ^ 1][i] = 0.0;
-                aw.G2[q ^ 1][i] = 0.0;
-            }
+            // adjoint of E^n for step n - 1; clear the other parity's G2
+            for (int i = threadIdx.x; i < ng; i += blockDim.x)
+                aw.lam[q ^ 1][i] = lt[i] + 0.5 * rep_sum(aw.G1[q], i, nrep, ng) + t4[kGhost + i];
+            rep_zero(aw.G2[q ^ 1], ng, nrep, ng);
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            t4[kGhost + i] = -r.hdt * (t4[kGhost + i] - m);
     } else {
         tile_zero(t4, tw);
     }
+    if constexpr (STAGE == 4)
+        tile_zero(tm, tw);
     __syncthreads();
     if constexpr (STAGE >= 2)
         ghost_fill(jb2, 1, ng, tw);
-    if constexpr (STAGE == 3)
+    if constexpr (STAGE >= 3)
         ghost_fill(t4, 1, ng, tw);
     __syncthreads();
 
@@ -235,9 +263,9 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
     dep.init(nullptr, r);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double x = X[p], v = V[p], axp = aw.ax[p], avp = aw.av[p];
-        const double q = (r.w ? r.w[p] : r.wu) * r.qs;
-        const AdjOut<ORDER, STAGE> o =
-            adj_particle<ORDER, STAGE>(r, x, v, axp, avp, q, es, eb, jb2, t4);
+        const double qp = (r.w ? r.w[p] : r.wu) * r.qs;
+        const AdjOut<ORDER, STAGE == 4 ? 3 : STAGE> o =
+            adj_particle<ORDER, STAGE == 4 ? 3 : STAGE>(r, x, v, axp, avp, qp, es, eb, jb2, t4);
         if constexpr (STAGE == 1) {
             const double c[1] = {o.ebar_b};
             dep.add(t4, tw, ng, o.sh, c);
@@ -247,11 +275,21 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
         } else {
             aw.ax[p] = o.xb;
             aw.av[p] = o.vb;
+            if constexpr (STAGE == 4) {
+                const AdjOut<ORDER, 1> o1 = adj_particle<ORDER, 1>(r, Xm[p], Vm[p], o.xb, o.vb, qp,
+                                                                   esm, ebm, jb2, t4);
+                const double c[1] = {o1.ebar_b};
+                dep.add(tm, tw, ng, o1.sh, c);
+            }
         }
     }
-    if constexpr (STAGE < 3) {
+    if constexpr (STAGE == 1 || STAGE == 2) {
         __syncthreads();
-        tile_flush(t4, STAGE == 1 ? aw.G1[q] : aw.G2[q], 1, ng, tw);
+        tile_flush(t4, g_slot(STAGE == 1 ? aw.G1[q] : aw.G2[q], nrep, ng), 1, ng, tw);
+    }
+    if constexpr (STAGE == 4) {
+        __syncthreads();
+        tile_flush(tm, g_slot(aw.G1[q ^ 1], nrep, ng), 1, ng, tw);
     }
 }
 

@@ -1238,9 +1238,9 @@ pic_params adj_forward_params(const pic_adj_params *p)
     return q;
 }
 
-size_t adj_lds(const pic_params *q)
+size_t adj_lds(const pic_params *q, int stage = 4)
 {
-    return adj_lds_doubles((int)tile_width(q), q->n_cells) * 8;
+    return adj_lds_doubles((int)tile_width(q), q->n_cells, stage) * 8;
 }
 
 int adj_validate(const pic_adj_params *p)
@@ -1287,8 +1287,8 @@ AdjLayout adj_layout(const pic_adj_params *p)
     A.ax = take(np * 8);
     A.av = take(np * 8);
     A.lam = take(2 * ng * 8);
-    A.G1 = take(2 * ng * 8);
-    A.G2 = take(2 * ng * 8);
+    A.G1 = take(2 * (size_t)nrep_of(&q) * ng * 8);
+    A.G2 = take(2 * (size_t)nrep_of(&q) * ng * 8);
     A.rhobar = take(ng * 8);
     A.gpart = take((size_t)blocks_of(&q, nullptr) * (PIC_ADJ_MAX_MODES + 2) * 8);
     A.total = o;
@@ -1354,11 +1354,12 @@ void adj_predeposit(pic_adj *c, const double *X, const double *V)
 }
 
 template <int ORDER, int STAGE>
-void adj_rev(pic_adj *c, int q, const double *X, const double *V, const double *g)
+void adj_rev(pic_adj *c, int q, const double *X, const double *V, const double *g,
+             const double *Xm = nullptr, const double *Vm = nullptr, const double *gm = nullptr)
 {
-    const int ng = c->p.n_cells;
-    hipLaunchKernelGGL((k_adj_reverse<ORDER, STAGE>), dim3(c->run.nblocks), dim3(c->threads), adj_lds(&c->q),
-                       c->stream, c->run, c->wk, c->aw, c->ap, q, X, V, g, g + ng, g + 2 * ng);
+    hipLaunchKernelGGL((k_adj_reverse<ORDER, STAGE>), dim3(c->run.nblocks), dim3(c->threads),
+                       adj_lds(&c->q, STAGE), c->stream, c->run, c->wk, c->aw, c->ap, q, X, V, g, Xm, Vm,
+                       gm);
 }
 
 int grid_threads_of(int ng)
@@ -1415,8 +1416,8 @@ void adj_backward_launches(pic_adj *c)
     fill_range(c->stream, c->aw.ax, r.np);
     fill_range(c->stream, c->aw.av, r.np);
     fill_range(c->stream, c->aw.lam[0], 2 * (int64_t)ng);    // both parities
-    fill_range(c->stream, c->aw.G1[0], 2 * (int64_t)ng);
-    fill_range(c->stream, c->aw.G2[0], 2 * (int64_t)ng);
+    fill_range(c->stream, c->aw.G1[0], 2 * (int64_t)r.nrep * ng);
+    fill_range(c->stream, c->aw.G2[0], 2 * (int64_t)r.nrep * ng);
     int q = 0;
     for (int cp = c->A.ncp - 1; cp >= 0; --cp) {
         const int s0 = cp * K, len = std::min(K, N - s0);
@@ -1436,13 +1437,19 @@ void adj_backward_launches(pic_adj *c)
             if (j + 1 < len)
                 adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np);
         }
-        // reverse steps of the segment
+        // reverse steps of the segment: R1 of its last step, then per step R2 and R3 fused
+        // with R1 of the step before (R3 alone for the segment's first step, whose
+        // predecessor is in the previous segment)
         for (int j = len - 1; j >= 0; --j) {
             const double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
             const double *g = c->segg + (int64_t)j * 3 * ng;
-            adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
+            if (j == len - 1)
+                adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
             adj_rev<ORDER, 2>(c, q, Xj, Vj, g);
-            adj_rev<ORDER, 3>(c, q, Xj, Vj, g);
+            if (j > 0)
+                adj_rev<ORDER, 4>(c, q, Xj, Vj, g, Xj - r.np, Vj - r.np, g - 3 * ng);
+            else
+                adj_rev<ORDER, 3>(c, q, Xj, Vj, g);
             q ^= 1;
         }
     }
@@ -1513,8 +1520,8 @@ int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_st
     aw.av = (double *)(ws + A.av);
     for (int k = 0; k < 2; ++k) {
         aw.lam[k] = (double *)(ws + A.lam) + k * ng;
-        aw.G1[k] = (double *)(ws + A.G1) + k * ng;
-        aw.G2[k] = (double *)(ws + A.G2) + k * ng;
+        aw.G1[k] = (double *)(ws + A.G1) + (size_t)k * c->run.nrep * ng;
+        aw.G2[k] = (double *)(ws + A.G2) + (size_t)k * c->run.nrep * ng;
     }
     aw.rhobar = (double *)(ws + A.rhobar);
     aw.gpart = (double *)(ws + A.gpart);
