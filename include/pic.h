@@ -226,7 +226,7 @@ typedef struct {
     const int64_t *n_particles;  /* HOST array [n_runs]: N_p of each run (>= 1)           */
     const int32_t *n_cells;      /* HOST array [n_runs]: N_g of each run                  */
     const double  *length;       /* HOST array [n_runs]: L of each run                    */
-    int32_t block_threads;       /* 0 = default, else a multiple of 64 in [64, 1024]      */
+    int32_t block_threads;       /* 0 = default (256), else a multiple of 64 in [64, 512] */
     int32_t chunk;               /* particles per work item, 0 = default; a multiple of
                                     block_threads                                         */
     int32_t grid_blocks;         /* persistent grid, 0 = default                          */

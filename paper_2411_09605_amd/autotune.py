@@ -11,8 +11,8 @@ import os
 import time
 from typing import Dict, Sequence, Tuple
 
-CANDIDATES: Sequence[Tuple[int, int]] = ((256, 4096), (256, 8192), (256, 16384),
-                                         (512, 8192), (512, 16384), (512, 32768))
+CANDIDATES: Sequence[Tuple[int, int]] = ((256, 8192), (256, 16384), (256, 32768),
+                                         (512, 16384), (512, 32768), (512, 65536))
 
 
 def cache_path() -> str:

@@ -675,7 +675,7 @@ __device__ __forceinline__ double dminus(const double *g, int i, int ng, double 
 //   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
 //   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
 // In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
-__device__ void predictor_fields(const Run &r, const double *E, const double *B,
+__device__ __forceinline__ void predictor_fields(const Run &r, const double *E, const double *B,
                                  const double *J, double *es, double *bs, double *red, int nrep)
 {
     const int ng = r.ng, tw = r.tw, rs = 3 * ng;
@@ -715,7 +715,7 @@ __device__ void predictor_fields(const Run &r, const double *E, const double *B,
 //     E_x' = E_x - dt j_x
 //   The circulant system is solved with the first row g of its inverse.
 // scratch: EM only, 8 N_g doubles of LDS (E^n, B^n, right-hand sides, g).
-__device__ void field_update(const Run &r, const Work &wk, const double *E, const double *B,
+__device__ __forceinline__ void field_update(const Run &r, const Work &wk, const double *E, const double *B,
                              const double *J, double *e1, double *b1, double *eb, double *bb,
                              double *scratch, double *red, int nrep)
 {
@@ -778,7 +778,7 @@ __device__ void field_update(const Run &r, const Work &wk, const double *E, cons
 
 // W_E = h/2 sum |E|^2 and W_B = c^2 h/2 sum |B|^2 (section 5.1) of LDS/global fields;
 // every thread gets the result.
-__device__ void field_energies(const Run &r, const double *E, const double *B, double *we,
+__device__ __forceinline__ void field_energies(const Run &r, const double *E, const double *B, double *we,
                                double *wb, double *red)
 {
     const bool em = r.scheme == 2;
@@ -795,7 +795,7 @@ __device__ void field_energies(const Run &r, const double *E, const double *B, d
 
 // Write the record of `step` from the pass-B scalars of every workgroup (summed in a
 // fixed order) and the field energies in st; run by one workgroup.
-__device__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
+__device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
 {
     double ke = 0.0, fb = 0.0, gd = 0.0, nf = 0.0;
     for (int b = threadIdx.x; b < r.nblocks; b += blockDim.x) {
@@ -1562,6 +1562,27 @@ struct BatchItem {
     int64_t p0, p1;        // run-local particle range
 };
 
+// Copy of a structure that is the same for the whole workgroup (a run's scalars and
+// arrays) into scalar registers, one 32-bit word at a time.
+template <int N> struct Words {
+    int w[N];
+};
+
+template <typename T> __device__ __forceinline__ T uniform_copy(const T &g)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    constexpr int n = (int)(sizeof(T) / 4);
+    Words<n> w = __builtin_bit_cast(Words<n>, g);
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+        w.w[i] = __builtin_amdgcn_readfirstlane(w.w[i]);
+    return __builtin_bit_cast(T, w);
+}
+
+// Workgroups of the batched passes hold at most 512 threads, so the persistent kernels,
+// which keep a run's scalars live across work items, have up to 256 VGPRs (no spills).
+constexpr int kBatchMaxThreads = 512;
+
 struct Batch {
     const BatchRun *runs;
     const BatchItem *items;
@@ -1571,7 +1592,7 @@ struct Batch {
 };
 
 template <int ORDER, int NV, bool EM, int DEP>
-__global__ __launch_bounds__(1024) void k_batch_pass_a(Batch b)
+__global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
 {
     extern __shared__ double smem[];
     __shared__ double red[16];
@@ -1580,8 +1601,8 @@ __global__ __launch_bounds__(1024) void k_batch_pass_a(Batch b)
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
-        const Run r = br.r;
-        const Work wk = br.wk;
+        const Run r = uniform_copy(br.r);
+        const Work wk = uniform_copy(br.wk);
         pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, b.X + br.poff, b.V + br.poff, item.p0,
                                         item.p1, item.slot == 0, smem, red);
         __syncthreads();
@@ -1589,7 +1610,7 @@ __global__ __launch_bounds__(1024) void k_batch_pass_a(Batch b)
 }
 
 template <int ORDER, int NV, bool EM, bool PRED, int DEP>
-__global__ __launch_bounds__(1024) void k_batch_pass_b(Batch b)
+__global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
 {
     extern __shared__ double smem[];
     __shared__ double red[16];
@@ -1597,8 +1618,8 @@ __global__ __launch_bounds__(1024) void k_batch_pass_b(Batch b)
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
-        const Run r = br.r;
-        const Work wk = br.wk;
+        const Run r = uniform_copy(br.r);
+        const Work wk = uniform_copy(br.wk);
         pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, b.X + br.poff, b.V + br.poff,
                                               b.X + br.poff, b.V + br.poff, item.p0, item.p1,
                                               item.slot == 0, item.slot, smem, red);
@@ -1619,8 +1640,8 @@ __global__ __launch_bounds__(1024) void k_batch_finish(Batch b)
     __shared__ double red[16];
     const int64_t step = *b.stepc;
     const BatchRun &br = b.runs[blockIdx.x];
-    const Run r = br.r;
-    const Work wk = br.wk;
+    const Run r = uniform_copy(br.r);
+    const Work wk = uniform_copy(br.wk);
     finish_body(r, wk, (int)(step & 1), step, red);
 }
 
@@ -1631,8 +1652,8 @@ __global__ __launch_bounds__(1024) void k_batch_init_particles(Batch b)
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
-        const Run r = br.r;
-        const Work wk = br.wk;
+        const Run r = uniform_copy(br.r);
+        const Work wk = uniform_copy(br.wk);
         init_particles_body<NV>(r, wk, b.X + br.poff, b.V + br.poff, item.p0, item.p1, item.slot,
                                 red);
         __syncthreads();
@@ -1646,8 +1667,8 @@ __global__ __launch_bounds__(1024) void k_batch_deposit_rho(Batch b)
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
-        const Run r = br.r;
-        const Work wk = br.wk;
+        const Run r = uniform_copy(br.r);
+        const Work wk = uniform_copy(br.wk);
         deposit_rho_body<ORDER>(r, wk, b.X + br.poff, item.p0, item.p1, smem);
         __syncthreads();
     }
@@ -1660,8 +1681,8 @@ __global__ __launch_bounds__(1024) void k_batch_predeposit(Batch b)
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
-        const Run r = br.r;
-        const Work wk = br.wk;
+        const Run r = uniform_copy(br.r);
+        const Work wk = uniform_copy(br.wk);
         predeposit_body<ORDER, NV, EM>(r, wk, b.X + br.poff, b.V + br.poff, item.p0, item.p1, smem);
         __syncthreads();
     }
@@ -1672,16 +1693,16 @@ __global__ __launch_bounds__(1024) void k_batch_gauss(Batch b)
 {
     extern __shared__ double smem[];
     const BatchRun &br = b.runs[blockIdx.x];
-    const Run r = br.r;
-    const Work wk = br.wk;
+    const Run r = uniform_copy(br.r);
+    const Work wk = uniform_copy(br.wk);
     gauss_body(r, wk, smem);
 }
 
 __global__ __launch_bounds__(1024) void k_batch_cn_init(Batch b)
 {
     const BatchRun &br = b.runs[blockIdx.x];
-    const Run r = br.r;
-    const Work wk = br.wk;
+    const Run r = uniform_copy(br.r);
+    const Work wk = uniform_copy(br.wk);
     cn_init_body(r, wk);
 }
 
@@ -1689,8 +1710,8 @@ __global__ __launch_bounds__(1024) void k_batch_init_finish(Batch b)
 {
     __shared__ double red[16];
     const BatchRun &br = b.runs[blockIdx.x];
-    const Run r = br.r;
-    const Work wk = br.wk;
+    const Run r = uniform_copy(br.r);
+    const Work wk = uniform_copy(br.wk);
     init_finish_body(r, wk, red);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         *b.stepc = 0;

@@ -823,8 +823,8 @@ int batch_validate(const pic_batch_params *p)
         return fail(nullptr, PIC_EINVAL, "n_runs >= 1 and the per-run arrays are required");
     if (p->flags & ~(uint32_t)PIC_BF_INIT_GAUSS)
         return fail(nullptr, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
-    if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > 1024))
-        return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+    if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > kBatchMaxThreads))
+        return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, %d]", kBatchMaxThreads);
     if (p->chunk < 0 || p->chunk % batch_threads(p))
         return fail(nullptr, PIC_EINVAL, "chunk must be 0 or a positive multiple of block_threads");
     if (p->grid_blocks < 0 || p->graph_steps < 0 || p->record_capacity < 0 || p->reserved)
@@ -842,6 +842,13 @@ int batch_validate(const pic_batch_params *p)
     return PIC_OK;
 }
 
+// Replicas of a run's current accumulators: about 32 work items per replica.
+int batch_nrep(const pic_batch_params *p, int r)
+{
+    const int64_t items = (p->n_particles[r] + batch_chunk(p) - 1) / batch_chunk(p);
+    return (int)std::min<int64_t>(kMaxRep, std::max<int64_t>(1, (items + 31) / 32));
+}
+
 BatchLayout batch_layout(const pic_batch_params *p)
 {
     BatchLayout L;
@@ -854,10 +861,11 @@ BatchLayout batch_layout(const pic_batch_params *p)
         L.Ef1.push_back(take(3 * ng * 8));
         L.Bf0.push_back(take(2 * ng * 8));
         L.Bf1.push_back(take(2 * ng * 8));
-        L.J10.push_back(take(3 * ng * 8));
-        L.J11.push_back(take(3 * ng * 8));
-        L.J20.push_back(take(3 * ng * 8));
-        L.J21.push_back(take(3 * ng * 8));
+        const size_t nr = (size_t)batch_nrep(p, r);
+        L.J10.push_back(take(nr * 3 * ng * 8));
+        L.J11.push_back(take(nr * 3 * ng * 8));
+        L.J20.push_back(take(nr * 3 * ng * 8));
+        L.J21.push_back(take(nr * 3 * ng * 8));
         L.cninv.push_back(take(ng * 8));
         L.nitems += (int)((p->n_particles[r] + batch_chunk(p) - 1) / batch_chunk(p));
     }
@@ -1037,7 +1045,7 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
         R.chunk = chunk;
         R.scheme = q.scheme;
         R.tw = q.n_cells + 2 * kGhost;
-        R.nrep = 1;
+        R.nrep = batch_nrep(p, r);
         R.pad0 = 0;
         R.L = q.length;
         R.h = q.length / q.n_cells;
