@@ -110,7 +110,9 @@ typedef struct {
                               (512), else a multiple of 64 in [64, 1024]                  */
     int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default, with
                               m = ceil(N_p / block_threads): min(max(ceil(m / 8),
-                              min(m, 64)), 512)                                           */
+                              min(m, 64)), 512).  Each workgroup takes a chunk of
+                              ceil(N_p / grid) particles rounded up to a multiple of 64,
+                              so the grid launched may be smaller than asked             */
     int32_t deposit_mode;  /* enum pic_deposit_mode                                      */
     int32_t record_capacity; /* per-step diagnostic records kept on the device: 0 = 4096 */
     int32_t reserved;      /* must be 0                                                  */

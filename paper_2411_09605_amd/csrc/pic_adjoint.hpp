@@ -70,10 +70,11 @@ template <> __device__ __forceinline__ Stencil<2> dstencil<2>(double xi)
     return s;
 }
 
-// Gamma and its branch: ok = the root is real (no fallback).
-__device__ __forceinline__ double adj_gamma(double num, double den, double &rho, bool &ok)
+// Gamma and its branch: ok = the root is real (no fallback).  num2 = 2 num, formed as in
+// the forward pass so that the branch taken is the forward run's.
+__device__ __forceinline__ double adj_gamma(double num2, double den, double &rho, bool &ok)
 {
-    rho = 2.0 * num / den;
+    rho = num2 / den;
     const double rr = 1.0 + rho;
     ok = rr >= 0.0 && isfinite(rr);
     return ok ? sqrt(rr) : 1.0;
@@ -108,25 +109,26 @@ __device__ __forceinline__ AdjOut<ORDER, STAGE> adj_particle(const Run &r, doubl
     o.sh = stencil<ORDER>(xh * r.inv_h);
     o.nh = slots_of<ORDER>(o.sh, r.ng);
     const double vd = fma(r.dt, gather1<ORDER>(eb, o.sh, o.nh), v);
-    const double a = vs - 0.5 * (vd + v), b = vd - v;
-    const double num = a * b, den = vd * vd;
+    // num2 = 2 num = a2 b with a2 = 2 v* - (vd + v), b = vd - v
+    const double a2 = fma(2.0, vs, -(vd + v)), b = vd - v;
+    const double num2 = fma(a2, b, 0.0), den = fma(vd, vd, 0.0);
     double rho;
     bool ok;
-    const double gam = adj_gamma(num, den, rho, ok);
+    const double gam = adj_gamma(num2, den, rho, ok);
 
     // v^{n+1} = Gamma vd
     double vdb = gam * avp;
     const double gb = avp * vd;
-    double numb = 0.0, denb = 0.0;
+    double numb = 0.0, denb = 0.0;              // adjoints of num2 and den
     if (ok) {
         const double rhob = gb / (2.0 * gam);
-        numb = 2.0 * rhob / den;
+        numb = rhob / den;
         denb = -rho * rhob / den;
     }
-    const double ab = numb * b, bb = numb * a;
-    double vsb = ab;
-    vdb += -0.5 * ab + bb + 2.0 * vd * denb;
-    double vb = -0.5 * ab - bb + vdb;           // vd = v + dt Ebar_p
+    const double ab = numb * b, bb = numb * a2;  // adjoints of a2 and b
+    double vsb = 2.0 * ab;
+    vdb += -ab + bb + 2.0 * vd * denb;
+    double vb = -ab - bb + vdb;                 // vd = v + dt Ebar_p
     o.ebar_b = r.dt * vdb;
     o.ehat_b = 0.0;
     o.xb = 0.0;

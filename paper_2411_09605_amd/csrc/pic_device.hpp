@@ -55,6 +55,10 @@ template <int U, int NV> struct PBatch {
     double x[U], v[U][NV];
 };
 
+// Loads U particles per thread.  Entries past p1 repeat particle p1 - 1 (every range
+// holds at least one particle), so the loads are issued without a per-lane branch: the
+// compiler then knows how many are in flight and lets the next batch load while the
+// current one is processed.  Callers mask the entries past p1 with their own bounds test.
 template <int U, int NV>
 __device__ __forceinline__ void load_batch(PBatch<U, NV> &b, const double *__restrict__ X,
                                            const double *__restrict__ V, int64_t vstride,
@@ -62,19 +66,23 @@ __device__ __forceinline__ void load_batch(PBatch<U, NV> &b, const double *__res
 {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int64_t p = base + (int64_t)u * blockDim.x;
-        if (p < p1) {
-            b.x[u] = X[p];
+        const int64_t p = min(base + (int64_t)u * blockDim.x, p1 - 1);
+        b.x[u] = X[p];
 #pragma unroll
-            for (int c = 0; c < NV; ++c)
-                b.v[u][c] = V[c * vstride + p];
-        } else {
-            b.x[u] = 0.0;
-#pragma unroll
-            for (int c = 0; c < NV; ++c)
-                b.v[u][c] = 0.0;
-        }
+        for (int c = 0; c < NV; ++c)
+            b.v[u][c] = V[c * vstride + p];
     }
+}
+
+// Weights of the batch at base (W[p], or wu when W is null).  Issued before the next
+// batch's loads, so that waiting for them does not wait for the prefetch.
+template <int U>
+__device__ __forceinline__ void load_weights(double (&w)[U], const double *__restrict__ W,
+                                             double wu, int64_t base, int64_t p1)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        w[u] = W ? W[min(base + (int64_t)u * blockDim.x, p1 - 1)] : wu;
 }
 
 // Per-step record, laid out exactly like pic_diag.
@@ -158,16 +166,19 @@ __device__ __forceinline__ Stencil<1> stencil1(double xi)
     return s;
 }
 
+// Quadratic weights (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2, expanded as
+// t -+ d/2 with t = 1/8 + d^2/2 (five operations; gather and deposit share them).
 __device__ __forceinline__ Stencil<2> stencil2(double xi)
 {
     double f = floor(xi + 0.5);
     double d = xi - f;                       // in [-1/2, 1/2)
-    double a = 0.5 - d, b = 0.5 + d;
+    double hd = 0.5 * d;
+    double t = fma(hd, d, 0.125);
     Stencil<2> s;
     s.first = (int)f - 1;
-    s.w[0] = 0.5 * a * a;
+    s.w[0] = t - hd;
     s.w[1] = fma(-d, d, 0.75);
-    s.w[2] = 0.5 * b * b;
+    s.w[2] = t + hd;
     return s;
 }
 
@@ -191,9 +202,12 @@ __device__ __forceinline__ int wrap_node(int i, int ng)
 }
 
 // LDS tiles hold N_g nodes plus kGhost periodic copies on each side: node i of
-// component c sits at slot c * tw + kGhost + i (tw = N_g + 2 kGhost).  A stencil whose
-// nodes fall inside the padded range indexes the tile directly; only particles beyond
-// the ghost band go through the periodic wrap.
+// component c sits at slot c * tw + kGhost + i (tw = N_g + 2 kGhost).  The ORDER + 1
+// slots of a stencil are always consecutive: a stencil whose nodes fall inside the padded
+// range indexes the tile directly, and one beyond the ghost band has its first node
+// wrapped into [0, N_g), which keeps the rest inside the right ghost band (ORDER <=
+// kGhost).  So the LDS accesses of one stencil share a base address.
+static_assert(kGhost >= 2, "a wrapped quadratic stencil must fit the right ghost band");
 template <int ORDER> struct Slots {
     int n[ORDER + 1];
 };
@@ -201,17 +215,13 @@ template <int ORDER> struct Slots {
 template <int ORDER>
 __device__ __forceinline__ Slots<ORDER> slots_of(const Stencil<ORDER> &s, int ng)
 {
+    int b = s.first + kGhost;
+    if ((unsigned)b > (unsigned)(ng + 2 * kGhost - ORDER - 1))
+        b = wrap_node(s.first, ng) + kGhost;
     Slots<ORDER> o;
-    const int b = s.first + kGhost;
-    if ((unsigned)b <= (unsigned)(ng + 2 * kGhost - ORDER - 1)) {
 #pragma unroll
-        for (int k = 0; k <= ORDER; ++k)
-            o.n[k] = b + k;
-    } else {
-#pragma unroll
-        for (int k = 0; k <= ORDER; ++k)
-            o.n[k] = wrap_node(s.first + k, ng) + kGhost;
-    }
+    for (int k = 0; k <= ORDER; ++k)
+        o.n[k] = b + k;
     return o;
 }
 
@@ -851,21 +861,21 @@ template <int ORDER, int NV, bool EM> struct Half {
     double xh;           // x^{n+1/2}
 };
 
-// Gamma = sqrt(r), r = 1 + rho, rho = 2 num / den  (eq. (opt_solution)); r < 0 or a
-// non-finite r (e.g. den = 0) takes the fallback Gamma = 1 and is counted.
+// Gamma = sqrt(r), r = 1 + rho, rho = num2 / den with num2 = 2 num (eq. (opt_solution));
+// r < 0 or a non-finite r (e.g. den = 0) takes the fallback Gamma = 1 and is counted.
 // Because Gamma - 1 is tiny for almost every particle (O(dt^4) for ESEC2), the common
-// case |rho| < 1e-4 evaluates rho with a Newton-refined hardware reciprocal and sqrt(1 +
-// rho) by its Taylor series through rho^4 (truncation below 3e-22); any other rho is
-// evaluated with an IEEE division and square root.
-__device__ __forceinline__ double gamma_factor(double num, double den, int &fallbacks)
+// case |rho| < 1e-4 evaluates rho with the hardware reciprocal refined by one Newton step
+// (relative error about 2^-46, so below 1e-18 in Gamma) and sqrt(1 + rho) by its Taylor
+// series through rho^4 (truncation below 3e-22); any other rho is evaluated with an IEEE
+// division and square root.
+__device__ __forceinline__ double gamma_factor(double num2, double den, int &fallbacks)
 {
     double rc = __builtin_amdgcn_rcp(den);
     rc = fma(rc, fma(-den, rc, 1.0), rc);
-    rc = fma(rc, fma(-den, rc, 1.0), rc);
-    const double rho = 2.0 * num * rc;
+    const double rho = num2 * rc;
     if (fabs(rho) < 1e-4)
         return fma(rho, fma(rho, fma(rho, fma(rho, -0.0390625, 0.0625), -0.125), 0.5), 1.0);
-    const double rr = 1.0 + 2.0 * num / den;
+    const double rr = 1.0 + num2 / den;
     if (rr >= 0.0 && isfinite(rr))
         return sqrt(rr);
     ++fallbacks;
@@ -963,8 +973,9 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     // the trip count is the same for every thread of the workgroup (DEP = 2 needs whole
     // wavefronts in its deposit); particles past the end are masked with `valid`
     for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
-        if (b0 + stride < p1)
-            load_batch(nxt, X, V, r.vstride, base + stride, p1);
+        double wb[U];
+        load_weights(wb, r.w, r.wu, base, p1);
+        load_batch(nxt, X, V, r.vstride, base + stride, p1);   // the last one is discarded
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t p = base + (int64_t)u * blockDim.x;
@@ -974,7 +985,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
                     break;
             }
             const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], cur.v[u], es, bs);
-            const double q = valid ? (r.w ? r.w[p] : r.wu) * r.qs : 0.0;
+            const double q = valid ? wb[u] * r.qs : 0.0;
             double qv[T::ncur];
 #pragma unroll
             for (int c = 0; c < T::ncur; ++c)
@@ -1067,8 +1078,9 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
     for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
-        if (b0 + stride < p1)
-            load_batch(nxt, X, V, r.vstride, base + stride, p1);
+        double wb[U];
+        load_weights(wb, r.w, r.wu, base, p1);
+        load_batch(nxt, X, V, r.vstride, base + stride, p1);   // the last one is discarded
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t p = base + (int64_t)u * blockDim.x;
@@ -1106,15 +1118,17 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                 vd[1] = v[1] + r.dt * (e[1] + (hs.vs[2] * b[0] - hs.vs[0] * b[2]));
                 vd[2] = v[2] + r.dt * (e[2] + (hs.vs[0] * b[1] - hs.vs[1] * b[0]));
             }
-            // Gamma (eq. (opt_solution)); an imaginary or undefined root falls back to 1
-            double num = 0.0, den = 0.0;
+            // Gamma (eq. (opt_solution)); an imaginary or undefined root falls back to 1.
+            // num2 = 2 num = sum (2 v* - (v-dagger + v)) . (v-dagger - v)
+            double num2 = 0.0, den = 0.0;
 #pragma unroll
             for (int c = 0; c < NV; ++c) {
-                num = fma(hs.vs[c] - 0.5 * (vd[c] + v[c]), vd[c] - v[c], num);
+                const double a2 = fma(2.0, hs.vs[c], -(vd[c] + v[c]));
+                num2 = fma(a2, vd[c] - v[c], num2);
                 den = fma(vd[c], vd[c], den);
             }
             int fbp = 0;
-            const double g = gamma_factor(num, den, fbp);
+            const double g = gamma_factor(num2, den, fbp);
             double vn[NV];
             double v2 = 0.0;
 #pragma unroll
@@ -1123,7 +1137,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                 v2 = fma(vn[c], vn[c], v2);
             }
             const double xw = wrap_pos(hs.x1, r.L);
-            const double wp = valid ? (r.w ? r.w[p] : r.wu) : 0.0;
+            const double wp = valid ? wb[u] : 0.0;
             if (valid) {
 #pragma unroll
                 for (int c = 0; c < NV; ++c)

@@ -1,6 +1,7 @@
 // Host runtime of the PIC library: parameter validation, workspace layout, kernel
 // dispatch and diagnostics behind the C ABI declared in include/pic.h.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -52,10 +53,11 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
                                                                       std::min<int64_t>(per_thread, 64)),
                                                     kDefaultGrid);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid));
-    // chunks are whole multiples of the batch a workgroup loads at once (4 particles
-    // per thread), so only the last workgroup has a ragged tail
+    // chunks are whole wavefronts of particles; rounding only this far keeps the number of
+    // workgroups at (or one below) the one asked for, so that a grid of k workgroups per
+    // compute unit loads every unit alike
     int64_t chunk = (p->n_particles + nb - 1) / nb;
-    chunk = (chunk + 4 * t - 1) / (4 * t) * (4 * t);
+    chunk = (chunk + 63) / 64 * 64;
     nb = (p->n_particles + chunk - 1) / chunk;
     if (chunk_out)
         *chunk_out = chunk;
@@ -253,10 +255,11 @@ struct pic_ctx {
     int64_t records_read;     // records handed out so far (step index of the next one)
     int64_t steps_done;       // steps enqueued since init
     std::string err;
-    // event profiler: pairs of (class, start, stop) recorded around each launch
+    // event profiler: (class, start, stop) for each timed launch
     int profiling;
     struct Timed { int cls; hipEvent_t a, b; };
     std::vector<Timed> timed;
+    hipEvent_t kev[2];        // start/stop events handed to the next particle-pass launch
     std::vector<hipEvent_t> pool;
     double prof_ms[PIC_K_COUNT];
     int64_t prof_n[PIC_K_COUNT];
@@ -268,18 +271,30 @@ namespace {
 // kind: 0 = 1D-1V electrostatic, 1 = 1D-3V electrostatic, 2 = 1D-3V electromagnetic
 int kind_of(const pic_params *p) { return is_em(p) ? 2 : (p->nv == 3 ? 1 : 0); }
 
+// Launches a particle pass; when the profiler has handed it a pair of events, the runtime
+// stamps them with the start and end of this dispatch itself (no marker packets between
+// kernels, so the timeline being measured is the one that runs unprofiled).
+template <typename K, typename... A>
+void launch_pass(pic_ctx *c, K kernel, uint32_t lds, A... args)
+{
+    hipEvent_t e0 = c->kev[0], e1 = c->kev[1];
+    c->kev[0] = c->kev[1] = nullptr;
+    hipExtLaunchKernelGGL(kernel, dim3(c->run.nblocks), dim3(c->threads), lds, c->stream, e0, e1,
+                          0u, args...);
+}
+
 template <int ORDER, int NV, bool EM, int DEP>
 void launch_a(pic_ctx *c, int par, int64_t step, const double *X, const double *V)
 {
-    hipLaunchKernelGGL((k_pass_a<ORDER, NV, EM, DEP>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_a(&c->p), c->stream, c->run, c->wk, par, step, X, V);
+    launch_pass(c, k_pass_a<ORDER, NV, EM, DEP>, (uint32_t)lds_pass_a(&c->p), c->run, c->wk, par,
+                step, X, V);
 }
 
 template <int ORDER, int NV, bool EM, bool PRED, int DEP>
 void launch_b(pic_ctx *c, int par, const double *X, const double *V)
 {
-    hipLaunchKernelGGL((k_pass_b<ORDER, NV, EM, PRED, DEP>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_b(&c->p), c->stream, c->run, c->wk, par, X, V, c->b.x, c->b.v);
+    launch_pass(c, k_pass_b<ORDER, NV, EM, PRED, DEP>, (uint32_t)lds_pass_b(&c->p), c->run, c->wk,
+                par, X, V, c->b.x, c->b.v);
 }
 
 template <int ORDER, int NV, bool EM>
@@ -458,26 +473,45 @@ hipEvent_t take_event(pic_ctx *c)
     return e;
 }
 
-// Wraps one launch in a pair of events when the profiler is on.
+// Times what is enqueued in its scope when the profiler is on. A particle pass (one kernel)
+// takes the two events as launch arguments and is timed from its own dispatch; a group of
+// launches (the rebin) is bracketed by two recorded events.
 struct Timer {
     pic_ctx *c;
     int cls;
-    hipEvent_t a = nullptr;
-    Timer(pic_ctx *ctx, int k) : c(ctx), cls(k)
+    bool on_kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(pic_ctx *ctx, int k, bool one_kernel) : c(ctx), cls(k), on_kernel(one_kernel)
     {
-        if (c->profiling && (a = take_event(c)))
+        if (!c->profiling)
+            return;
+        a = take_event(c);
+        b = a ? take_event(c) : nullptr;
+        if (!b) {
+            if (a)
+                c->pool.push_back(a);
+            a = nullptr;
+            return;
+        }
+        if (on_kernel) {
+            c->kev[0] = a;
+            c->kev[1] = b;
+        } else {
             (void)hipEventRecord(a, c->stream);
+        }
     }
     ~Timer()
     {
         if (!a)
             return;
-        hipEvent_t b = take_event(c);
-        if (!b) {
+        if (on_kernel && c->kev[0] == a) {   // nothing was launched with them
+            c->kev[0] = c->kev[1] = nullptr;
             c->pool.push_back(a);
+            c->pool.push_back(b);
             return;
         }
-        (void)hipEventRecord(b, c->stream);
+        if (!on_kernel)
+            (void)hipEventRecord(b, c->stream);
         c->timed.push_back({cls, a, b});
     }
 };
@@ -552,6 +586,7 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     c->records_read = 0;
     c->steps_done = 0;
     c->profiling = 0;
+    c->kev[0] = c->kev[1] = nullptr;
     for (int k = 0; k < PIC_K_COUNT; ++k) {
         c->prof_ms[k] = 0.0;
         c->prof_n[k] = 0;
@@ -611,17 +646,17 @@ int pic_step(pic_ctx *c, int64_t n_steps)
         // after a rebin this step reads the sorted copy; pass B writes the caller's arrays
         const double *X = c->b.x, *V = c->b.v;
         if (K > 0 && n % K == 0) {
-            Timer t(c, PIC_K_REBIN);
+            Timer t(c, PIC_K_REBIN, false);
             rebin(c);
             X = c->wk.x2;
             V = c->wk.v2;
         }
         {
-            Timer t(c, PIC_K_PASS_A);
+            Timer t(c, PIC_K_PASS_A, true);
             dispatch(c, D_PASS_A, par, n, X, V);
         }
         {
-            Timer t(c, PIC_K_PASS_B);
+            Timer t(c, PIC_K_PASS_B, true);
             dispatch(c, D_PASS_B, par, n, X, V);
         }
         c->steps_done = n + 1;

@@ -98,10 +98,15 @@ def test_launch_shapes_agree():
     wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
     for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
         gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
-    # default shape: 512 threads, whole 4-particle batches per thread in every chunk
+    # default shape: 512 threads, chunks of whole wavefronts, one ragged last workgroup
     from paper_2411_09605_amd import Pic
     t, g, c = Pic.from_workload(wl).launch_shape()
-    assert t == 512 and c % (4 * 512) == 0 and (g - 1) * c < wl.n_particles <= g * c
+    assert t == 512 and c % 64 == 0 and (g - 1) * c < wl.n_particles <= g * c
+    # a grid asked for is the most launched; chunks are whole wavefronts
+    for gb in (64, 100, 768):
+        _, g, c = Pic.from_workload(wl, grid_blocks=gb).launch_shape()
+        assert g <= gb and c % 64 == 0 and (g - 1) * c < wl.n_particles <= g * c
+        assert c == -(-(-(-wl.n_particles // gb)) // 64) * 64
 
 
 def test_fast_particles_cross_several_cells():
@@ -277,3 +282,38 @@ def test_rebin_full_size_two_stream(mode):
     gpu.step(60)
     rec = gpu.diagnostics()
     assert rec["rel_energy_err"].max() < 1e-11
+
+
+def test_profiler_counts_and_bounds():
+    """The event profiler times every pass and rebin launch; the per-kernel times fit inside
+    the wall time of the same steps, and turning it on leaves the state as it was (up to the
+    order of the floating-point atomics that flush the current tiles)."""
+    _say("case: profiler, two-stream 2e5 x 512, rebin every 3")
+    import torch
+    from paper_2411_09605_amd import Pic
+    wl = workloads.two_stream(n_particles=200_000, n_cells=512)
+    a = Pic.from_workload(wl, rebin_every=3, track_ids=True)
+    b = Pic.from_workload(wl, rebin_every=3, track_ids=True)
+    steps = 12
+    a.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(a.stream)
+    a.step(steps)
+    e1.record(a.stream)
+    prof = a.profile_read()
+    wall = e0.elapsed_time(e1)
+    assert prof["pass_a"][1] == steps and prof["pass_b"][1] == steps
+    assert prof["rebin"][1] == steps // 3
+    for k in ("pass_a", "pass_b", "rebin"):
+        assert prof[k][0] > 0.0
+    assert sum(ms for ms, _ in prof.values()) <= wall * 1.001
+    assert a.profile_read()["pass_b"] == (0.0, 0)          # read resets
+    b.step(steps)
+    # the scatter of the rebin orders particles within a cell arbitrarily: match by id
+    sa, sb = gu.order_by_ids(a.state()), gu.order_by_ids(b.state())
+    assert gu.periodic_err(sa["x"], sb["x"], wl.length).max() <= 1e-10 * wl.length
+    for k in ("v", "E"):
+        scale = np.abs(sb[k]).max()
+        np.testing.assert_allclose(sa[k], sb[k], rtol=0, atol=1e-10 * scale)
+    a.destroy()
+    b.destroy()
