@@ -215,7 +215,7 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
                                                       const double *__restrict__ gm)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const int ng = r.ng, tw = r.tw, nrep = r.nrep;
     double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
     double *e1 = t4 + tw, *lt = e1 + ng;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(1024) void k_adj_grad(Run r, AdjWork aw, AdjParams 
                                                    const double *__restrict__ Gn)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const int ng = r.ng, tw = r.tw;
     double *rb = smem;
     for (int i = threadIdx.x; i < ng; i += blockDim.x)
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_adj_grad(Run r, AdjWork aw, AdjParams 
 // Gradient = sum of the workgroup partials in workgroup order (one workgroup).
 __global__ void k_adj_grad_final(AdjWork aw, int nblocks, int nparam, double *grad)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     for (int m = 0; m < nparam; ++m) {
         double s = 0.0;
         for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
@@ -406,7 +406,7 @@ __global__ void k_adj_grad_final(AdjWork aw, int nblocks, int nparam, double *gr
 // J = lw * sum_{n=1..N} W_E^n from the record ring (one workgroup, fixed order).
 __global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, double *loss)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     double s = 0.0;
     for (int64_t n = 1 + threadIdx.x; n <= nsteps; n += blockDim.x)
         s += wk.rec[n % rec_cap].field_e;

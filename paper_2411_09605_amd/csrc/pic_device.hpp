@@ -55,35 +55,90 @@ template <int U, int NV> struct PBatch {
     double x[U], v[U][NV];
 };
 
-// Loads U particles per thread.  Entries past p1 repeat particle p1 - 1 (every range
-// holds at least one particle), so the loads are issued without a per-lane branch: the
-// compiler then knows how many are in flight and lets the next batch load while the
-// current one is processed.  Callers mask the entries past p1 with their own bounds test.
+// Addressing of a wavefront's batch of 64 U consecutive particles starting at `start` (the
+// same in every lane): lane l takes start + l + 64 u.  Entries past p1 are clamped to
+// particle p1 - 1 (every range holds at least one particle), so loads are issued without a
+// per-lane branch.  The base is wavefront-uniform and the per-lane offset 32-bit, which
+// lets the loads use a scalar base register instead of 64-bit vector address arithmetic.
+struct BatchAddr {
+    int64_t b0;        // first particle of the batch, clamped to p1 - 1
+    unsigned lim;      // largest offset inside [b0, p1)
+    __device__ __forceinline__ BatchAddr(int64_t start, int64_t p1, unsigned span)
+    {
+        b0 = min(start, p1 - 1);
+        lim = (unsigned)min(p1 - 1 - b0, (int64_t)(span - 1));
+    }
+    __device__ __forceinline__ unsigned off(unsigned lane, int u) const
+    {
+        return min(lane + 64u * (unsigned)u, lim);
+    }
+};
+
+// Loads the batch at `start` (U particles per lane).  The compiler then knows how many
+// loads are in flight and lets the next batch load while the current one is processed.
+// Callers mask the entries past p1 with their own bounds test.
 template <int U, int NV>
 __device__ __forceinline__ void load_batch(PBatch<U, NV> &b, const double *__restrict__ X,
                                            const double *__restrict__ V, int64_t vstride,
-                                           int64_t base, int64_t p1)
+                                           int64_t start, int64_t p1)
 {
+    const BatchAddr a(start, p1, 64u * U);
+    const unsigned lane = threadIdx.x & 63;
+    const double *Xb = X + a.b0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int64_t p = min(base + (int64_t)u * blockDim.x, p1 - 1);
-        b.x[u] = X[p];
+        const unsigned o = a.off(lane, u);
+        b.x[u] = Xb[o];
 #pragma unroll
         for (int c = 0; c < NV; ++c)
-            b.v[u][c] = V[c * vstride + p];
+            b.v[u][c] = (V + c * vstride + a.b0)[o];
     }
 }
 
-// Weights of the batch at base (W[p], or wu when W is null).  Issued before the next
+// Weights of the batch at `start` (W[p], or wu when W is null).  Issued before the next
 // batch's loads, so that waiting for them does not wait for the prefetch.
 template <int U>
 __device__ __forceinline__ void load_weights(double (&w)[U], const double *__restrict__ W,
-                                             double wu, int64_t base, int64_t p1)
+                                             double wu, int64_t start, int64_t p1)
 {
+    const BatchAddr a(start, p1, 64u * U);
+    const unsigned lane = threadIdx.x & 63;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        w[u] = W ? W[min(base + (int64_t)u * blockDim.x, p1 - 1)] : wu;
+        w[u] = W ? (W + a.b0)[a.off(lane, u)] : wu;
 }
+
+// A workgroup's particles [p0, p1) go to its wavefronts in batches of 64 U consecutive
+// particles (lane l takes b + l + 64 u): wavefront w starts with batch w, and each then
+// claims the next unclaimed batch from a counter in LDS.  The hardware issues older
+// wavefronts first, so a fixed split leaves the youngest ones finishing alone at the end
+// of the pass; claiming batches as they go, the wavefronts of a workgroup finish within
+// about one batch of each other.  The counter is set by reset() before a barrier that
+// precedes the first claim.
+template <int U> struct WaveBatches {
+    static constexpr int kBatch = 64 * U;
+    int64_t p0;
+    int *ctr;
+    __device__ __forceinline__ WaveBatches(int64_t first, int *counter) : p0(first), ctr(counter) {}
+    __device__ __forceinline__ void reset() const
+    {
+        if (threadIdx.x == 0)
+            *ctr = (int)(blockDim.x >> 6);
+    }
+    // first particle of this wavefront's first batch (the same in every lane)
+    __device__ __forceinline__ int64_t first() const
+    {
+        return p0 + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * kBatch;
+    }
+    // claim the next batch (every lane of the wavefront active)
+    __device__ __forceinline__ int64_t claim() const
+    {
+        int k = 0;
+        if ((threadIdx.x & 63) == 0)
+            k = atomicAdd(ctr, 1);
+        return p0 + (int64_t)__builtin_amdgcn_readlane(k, 0) * kBatch;
+    }
+};
 
 // Per-step record, laid out exactly like pic_diag.
 struct DevRecord {
@@ -242,6 +297,21 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
     return acc;
 }
 
+// Add a workgroup's ghost-padded LDS current tile (ncomp components) into the global
+// current (hardware FP64 atomics); ghost slots go to their periodic nodes, zero entries
+// (common when the particles are cell-sorted) are skipped.
+__device__ __forceinline__ void tile_flush(const double *tile, double *J, int ncomp, int ng,
+                                           int tw)
+{
+    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+        const double val = tile[idx];
+        if (val != 0.0) {
+            const int c = idx / tw, j = idx % tw;
+            unsafeAtomicAdd(&J[c * ng + wrap_node(j - kGhost, ng)], val);
+        }
+    }
+}
+
 // Deposit accumulator of one thread for NC current components (tile stride tw).
 // DEP = 0: each particle adds its ORDER + 1 contributions with LDS atomics on a 64-bit
 //          fixed-point tile (below).
@@ -252,7 +322,7 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
 // DEP = 2: a register window shared by the wavefront (below).
 // DEP = 3: each particle adds its contributions with FP64 LDS atomics.
 // Every kind has init(side, run), add(...), finish(tile, tw, ng); after the workgroup has
-// synchronised, to_double(tile, n) leaves the tile as doubles (ready for tile_flush).
+// synchronised, flush_tile(tile, J, ncomp, ng, tw) adds the tile into the global current.
 template <int ORDER, int NC, int DEP> struct Depo;
 
 // DEP = 0.  A contribution c is stored as round(c 2^S): one FMA against 1.5 2^52 rounds
@@ -297,14 +367,18 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
         }
     }
     __device__ __forceinline__ void finish(double *, int, int) {}
-    // tile entries (n of them) back to doubles: integer sum times 2^-S plus the side tile
-    __device__ __forceinline__ void to_double(double *jt, int n)
+    // each entry back to a double (integer sum times 2^-S plus the side tile) on its way
+    // into the global current
+    __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
+                                               int tw)
     {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const long long iv = __double_as_longlong(jt[i]);
-            jt[i] = (double)iv * inv + side[i];
+        for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+            const double val = (double)__double_as_longlong(jt[idx]) * inv + side[idx];
+            if (val != 0.0) {
+                const int c = idx / tw, j = idx % tw;
+                unsafeAtomicAdd(&J[c * ng + wrap_node(j - kGhost, ng)], val);
+            }
         }
-        __syncthreads();
     }
 };
 
@@ -321,7 +395,11 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 3> {
                 atomicAdd(&jt[c * tw + sl.n[k]], q[c] * s.w[k]);
     }
     __device__ __forceinline__ void finish(double *, int, int) {}
-    __device__ __forceinline__ void to_double(double *, int) {}
+    __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
+                                               int tw)
+    {
+        tile_flush(jt, J, ncomp, ng, tw);
+    }
 };
 
 
@@ -344,7 +422,11 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
         anchor = 0;
         clear();
     }
-    __device__ __forceinline__ void to_double(double *, int) {}
+    __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
+                                               int tw)
+    {
+        tile_flush(jt, J, ncomp, ng, tw);
+    }
     __device__ __forceinline__ void flush(double *jt, int tw, int ng)
     {
         if (!live)
@@ -434,7 +516,11 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 2> {
         anchor = 0;
         clear();
     }
-    __device__ __forceinline__ void to_double(double *, int) {}
+    __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
+                                               int tw)
+    {
+        tile_flush(jt, J, ncomp, ng, tw);
+    }
     // all lanes of the wavefront active
     __device__ __forceinline__ void flush(double *jt, int tw, int ng)
     {
@@ -525,52 +611,98 @@ __device__ __forceinline__ double wrap_pos(double x, double L)
 }
 
 // --------------------------------------------------------------- block reductions
+// Workgroup barrier that orders LDS only.  __syncthreads also waits for every global load
+// and store the wavefront has in flight (particle writes, the last prefetch), which costs
+// microseconds at the end of a pass; exchanges through LDS need only the LDS operations
+// complete.  Global memory written before it is not made visible to the workgroup.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum (max) over the 64 lanes of a wavefront, all lanes active; every lane gets the same
+// value.  Within each row of 16 lanes, DPP butterflies (quad permutations, half-row and row
+// mirrors) leave the row's sum in all of its lanes (each addition pairs the same two
+// values in both lanes, so the lanes agree bit for bit); the four row sums are then read
+// from lanes 0, 16, 32, 48 and combined in that order.  No LDS round trips.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);    // row_half_mirror
+    v += dpp_mov<0x140>(v);    // row_mirror
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
+    v = fmax(v, dpp_mov<0xB1>(v));
+    v = fmax(v, dpp_mov<0x4E>(v));
+    v = fmax(v, dpp_mov<0x141>(v));
+    v = fmax(v, dpp_mov<0x140>(v));
+    return fmax(fmax(fmax(read_lane(v, 0), read_lane(v, 16)), read_lane(v, 32)), read_lane(v, 48));
+}
+
+// LDS for the block reductions: up to 4 values per wavefront of a 1024-thread workgroup.
+constexpr int kRedSize = 64;
+
+// Deterministic reduction of N values over the workgroup in one round of LDS: value k is
+// summed, or maximised where bit k of MAXMASK is set, always in the same fixed order for a
+// given blockDim (so a value gives the same result whatever is reduced beside it); every
+// thread gets the results.  red: kRedSize doubles of LDS.  The barriers order LDS only.
+template <unsigned MAXMASK, int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
+{
+    static_assert(N >= 1 && N * 16 <= kRedSize, "reduction too wide");
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    for (int k = 0; k < N; ++k)
+        v[k] = (MAXMASK >> k) & 1u ? wave_max(v[k]) : wave_sum(v[k]);
+    lds_barrier();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            red[k * 16 + wid] = v[k];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double *rk = red + k * 16;
+        double t;
+        if ((MAXMASK >> k) & 1u) {
+            t = rk[0];
+            for (int i = 1; i < nw; ++i)
+                t = fmax(t, rk[i]);
+        } else {
+            t = 0.0;
+            for (int i = 0; i < nw; ++i)
+                t += rk[i];
+        }
+        v[k] = t;
+    }
+    lds_barrier();
 }
 
-// Deterministic block sum (fixed order for a given blockDim); every thread gets the
-// result.  red: >= 16 doubles of LDS.
-__device__ double block_sum(double v, double *red)
+__device__ __forceinline__ double block_sum(double v, double *red)
 {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
-    if (lane == 0)
-        red[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i)
-        t += red[i];
-    __syncthreads();
-    return t;
+    double a[1] = {v};
+    block_reduce<0u>(a, red);
+    return a[0];
 }
 
-__device__ double block_max(double v, double *red)
+__device__ __forceinline__ double block_max(double v, double *red)
 {
-    v = wave_max(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
-    if (lane == 0)
-        red[wid] = v;
-    __syncthreads();
-    double t = red[0];
-    for (int i = 1; i < nw; ++i)
-        t = fmax(t, red[i]);
-    __syncthreads();
-    return t;
+    double a[1] = {v};
+    block_reduce<1u>(a, red);
+    return a[0];
 }
 
 // Mean of n values (LDS or global), identical in every workgroup of a launch.
@@ -614,6 +746,18 @@ __device__ __forceinline__ void rep_zero(double *J, int n, int nrep, int rs)
             J[(size_t)k * rs + i] = 0.0;
 }
 
+// Zero part `part` of `nparts` of every replica of the first n values of J (the parts
+// together cover them once), so that all workgroups of a launch share the clearing.
+__device__ __forceinline__ void rep_zero_part(double *J, int n, int nrep, int rs, int64_t part,
+                                              int64_t nparts)
+{
+    const int64_t tot = (int64_t)nrep * n;
+    const int64_t per = (tot + nparts - 1) / nparts;
+    const int64_t e1 = min(tot, (part + 1) * per);
+    for (int64_t e = part * per + threadIdx.x; e < e1; e += blockDim.x)
+        J[(e / n) * rs + e % n] = 0.0;
+}
+
 // The replica a workgroup adds into.
 __device__ __forceinline__ double *rep_slot(double *J, int nrep, int ng)
 {
@@ -650,21 +794,6 @@ __device__ __forceinline__ void tile_load_ghost(double *tile, const double *src,
     for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
         const int c = idx / tw, j = idx % tw;
         tile[idx] = src[c * ng + wrap_node(j - kGhost, ng)];
-    }
-}
-
-// Add a workgroup's ghost-padded LDS current tile (ncomp components) into the global
-// current (hardware FP64 atomics); ghost slots go to their periodic nodes, zero entries
-// (common when the particles are cell-sorted) are skipped.
-__device__ __forceinline__ void tile_flush(const double *tile, double *J, int ncomp, int ng,
-                                           int tw)
-{
-    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
-        const double val = tile[idx];
-        if (val != 0.0) {
-            const int c = idx / tw, j = idx % tw;
-            unsafeAtomicAdd(&J[c * ng + wrap_node(j - kGhost, ng)], val);
-        }
     }
 }
 
@@ -784,6 +913,41 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
         eb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (E0[i] + e1[i]);
     for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
         bb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (B0[i] + b1[i]);
+}
+
+// ESEC2 electrostatic fields of pass B: the predictor field E* into the interior of es
+// (exactly as predictor_fields computes it), E^{n+1} into e1 and the average into the
+// interior of eb (exactly as field_update computes them).  Two rounds of loads (the
+// replicas of j^{n,*}; those of j^{*,n+1/2} with E^n, which waits in eb) and one block
+// reduction for both means, instead of four rounds and two reductions.
+__device__ __forceinline__ void esec2_fields(const Run &r, const double *E, const double *J1,
+                                             const double *J2, double *es, double *e1,
+                                             double *eb, double *red, int nrep)
+{
+    const int ng = r.ng, rs = 3 * ng;
+    double *e0 = es + kGhost, *ebi = eb + kGhost;
+    double m[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const double a = rep_sum(J1, i, nrep, rs);
+        e0[i] = a;
+        m[0] += a;
+    }
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const double en0 = E[i];
+        const double b = rep_sum(J2, i, nrep, rs);
+        ebi[i] = en0;
+        e1[i] = b;
+        m[1] += b;
+    }
+    block_reduce<0u>(m, red);
+    const double mean1 = m[0] / ng, mean2 = m[1] / ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const double en0 = ebi[i];
+        e0[i] = en0 - r.hdt * (e0[i] - mean1);
+        const double en = en0 - r.dt * (e1[i] - mean2);
+        e1[i] = en;
+        ebi[i] = 0.5 * (en0 + en);
+    }
 }
 
 // W_E = h/2 sum |E|^2 and W_B = c^2 h/2 sum |B|^2 (section 5.1) of LDS/global fields;
@@ -938,54 +1102,61 @@ template <int ORDER, int NV, bool EM, int DEP>
 __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int par, int64_t step,
                                             const double *__restrict__ X,
                                             const double *__restrict__ V, int64_t p0,
-                                            int64_t p1, bool lead, double *smem, double *red)
+                                            int64_t p1, bool lead, double *smem, double *red,
+                                            int *wctr)
 {
     using T = TileSizes<NV, EM>;
     constexpr int U = kUnrollA<NV>;
     const int ng = r.ng, tw = r.tw;
+    const unsigned lane = threadIdx.x & 63;
     double *jt = smem;
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
     double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
+    const WaveBatches<U> wb(p0, wctr);
     PBatch<U, NV> cur, nxt;
-    int64_t base = p0 + threadIdx.x;
-    const int64_t stride = (int64_t)U * blockDim.x;
-    load_batch(cur, X, V, r.vstride, base, p1);
+    int64_t bcur = wb.first();
+    load_batch(cur, X, V, r.vstride, bcur, p1);
+    wb.reset();
     predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
     tile_zero(jt, T::ncur * tw);
     tile_zero(side, T::ncur * tw);
-    if (lead) {
-        // the predictor current of the next step accumulates into the other buffer
+    // the currents of the next step accumulate into the other buffers (nothing reads them
+    // in this pass): every workgroup clears its share
+    {
+        const int64_t part = p0 / r.chunk, nparts = r.nblocks;
         if (r.scheme != 1)
-            rep_zero(wk.J1[par ^ 1], T::ncur * ng, r.nrep, 3 * ng);
-        // the record of the state this step starts from, if not written yet
-        if (step > wk.st->recorded)
-            write_record(r, wk, step, red);
+            rep_zero_part(wk.J1[par ^ 1], T::ncur * ng, r.nrep, 3 * ng, part, nparts);
+        rep_zero_part(wk.J2[par ^ 1], T::ncur * ng, r.nrep, 3 * ng, part, nparts);
     }
-    __syncthreads();
+    // the record of the state this step starts from, if not written yet
+    if (lead && step > wk.st->recorded)
+        write_record(r, wk, step, red);
+    lds_barrier();
     ghost_fill(es, T::ne, ng, tw);
     if constexpr (EM)
         ghost_fill(bs, T::nb, ng, tw);
-    __syncthreads();
+    lds_barrier();
 
     Depo<ORDER, T::ncur, DEP> dep;
     dep.init(side, r);
-    // the trip count is the same for every thread of the workgroup (DEP = 2 needs whole
-    // wavefronts in its deposit); particles past the end are masked with `valid`
-    for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
-        double wb[U];
-        load_weights(wb, r.w, r.wu, base, p1);
-        load_batch(nxt, X, V, r.vstride, base + stride, p1);   // the last one is discarded
+    // whole wavefronts run the loop (DEP = 2 needs them in its deposit); particles past the
+    // end are masked with `valid`
+    while (bcur < p1) {
+        const int64_t bnxt = wb.claim();
+        const unsigned nval = (unsigned)min(p1 - bcur, (int64_t)(64 * U));
+        double w[U];
+        load_weights(w, r.w, r.wu, bcur, p1);
+        load_batch(nxt, X, V, r.vstride, bnxt, p1);   // the last one is discarded
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t p = base + (int64_t)u * blockDim.x;
-            const bool valid = p < p1;
+            const bool valid = lane + 64u * u < nval;
             if constexpr (DEP != 2) {
                 if (!valid)
                     break;
             }
             const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], cur.v[u], es, bs);
-            const double q = valid ? wb[u] * r.qs : 0.0;
+            const double q = valid ? w[u] * r.qs : 0.0;
             double qv[T::ncur];
 #pragma unroll
             for (int c = 0; c < T::ncur; ++c)
@@ -993,11 +1164,11 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
             dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv, valid, u == 0);
         }
         cur = nxt;
+        bcur = bnxt;
     }
     dep.finish(jt, tw, ng);
-    __syncthreads();
-    dep.to_double(jt, T::ncur * tw);
-    tile_flush(jt, rep_slot(wk.J2[par], r.nrep, ng), T::ncur, ng, tw);
+    lds_barrier();
+    dep.flush_tile(jt, rep_slot(wk.J2[par], r.nrep, ng), T::ncur, ng, tw);
 }
 
 template <int ORDER, int NV, bool EM, int DEP>
@@ -1007,10 +1178,11 @@ void k_pass_a(Run r, Work wk, int par, int64_t step,
                                                  const double *__restrict__ V)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, X, V, p0, min(r.np, p0 + r.chunk),
-                                    blockIdx.x == 0, smem, red);
+                                    blockIdx.x == 0, smem, red, &wctr);
 }
 
 // Pass B of step n (par = n & 1): new fields, second gather, Gamma, state write and
@@ -1023,15 +1195,17 @@ template <int ORDER, int NV, bool EM, bool PRED, int DEP>
 __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int par, const double *X,
                                             const double *V, double *Xo, double *Vo,
                                             int64_t p0, int64_t p1, bool lead, int slot,
-                                            double *smem, double *red)
+                                            double *smem, double *red, int *wctr)
 {
     using T = TileSizes<NV, EM>;
     constexpr int U = kUnrollB<NV>;
     const int ng = r.ng, tw = r.tw;
+    const unsigned lane = threadIdx.x & 63;
+    const WaveBatches<U> wb(p0, wctr);
     PBatch<U, NV> cur, nxt;
-    int64_t base = p0 + threadIdx.x;
-    const int64_t stride = (int64_t)U * blockDim.x;
-    load_batch(cur, X, V, r.vstride, base, p1);
+    int64_t bcur = wb.first();
+    load_batch(cur, X, V, r.vstride, bcur, p1);
+    wb.reset();
     double *jt = smem;
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
@@ -1043,13 +1217,17 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double *side = scratch + (EM ? 8 * ng : 0);   // [ncur][tw] FP64 side tile of the deposit
     const double *En = wk.Ef[par];
     const double *Bn = EM ? wk.Bf[par] : nullptr;
-    predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
-    field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red, r.nrep);
+    if (!EM && r.scheme == 0) {
+        esec2_fields(r, En, wk.J1[par], wk.J2[par], es, e1, eb, red, r.nrep);
+    } else {
+        predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
+        field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red, r.nrep);
+    }
     if constexpr (PRED) {
         tile_zero(jt, T::ncur * tw);
         tile_zero(side, T::ncur * tw);
     }
-    __syncthreads();
+    lds_barrier();
     ghost_fill(es, T::ne, ng, tw);
     ghost_fill(eb, T::ne, ng, tw);
     if constexpr (EM) {
@@ -1063,7 +1241,6 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
         if constexpr (EM)
             for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
                 wk.Bf[par ^ 1][i] = b1[i];
-        rep_zero(wk.J2[par ^ 1], T::ncur * ng, r.nrep, 3 * ng);
         double we, wb;
         field_energies(r, e1, b1, &we, &wb, red);
         if (threadIdx.x == 0) {
@@ -1071,20 +1248,23 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
             wk.st->wb = wb;
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     Depo<ORDER, T::ncur, DEP> dep;
     dep.init(side, r);
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
-    for (int64_t b0 = p0; b0 < p1; b0 += stride, base += stride) {
-        double wb[U];
-        load_weights(wb, r.w, r.wu, base, p1);
-        load_batch(nxt, X, V, r.vstride, base + stride, p1);   // the last one is discarded
+    while (bcur < p1) {
+        const int64_t bnxt = wb.claim();
+        const unsigned nval = (unsigned)min(p1 - bcur, (int64_t)(64 * U));
+        double w[U];
+        load_weights(w, r.w, r.wu, bcur, p1);
+        load_batch(nxt, X, V, r.vstride, bnxt, p1);   // the last one is discarded
+        double *Xob = Xo + bcur;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t p = base + (int64_t)u * blockDim.x;
-            const bool valid = p < p1;
+            const unsigned o = lane + 64u * u;
+            const bool valid = o < nval;
             if constexpr (DEP != 2) {
                 if (!valid)
                     break;
@@ -1137,12 +1317,12 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                 v2 = fma(vn[c], vn[c], v2);
             }
             const double xw = wrap_pos(hs.x1, r.L);
-            const double wp = valid ? wb[u] : 0.0;
+            const double wp = valid ? w[u] : 0.0;
             if (valid) {
 #pragma unroll
                 for (int c = 0; c < NV; ++c)
-                    Vo[c * r.vstride + p] = vn[c];
-                Xo[p] = xw;
+                    (Vo + c * r.vstride + bcur)[o] = vn[c];
+                Xob[o] = xw;
                 fb += fbp;
                 gdev = fmax(gdev, fabs(g - 1.0));
                 ke = fma(wp, v2, ke);
@@ -1159,23 +1339,22 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
             }
         }
         cur = nxt;
+        bcur = bnxt;
     }
     if constexpr (PRED)
         dep.finish(jt, tw, ng);
-    const double bke = block_sum(ke, red);
-    const double bgd = block_max(gdev, red);
-    const double bfb = block_sum((double)fb, red);
-    const double bnf = block_max((double)nonfinite, red);
+    // kinetic energy and fallbacks (sums), max |Gamma - 1| and the non-finite flag (maxima)
+    double sc[4] = {ke, (double)fb, gdev, (double)nonfinite};
+    block_reduce<0xcu>(sc, red);
     if (threadIdx.x == 0) {
-        wk.spart[slot * kNS + 0] = 0.5 * bke;
-        wk.spart[slot * kNS + 1] = bfb;
-        wk.spart[slot * kNS + 2] = bgd;
-        wk.spart[slot * kNS + 3] = bnf;
+        wk.spart[slot * kNS + 0] = 0.5 * sc[0];
+        wk.spart[slot * kNS + 1] = sc[1];
+        wk.spart[slot * kNS + 2] = sc[2];
+        wk.spart[slot * kNS + 3] = sc[3];
     }
     if constexpr (PRED) {
-        __syncthreads();
-        dep.to_double(jt, T::ncur * tw);
-        tile_flush(jt, rep_slot(wk.J1[par ^ 1], r.nrep, ng), T::ncur, ng, tw);
+        lds_barrier();
+        dep.flush_tile(jt, rep_slot(wk.J1[par ^ 1], r.nrep, ng), T::ncur, ng, tw);
     }
 }
 
@@ -1185,10 +1364,11 @@ void k_pass_b(Run r, Work wk, int par, const double *X,
                                                  const double *V, double *Xo, double *Vo)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, X, V, Xo, Vo, p0, min(r.np, p0 + r.chunk),
-                                          blockIdx.x == 0, blockIdx.x, smem, red);
+                                          blockIdx.x == 0, blockIdx.x, smem, red, &wctr);
 }
 
 // End of a pic_step call (one workgroup): the record of the newest state and a copy of
@@ -1206,7 +1386,7 @@ __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step,
 
 __global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_t step)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     finish_body(r, wk, par, step, red);
 }
 
@@ -1234,8 +1414,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
     }
     __syncthreads();
-    dep.to_double(jt, T::ncur * r.tw);
-    tile_flush(jt, rep_slot(wk.J1[0], r.nrep, r.ng), T::ncur, r.ng, r.tw);
+    dep.flush_tile(jt, rep_slot(wk.J1[0], r.nrep, r.ng), T::ncur, r.ng, r.tw);
 }
 
 template <int ORDER, int NV, bool EM>
@@ -1264,8 +1443,7 @@ __device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
     }
     __syncthreads();
-    dep.to_double(jt, r.tw);
-    tile_flush(jt, rep_slot(wk.J2[0], r.nrep, r.ng), 1, r.ng, r.tw);
+    dep.flush_tile(jt, rep_slot(wk.J2[0], r.nrep, r.ng), 1, r.ng, r.tw);
 }
 
 template <int ORDER>
@@ -1314,7 +1492,7 @@ __global__ __launch_bounds__(1024) void k_rebin_count(Run r, Work wk, const doub
 __global__ __launch_bounds__(1024) void k_scan_sums(const int64_t *a, int64_t n, int64_t seg,
                                                     int64_t *segsum)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const int64_t s0 = (int64_t)blockIdx.x * seg, s1 = min(n, s0 + seg);
     double acc = 0.0;     // counts are exact in double below 2^53
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x)
@@ -1449,7 +1627,7 @@ template <int NV>
 __global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double *__restrict__ X,
                                                          const double *__restrict__ V)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     init_particles_body<NV>(r, wk, X, V, p0, min(r.np, p0 + r.chunk), blockIdx.x, red);
 }
@@ -1545,7 +1723,7 @@ __device__ void init_finish_body(const Run &r, const Work &wk, double *red)
 
 __global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     init_finish_body(r, wk, red);
 }
 
@@ -1609,7 +1787,8 @@ template <int ORDER, int NV, bool EM, int DEP>
 __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
     const int64_t step = *b.stepc;
     const int par = (int)(step & 1);
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
@@ -1618,8 +1797,8 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
         const Run r = uniform_copy(br.r);
         const Work wk = uniform_copy(br.wk);
         pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, b.X + br.poff, b.V + br.poff, item.p0,
-                                        item.p1, item.slot == 0, smem, red);
-        __syncthreads();
+                                        item.p1, item.slot == 0, smem, red, &wctr);
+        lds_barrier();
     }
 }
 
@@ -1627,7 +1806,8 @@ template <int ORDER, int NV, bool EM, bool PRED, int DEP>
 __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
 {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
     const int par = (int)(*b.stepc & 1);
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
@@ -1636,8 +1816,8 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
         const Work wk = uniform_copy(br.wk);
         pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, b.X + br.poff, b.V + br.poff,
                                               b.X + br.poff, b.V + br.poff, item.p0, item.p1,
-                                              item.slot == 0, item.slot, smem, red);
-        __syncthreads();
+                                              item.slot == 0, item.slot, smem, red, &wctr);
+        lds_barrier();
     }
 }
 
@@ -1651,7 +1831,7 @@ __global__ void k_batch_tick(Batch b)
 // One workgroup per run: newest record and fields into the caller's arrays.
 __global__ __launch_bounds__(1024) void k_batch_finish(Batch b)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const int64_t step = *b.stepc;
     const BatchRun &br = b.runs[blockIdx.x];
     const Run r = uniform_copy(br.r);
@@ -1662,7 +1842,7 @@ __global__ __launch_bounds__(1024) void k_batch_finish(Batch b)
 template <int NV>
 __global__ __launch_bounds__(1024) void k_batch_init_particles(Batch b)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
@@ -1722,7 +1902,7 @@ __global__ __launch_bounds__(1024) void k_batch_cn_init(Batch b)
 
 __global__ __launch_bounds__(1024) void k_batch_init_finish(Batch b)
 {
-    __shared__ double red[16];
+    __shared__ double red[kRedSize];
     const BatchRun &br = b.runs[blockIdx.x];
     const Run r = uniform_copy(br.r);
     const Work wk = uniform_copy(br.wk);

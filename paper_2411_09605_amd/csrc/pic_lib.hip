@@ -22,10 +22,12 @@ namespace {
 
 thread_local std::string g_last_error;
 
-constexpr int kDefaultThreads = 512;
-// Default grid cap: two workgroups per CU; more workgroups only add prologue work and
-// global flushes of the per-workgroup current tiles.
-constexpr int kDefaultGrid = 512;
+// Default launch: one 1024-thread workgroup per CU (256 CUs).  A workgroup's wavefronts
+// share its particles dynamically, which balances them only within the workgroup, so one
+// workgroup per CU lets every CU finish with all of its wavefronts busy; more workgroups
+// would also add prologue work and global flushes of the per-workgroup current tiles.
+constexpr int kDefaultThreads = 1024;
+constexpr int kDefaultGrid = 256;
 constexpr int kDefaultRecords = 4096;
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;

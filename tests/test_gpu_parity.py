@@ -93,15 +93,18 @@ def test_tiny_and_minimum_grids(n, ng, order):
 
 
 def test_launch_shapes_agree():
-    """Different workgroup sizes and counts give the same result (to roundoff)."""
+    """Different workgroup sizes and counts give the same result (to roundoff): wavefronts
+    claiming many batches each (1024 x 7, 256 x 13), wavefronts left without a batch
+    (512 x 300), and workgroups with a single partial batch (1024 x 3000)."""
     _say("case: launch shapes")
     wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
-    for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
+    for bt, gb in [(64, 7), (256, 13), (512, 300), (1024, 7), (1024, 3000)]:
+        _say(f"  shape {bt} x {gb}")
         gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
-    # default shape: 512 threads, chunks of whole wavefronts, one ragged last workgroup
+    # default shape: 1024 threads, chunks of whole wavefronts, one ragged last workgroup
     from paper_2411_09605_amd import Pic
     t, g, c = Pic.from_workload(wl).launch_shape()
-    assert t == 512 and c % 64 == 0 and (g - 1) * c < wl.n_particles <= g * c
+    assert t == 1024 and c % 64 == 0 and (g - 1) * c < wl.n_particles <= g * c
     # a grid asked for is the most launched; chunks are whole wavefronts
     for gb in (64, 100, 768):
         _, g, c = Pic.from_workload(wl, grid_blocks=gb).launch_shape()
