@@ -107,10 +107,12 @@ typedef struct {
                               only when nv == 3                                           */
     uint32_t flags;        /* enum pic_flag bits                                         */
     int32_t block_threads; /* threads per workgroup of the particle passes: 0 = default
-                              (1024), else a multiple of 64 in [64, 1024]                 */
-    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default, with
-                              m = ceil(N_p / block_threads): min(max(ceil(m / 8),
-                              min(m, 64)), 256).  Each workgroup takes a chunk of
+                              (1024, halved down to 64 while N_p < 512 block_threads,
+                              i.e. two particles per thread of 256 workgroups), else a
+                              multiple of 64 in [64, 1024]                                */
+    int32_t grid_blocks;   /* workgroups of the particle passes: 0 = default,
+                              min(256, ceil(N_p / (2 block_threads))), one per CU.
+                              Each workgroup takes a chunk of
                               ceil(N_p / grid) particles rounded up to a multiple of 64,
                               so the grid launched may be smaller than asked             */
     int32_t deposit_mode;  /* enum pic_deposit_mode                                      */

@@ -216,7 +216,13 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
 {
     extern __shared__ double smem[];
     __shared__ double red[kRedSize];
+    __shared__ int wctr;
     const int ng = r.ng, tw = r.tw, nrep = r.nrep;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    const int64_t p1 = min(r.np, p0 + r.chunk);
+    // wavefronts claim batches of 64 particles (the counter is set before the barriers below)
+    const WaveBatches<1> wb(p0, &wctr);
+    wb.reset();
     double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
     double *e1 = t4 + tw, *lt = e1 + ng;
     double *esm = lt + ng, *ebm = esm + tw, *tm = ebm + tw, *e1m = tm + tw;   // STAGE 4
@@ -259,11 +265,12 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
         ghost_fill(t4, 1, ng, tw);
     __syncthreads();
 
-    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
     Depo<ORDER, 1, 3> dep;          // adjoint values: FP64 atomics (no fixed-point scale)
     dep.init(nullptr, r);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t b = wb.first(); b < p1; b = wb.claim()) {
+        const int64_t p = b + (threadIdx.x & 63);
+        if (p >= p1)
+            continue;
         const double x = X[p], v = V[p], axp = aw.ax[p], avp = aw.av[p];
         const double qp = (r.w ? r.w[p] : r.wu) * r.qs;
         const AdjOut<ORDER, STAGE == 4 ? 3 : STAGE> o =

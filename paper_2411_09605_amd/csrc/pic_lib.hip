@@ -22,12 +22,14 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Default launch: one 1024-thread workgroup per CU (256 CUs).  A workgroup's wavefronts
-// share its particles dynamically, which balances them only within the workgroup, so one
-// workgroup per CU lets every CU finish with all of its wavefronts busy; more workgroups
-// would also add prologue work and global flushes of the per-workgroup current tiles.
+// Default launch: one workgroup per CU (the part has 256 CUs), 1024 threads wide.  A
+// workgroup's wavefronts share its particles dynamically, which balances them only within
+// the workgroup, so one workgroup per CU lets every CU finish with all of its wavefronts
+// busy; more workgroups would also add prologue work and global flushes of the
+// per-workgroup current tiles.  Runs with fewer than two particles per thread of such a
+// launch take narrower workgroups, so that they still spread over the CUs.
+constexpr int kCUs = 256;
 constexpr int kDefaultThreads = 1024;
-constexpr int kDefaultGrid = 256;
 constexpr int kDefaultRecords = 4096;
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
@@ -40,20 +42,25 @@ struct Layout {
     size_t total;
 };
 
-int threads_of(const pic_params *p) { return p->block_threads ? p->block_threads : kDefaultThreads; }
+int threads_of(const pic_params *p)
+{
+    if (p->block_threads)
+        return p->block_threads;
+    const int64_t per_cu = (p->n_particles + kCUs - 1) / kCUs;
+    int t = kDefaultThreads;
+    while (t > 64 && per_cu < 2 * t)
+        t /= 2;
+    return t;
+}
 
 int records_of(const pic_params *p) { return p->record_capacity ? p->record_capacity : kDefaultRecords; }
 
 int blocks_of(const pic_params *p, int64_t *chunk_out)
 {
     const int t = threads_of(p);
-    // default: about 8 batches of particles per thread, at least min(N / t, 64) and at
-    // most kDefaultGrid workgroups (fewer workgroups, fewer prologues and tile flushes)
-    const int64_t per_thread = (p->n_particles + t - 1) / t;
+    // default: one workgroup per CU, with at least two particles per thread
     int64_t nb = p->grid_blocks ? p->grid_blocks
-                                : std::min<int64_t>(std::max<int64_t>((per_thread + 7) / 8,
-                                                                      std::min<int64_t>(per_thread, 64)),
-                                                    kDefaultGrid);
+                                : std::min<int64_t>(kCUs, (p->n_particles + 2 * t - 1) / (2 * t));
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid));
     // chunks are whole wavefronts of particles; rounding only this far keeps the number of
     // workgroups at (or one below) the one asked for, so that a grid of k workgroups per

@@ -101,10 +101,15 @@ def test_launch_shapes_agree():
     for bt, gb in [(64, 7), (256, 13), (512, 300), (1024, 7), (1024, 3000)]:
         _say(f"  shape {bt} x {gb}")
         gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb)
-    # default shape: 1024 threads, chunks of whole wavefronts, one ragged last workgroup
+    # default shape: one workgroup per CU (256), 1024 threads halved while there are fewer
+    # than two particles per thread; chunks of whole wavefronts, one ragged last workgroup
     from paper_2411_09605_amd import Pic
     t, g, c = Pic.from_workload(wl).launch_shape()
-    assert t == 1024 and c % 64 == 0 and (g - 1) * c < wl.n_particles <= g * c
+    n = wl.n_particles
+    t_exp = 1024
+    while t_exp > 64 and -(-n // 256) < 2 * t_exp:
+        t_exp //= 2
+    assert t == t_exp and g <= 256 and c % 64 == 0 and (g - 1) * c < n <= g * c
     # a grid asked for is the most launched; chunks are whole wavefronts
     for gb in (64, 100, 768):
         _, g, c = Pic.from_workload(wl, grid_blocks=gb).launch_shape()
