@@ -1319,10 +1319,14 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
             const double xw = wrap_pos(hs.x1, r.L);
             const double wp = valid ? w[u] : 0.0;
             if (valid) {
+                // the new state is written through to memory (system-scope relaxed stores):
+                // nothing in this pass reads it back, and lines left dirty in the L2 of each
+                // XCD would be written back at the end of the kernel
 #pragma unroll
                 for (int c = 0; c < NV; ++c)
-                    (Vo + c * r.vstride + bcur)[o] = vn[c];
-                Xob[o] = xw;
+                    __hip_atomic_store(&(Vo + c * r.vstride + bcur)[o], vn[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&Xob[o], xw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 fb += fbp;
                 gdev = fmax(gdev, fabs(g - 1.0));
                 ke = fma(wp, v2, ke);
