@@ -297,6 +297,61 @@ __device__ __forceinline__ double gather1(const double *tile, const Stencil<ORDE
     return acc;
 }
 
+// Gathers that deposit nothing at the same position use the field as a polynomial in the
+// particle's offset d inside its cell (d as in stencil<ORDER>): sum_k E_k w_k(d) expanded
+// once per cell in the prologue, so a gather costs ORDER FMAs instead of the weights and
+// ORDER + 1 FMAs.  Coefficient tile: slot s holds the ORDER + 1 coefficients of the cell
+// whose stencil starts at slot s.
+template <int ORDER> struct Cell {
+    int base;            // slot of the stencil's first node
+    double d;
+};
+
+template <int ORDER> __device__ __forceinline__ Cell<ORDER> cell_of(double xi, int ng)
+{
+    const double f = floor(ORDER == 2 ? xi + 0.5 : xi);
+    Cell<ORDER> c;
+    c.d = xi - f;
+    Stencil<ORDER> s;
+    s.first = (int)f - (ORDER == 2 ? 1 : 0);
+    c.base = slots_of<ORDER>(s, ng).n[0];
+    return c;
+}
+
+template <int ORDER>
+__device__ __forceinline__ double gather_poly(const double *ct, const Cell<ORDER> &c)
+{
+    const double *k = ct + (ORDER + 1) * c.base;
+    if constexpr (ORDER == 1)
+        return fma(c.d, k[1], k[0]);
+    else
+        return fma(c.d, fma(c.d, k[2], k[1]), k[0]);
+}
+
+// Coefficients of every cell of a tile from its interior t[0..ng) (periodic).
+//   tent:      E(d) = E_0 + d (E_1 - E_0)
+//   quadratic: E(d) = (E_0 + E_2)/8 + 3 E_1/4 + d (E_2 - E_0)/2 + d^2 ((E_0 + E_2)/2 - E_1)
+template <int ORDER>
+__device__ __forceinline__ void coef_fill(double *ct, const double *t, int ng, int tw)
+{
+    for (int s = threadIdx.x; s < tw - ORDER; s += blockDim.x) {
+        const double e0 = t[wrap_node(s - kGhost, ng)], e1 = t[wrap_node(s - kGhost + 1, ng)];
+        if constexpr (ORDER == 1) {
+            ct[2 * s] = e0;
+            ct[2 * s + 1] = e1 - e0;
+        } else {
+            const double e2 = t[wrap_node(s - kGhost + 2, ng)];
+            ct[3 * s] = 0.125 * (e0 + e2) + 0.75 * e1;
+            ct[3 * s + 1] = 0.5 * (e2 - e0);
+            ct[3 * s + 2] = 0.5 * (e0 + e2) - e1;
+        }
+    }
+}
+
+// Offset (in doubles) of the coefficient tiles in the LDS of the passes, kept even so that
+// tent coefficients can be read as pairs.
+__host__ __device__ constexpr int coef_offset(int doubles) { return (doubles + 1) & ~1; }
+
 // Add a workgroup's ghost-padded LDS current tile (ncomp components) into the global
 // current (hardware FP64 atomics); ghost slots go to their periodic nodes, zero entries
 // (common when the particles are cell-sorted) are skipped.
@@ -1058,21 +1113,22 @@ __device__ __forceinline__ void rotate_half(const double u[3], const double t[3]
     o[2] = (u[2] + (u[0] * t[1] - u[1] * t[0]) + ut * t[2]) * inv;
 }
 
-// tiles: es[ne][tw] predictor E, bs[2][tw] predictor B (EM), ghost-padded
+// tiles: EM: es[3][tw] predictor E, bs[2][tw] predictor B, ghost-padded; ES: es is the
+// coefficient tile of E_x (coef_fill)
 template <int ORDER, int NV, bool EM>
 __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x, const double v[NV],
                                                         const double *es, const double *bs)
 {
     Half<ORDER, NV, EM> o;
     const double xs = fma(r.hdt, v[0], x);
-    const Stencil<ORDER> s = stencil<ORDER>(xs * r.inv_h);
-    const Slots<ORDER> n = slots_of<ORDER>(s, r.ng);
     if constexpr (NV == 1) {
-        o.vs[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
+        o.vs[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h, r.ng)), v[0]);
     } else {
         double u[3], t[3];
-        u[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
         if constexpr (EM) {
+            const Stencil<ORDER> s = stencil<ORDER>(xs * r.inv_h);
+            const Slots<ORDER> n = slots_of<ORDER>(s, r.ng);
+            u[0] = fma(r.hdt, gather1<ORDER>(es, s, n), v[0]);
             u[1] = fma(r.hdt, gather1<ORDER>(es + r.tw, s, n), v[1]);
             u[2] = fma(r.hdt, gather1<ORDER>(es + 2 * r.tw, s, n), v[2]);
             const Stencil<ORDER> sh = stencil<ORDER>(xs * r.inv_h - 0.5);
@@ -1081,6 +1137,7 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
             t[1] = r.hdt * (r.bext[1] + gather1<ORDER>(bs, sh, nh));
             t[2] = r.hdt * (r.bext[2] + gather1<ORDER>(bs + r.tw, sh, nh));
         } else {
+            u[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h, r.ng)), v[0]);
             u[1] = v[1];
             u[2] = v[2];
             t[0] = r.hdt * r.bext[0];
@@ -1113,6 +1170,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     double *es = jt + T::ncur * tw;
     double *bs = es + T::ne * tw;
     double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
+    double *ct = smem + coef_offset((2 * T::ncur + T::ne + T::nb) * tw);   // ES: coefficients
     const WaveBatches<U> wb(p0, wctr);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
@@ -1133,10 +1191,14 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     if (lead && step > wk.st->recorded)
         write_record(r, wk, step, red);
     lds_barrier();
-    ghost_fill(es, T::ne, ng, tw);
-    if constexpr (EM)
+    if constexpr (EM) {
+        ghost_fill(es, T::ne, ng, tw);
         ghost_fill(bs, T::nb, ng, tw);
+    } else {
+        coef_fill<ORDER>(ct, es + kGhost, ng, tw);
+    }
     lds_barrier();
+    const double *eg = EM ? es : ct;     // what half_step gathers E from
 
     Depo<ORDER, T::ncur, DEP> dep;
     dep.init(side, r);
@@ -1155,7 +1217,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
                 if (!valid)
                     break;
             }
-            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], cur.v[u], es, bs);
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], cur.v[u], eg, bs);
             const double q = valid ? w[u] * r.qs : 0.0;
             double qv[T::ncur];
 #pragma unroll
@@ -1215,6 +1277,9 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double *b1 = e1 + T::ne * ng;
     double *scratch = b1 + T::nb * ng;
     double *side = scratch + (EM ? 8 * ng : 0);   // [ncur][tw] FP64 side tile of the deposit
+    // ES: coefficient tiles of E* and E-bar
+    double *cts = smem + coef_offset((2 * T::ncur + 2 * T::ne + 2 * T::nb) * tw + (T::ne + T::nb + (EM ? 8 : 0)) * ng);
+    double *ctb = cts + (ORDER + 1) * tw;
     const double *En = wk.Ef[par];
     const double *Bn = EM ? wk.Bf[par] : nullptr;
     if (!EM && r.scheme == 0) {
@@ -1228,12 +1293,16 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
         tile_zero(side, T::ncur * tw);
     }
     lds_barrier();
-    ghost_fill(es, T::ne, ng, tw);
-    ghost_fill(eb, T::ne, ng, tw);
     if constexpr (EM) {
+        ghost_fill(es, T::ne, ng, tw);
+        ghost_fill(eb, T::ne, ng, tw);
         ghost_fill(bs, T::nb, ng, tw);
         ghost_fill(bb, T::nb, ng, tw);
+    } else {
+        coef_fill<ORDER>(cts, es + kGhost, ng, tw);
+        coef_fill<ORDER>(ctb, eb + kGhost, ng, tw);
     }
+    const double *eg = EM ? es : cts;    // what half_step gathers E* from
     if (lead) {
         // publish E^{n+1} (B^{n+1}) and their energies; clear the other centred current
         for (int i = threadIdx.x; i < T::ne * ng; i += blockDim.x)
@@ -1270,17 +1339,17 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                     break;
             }
             const double *v = cur.v[u];
-            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], v, es, bs);
-            const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
-            const Slots<ORDER> n = slots_of<ORDER>(s, ng);
+            const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], v, eg, bs);
             double vd[NV];
             if constexpr (NV == 1) {
-                vd[0] = fma(r.dt, gather1<ORDER>(eb, s, n), v[0]);
+                vd[0] = fma(r.dt, gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng)), v[0]);
             } else {
                 double e[3], b[3];
-                e[0] = gather1<ORDER>(eb, s, n);
                 b[0] = r.bext[0];
                 if constexpr (EM) {
+                    const Stencil<ORDER> s = stencil<ORDER>(hs.xh * r.inv_h);
+                    const Slots<ORDER> n = slots_of<ORDER>(s, ng);
+                    e[0] = gather1<ORDER>(eb, s, n);
                     e[1] = gather1<ORDER>(eb + tw, s, n);
                     e[2] = gather1<ORDER>(eb + 2 * tw, s, n);
                     const Stencil<ORDER> sh = stencil<ORDER>(hs.xh * r.inv_h - 0.5);
@@ -1288,6 +1357,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                     b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
                     b[2] = r.bext[2] + gather1<ORDER>(bb + tw, sh, nh);
                 } else {
+                    e[0] = gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
                     e[1] = 0.0;
                     e[2] = 0.0;
                     b[1] = r.bext[1];

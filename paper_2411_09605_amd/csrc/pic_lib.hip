@@ -32,7 +32,8 @@ constexpr int kCUs = 256;
 constexpr int kDefaultThreads = 1024;
 constexpr int kDefaultRecords = 4096;
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxLds = 64 * 1024;
+// LDS a workgroup may use on gfx950 (160 KB per CU, all of it available to one workgroup)
+constexpr size_t kMaxLds = 160 * 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -78,22 +79,30 @@ bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI; }
 // LDS bytes of the largest kernel of this configuration.
 size_t tile_width(const pic_params *p) { return (size_t)p->n_cells + 2 * kGhost; }
 
-size_t lds_pass_a(const pic_params *p)
+// LDS (bytes) of the particle passes for cells n_cells, shape order `order`; the layouts
+// are those of pass_a_body and pass_b_body (tiles ghost-padded, tw = N_g + 2 kGhost).
+size_t lds_pass_a_of(bool em, int order, size_t ng)
 {
-    // jt | es | bs | deposit side tile   (ghost-padded tiles)
-    const size_t tw = tile_width(p);
-    return is_em(p) ? (3 + 3 + 2 + 3) * tw * 8 : 3 * tw * 8;
+    const size_t tw = ng + 2 * kGhost;
+    // EM: jt[3] | es[3] | bs[2] | side[3];  ES: jt | es | side | coefficients[order + 1]
+    return em ? (3 + 3 + 2 + 3) * tw * 8
+              : ((size_t)pic::coef_offset((int)(3 * tw)) + (order + 1) * tw) * 8;
 }
 
-// Deposit-only kernels (initial predictor deposit, charge deposit): tile + side tile.
+size_t lds_pass_b_of(bool em, int order, size_t ng)
+{
+    const size_t tw = ng + 2 * kGhost;
+    // EM: jt[3] | es[3] | bs[2] | eb[3] | bb[2] | e1[3] | b1[2] | CN scratch[8] | side[3]
+    // ES: jt | es | eb | e1 | side | coefficients of E* and E-bar [2][order + 1]
+    return em ? (3 + 3 + 2 + 3 + 2 + 3) * tw * 8 + (3 + 2 + 8) * ng * 8
+              : ((size_t)pic::coef_offset((int)(4 * tw + ng)) + 2 * (order + 1) * tw) * 8;
+}
+
+size_t lds_pass_a(const pic_params *p) { return lds_pass_a_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
+
 size_t lds_deposit(const pic_params *p) { return 2 * (is_em(p) ? 3 : 1) * tile_width(p) * 8; }
 
-size_t lds_pass_b(const pic_params *p)
-{
-    // jt | es | bs | eb | bb (padded) | e1 | b1 | (EM) Crank-Nicolson scratch | side tile
-    const size_t tw = tile_width(p), ng = p->n_cells;
-    return is_em(p) ? (3 + 3 + 2 + 3 + 2 + 3) * tw * 8 + (3 + 2 + 8) * ng * 8 : 4 * tw * 8 + ng * 8;
-}
+size_t lds_pass_b(const pic_params *p) { return lds_pass_b_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
 
 size_t lds_rebin(const pic_params *p) { return (size_t)kVBins * p->n_cells * 8; }
 
@@ -1143,8 +1152,8 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
 
     const size_t tw = (size_t)maxg + 2 * kGhost;
     const size_t ng = (size_t)maxg;
-    c->lds_a = em ? 11 * tw * 8 : 3 * tw * 8;
-    c->lds_b = em ? 16 * tw * 8 + 13 * ng * 8 : 4 * tw * 8 + ng * 8;
+    c->lds_a = lds_pass_a_of(em, p->shape_order, ng);
+    c->lds_b = lds_pass_b_of(em, p->shape_order, ng);
     c->lds_dep = 2 * (em ? 3 : 1) * tw * 8;
     c->lds_gauss = 3 * ng * 8;
 

@@ -45,6 +45,14 @@ def test_validation_accepts_and_sizes():
         assert P.workspace_size(p) > 0
 
 
+def test_validation_lds_limits():
+    """The largest grids the particle passes fit in LDS (160 KB per workgroup)."""
+    import paper_2411_09605_amd as P
+    for kw in [dict(n_cells=1854), dict(shape_order=1, n_cells=2200),
+               dict(nv=3, scheme="emec_li", n_cells=701)]:
+        assert P.validate(_good(**kw)) == 0, (kw, P.last_error())
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(nv=2), -1), (dict(scheme=7), -1), (dict(nv=1, scheme="emec_li"), -1),
     (dict(shape_order=3), -1), (dict(n_particles=0), -1), (dict(n_cells=4), -1),
@@ -53,6 +61,8 @@ def test_validation_accepts_and_sizes():
     (dict(nv=3, b_ext=(float("inf"), 0, 0)), -1), (dict(block_threads=100), -1),
     (dict(grid_blocks=100000), -1), (dict(deposit_mode=9), -1), (dict(rebin_every=-1), -1),
     (dict(n_cells=100000), -6), (dict(nv=3, scheme="emec_li", n_cells=4096), -6),
+    # 160 KB of LDS per workgroup: quadratic ES pass B needs 11 N_g + 80 doubles, EM 29 N_g + 128
+    (dict(n_cells=1855), -6), (dict(nv=3, scheme="emec_li", n_cells=702), -6),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P

@@ -325,3 +325,14 @@ def test_profiler_counts_and_bounds():
         np.testing.assert_allclose(sa[k], sb[k], rtol=0, atol=1e-10 * scale)
     a.destroy()
     b.destroy()
+
+
+def test_large_grids_beyond_64k_lds():
+    """Grids whose pass tiles need more than 64 KB of LDS per workgroup (up to 160 KB): a
+    quadratic electrostatic run on 1800 cells and an electromagnetic one on 600."""
+    _say("case: two-stream 1e5 x 1800 cells, esec2, order 2")
+    wl = workloads.two_stream(n_particles=100_000, n_cells=1800, steps=3)
+    gu.run_pair(wl, 3)
+    _say("case: weibel 6e4 x 600 cells, emec_li, order 2")
+    wl = workloads.weibel(n_particles=60_000, n_cells=600, steps=3)
+    gu.run_pair(wl, 3)
