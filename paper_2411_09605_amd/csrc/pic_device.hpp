@@ -769,7 +769,9 @@ __device__ __forceinline__ double block_mean(const double *a, int n, double *red
     return block_sum(s, red) / n;
 }
 
-constexpr int kMaxRep = 16;      // upper bound on the replicas of the currents
+// Upper bound on the replicas of the currents: a default launch (256 workgroups) uses 8,
+// and a prologue keeps the replicas of two currents in flight at once.
+constexpr int kMaxRep = 8;
 
 // Component value J[i] summed over nrep <= kMaxRep replicas of stride rs, in replica
 // order; the loads are issued together.
@@ -970,11 +972,33 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
         bb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (B0[i] + b1[i]);
 }
 
+// ESEC2 electrostatic predictor field E* of pass A into the interior of es, exactly as
+// predictor_fields computes it, with one round of loads: the replicas of j^{n,*} and E^n
+// together (E^n waits in `stash`, ng doubles of LDS that the caller overwrites later).
+__device__ __forceinline__ void esec2_predictor(const Run &r, const double *E, const double *J1,
+                                                double *es, double *stash, double *red, int nrep)
+{
+    const int ng = r.ng, rs = 3 * ng;
+    double *e0 = es + kGhost;
+    double m[1] = {0.0};
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        const double en0 = E[i];
+        const double a = rep_sum(J1, i, nrep, rs);
+        e0[i] = a;
+        stash[i] = en0;
+        m[0] += a;
+    }
+    block_reduce<0u>(m, red);
+    const double mean = m[0] / ng;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        e0[i] = stash[i] - r.hdt * (e0[i] - mean);
+}
+
 // ESEC2 electrostatic fields of pass B: the predictor field E* into the interior of es
 // (exactly as predictor_fields computes it), E^{n+1} into e1 and the average into the
-// interior of eb (exactly as field_update computes them).  Two rounds of loads (the
-// replicas of j^{n,*}; those of j^{*,n+1/2} with E^n, which waits in eb) and one block
-// reduction for both means, instead of four rounds and two reductions.
+// interior of eb (exactly as field_update computes them).  One round of loads (the
+// replicas of j^{n,*} and of j^{*,n+1/2}, and E^n, which waits in eb) and one block
+// reduction for both means.
 __device__ __forceinline__ void esec2_fields(const Run &r, const double *E, const double *J1,
                                              const double *J2, double *es, double *e1,
                                              double *eb, double *red, int nrep)
@@ -983,15 +1007,13 @@ __device__ __forceinline__ void esec2_fields(const Run &r, const double *E, cons
     double *e0 = es + kGhost, *ebi = eb + kGhost;
     double m[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-        const double a = rep_sum(J1, i, nrep, rs);
-        e0[i] = a;
-        m[0] += a;
-    }
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
         const double en0 = E[i];
+        const double a = rep_sum(J1, i, nrep, rs);
         const double b = rep_sum(J2, i, nrep, rs);
+        e0[i] = a;
         ebi[i] = en0;
         e1[i] = b;
+        m[0] += a;
         m[1] += b;
     }
     block_reduce<0u>(m, red);
@@ -1176,7 +1198,10 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     int64_t bcur = wb.first();
     load_batch(cur, X, V, r.vstride, bcur, p1);
     wb.reset();
-    predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
+    if (!EM && r.scheme == 0)
+        esec2_predictor(r, wk.Ef[par], wk.J1[par], es, ct, red, r.nrep);
+    else
+        predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
     tile_zero(jt, T::ncur * tw);
     tile_zero(side, T::ncur * tw);
     // the currents of the next step accumulate into the other buffers (nothing reads them
