@@ -975,19 +975,31 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
 // ESEC2 electrostatic predictor field E* of pass A into the interior of es, exactly as
 // predictor_fields computes it, with one round of loads: the replicas of j^{n,*} and E^n
 // together (E^n waits in `stash`, ng doubles of LDS that the caller overwrites later).
-__device__ __forceinline__ void esec2_predictor(const Run &r, const double *E, const double *J1,
-                                                double *es, double *stash, double *red, int nrep)
+// Split in two so that the caller can issue its first particle loads in between: load
+// completions are counted in order, so loads issued before these would be waited for too.
+__device__ __forceinline__ double esec2_predictor_load(const Run &r, const double *E,
+                                                       const double *J1, double *es,
+                                                       double *stash, int nrep)
 {
     const int ng = r.ng, rs = 3 * ng;
     double *e0 = es + kGhost;
-    double m[1] = {0.0};
+    double m = 0.0;
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
         const double en0 = E[i];
         const double a = rep_sum(J1, i, nrep, rs);
         e0[i] = a;
         stash[i] = en0;
-        m[0] += a;
+        m += a;
     }
+    return m;
+}
+
+__device__ __forceinline__ void esec2_predictor_finish(const Run &r, double *es,
+                                                       const double *stash, double *red, double part)
+{
+    const int ng = r.ng;
+    double *e0 = es + kGhost;
+    double m[1] = {part};
     block_reduce<0u>(m, red);
     const double mean = m[0] / ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x)
@@ -998,14 +1010,18 @@ __device__ __forceinline__ void esec2_predictor(const Run &r, const double *E, c
 // (exactly as predictor_fields computes it), E^{n+1} into e1 and the average into the
 // interior of eb (exactly as field_update computes them).  One round of loads (the
 // replicas of j^{n,*} and of j^{*,n+1/2}, and E^n, which waits in eb) and one block
-// reduction for both means.
-__device__ __forceinline__ void esec2_fields(const Run &r, const double *E, const double *J1,
-                                             const double *J2, double *es, double *e1,
-                                             double *eb, double *red, int nrep)
+// reduction for both means; split in two like esec2_predictor.
+struct Sums2 {
+    double a, b;
+};
+
+__device__ __forceinline__ Sums2 esec2_fields_load(const Run &r, const double *E, const double *J1,
+                                                   const double *J2, double *es, double *e1,
+                                                   double *eb, int nrep)
 {
     const int ng = r.ng, rs = 3 * ng;
     double *e0 = es + kGhost, *ebi = eb + kGhost;
-    double m[2] = {0.0, 0.0};
+    Sums2 m = {0.0, 0.0};
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
         const double en0 = E[i];
         const double a = rep_sum(J1, i, nrep, rs);
@@ -1013,9 +1029,18 @@ __device__ __forceinline__ void esec2_fields(const Run &r, const double *E, cons
         e0[i] = a;
         ebi[i] = en0;
         e1[i] = b;
-        m[0] += a;
-        m[1] += b;
+        m.a += a;
+        m.b += b;
     }
+    return m;
+}
+
+__device__ __forceinline__ void esec2_fields_finish(const Run &r, double *es, double *e1,
+                                                    double *eb, double *red, Sums2 part)
+{
+    const int ng = r.ng;
+    double *e0 = es + kGhost, *ebi = eb + kGhost;
+    double m[2] = {part.a, part.b};
     block_reduce<0u>(m, red);
     const double mean1 = m[0] / ng, mean2 = m[1] / ng;
     for (int i = threadIdx.x; i < ng; i += blockDim.x) {
@@ -1196,12 +1221,15 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     const WaveBatches<U> wb(p0, wctr);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
-    load_batch(cur, X, V, r.vstride, bcur, p1);
     wb.reset();
-    if (!EM && r.scheme == 0)
-        esec2_predictor(r, wk.Ef[par], wk.J1[par], es, ct, red, r.nrep);
-    else
+    if (!EM && r.scheme == 0) {
+        const double part = esec2_predictor_load(r, wk.Ef[par], wk.J1[par], es, ct, r.nrep);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
+        esec2_predictor_finish(r, es, ct, red, part);
+    } else {
         predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
+    }
     tile_zero(jt, T::ncur * tw);
     tile_zero(side, T::ncur * tw);
     // the currents of the next step accumulate into the other buffers (nothing reads them
@@ -1291,7 +1319,6 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     const WaveBatches<U> wb(p0, wctr);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
-    load_batch(cur, X, V, r.vstride, bcur, p1);
     wb.reset();
     double *jt = smem;
     double *es = jt + T::ncur * tw;
@@ -1307,10 +1334,14 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     double *ctb = cts + (ORDER + 1) * tw;
     const double *En = wk.Ef[par];
     const double *Bn = EM ? wk.Bf[par] : nullptr;
+    // the first particle batch is issued after the field loads (see esec2_predictor)
     if (!EM && r.scheme == 0) {
-        esec2_fields(r, En, wk.J1[par], wk.J2[par], es, e1, eb, red, r.nrep);
+        const Sums2 part = esec2_fields_load(r, En, wk.J1[par], wk.J2[par], es, e1, eb, r.nrep);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
+        esec2_fields_finish(r, es, e1, eb, red, part);
     } else {
         predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
         field_update(r, wk, En, Bn, wk.J2[par], e1, b1, eb, bb, scratch, red, r.nrep);
     }
     if constexpr (PRED) {
