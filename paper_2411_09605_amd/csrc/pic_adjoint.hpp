@@ -186,11 +186,11 @@ __device__ __forceinline__ void adj_current2(const Run &r, const AdjParams &ap, 
                                              double *jb2, double *red)
 {
     const int ng = r.ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < ng; i += nthreads())
         lt[i] = fma(ap.lbw, e1[i], lam[i]) + 0.5 * rep_sum(G1, i, r.nrep, ng);
     __syncthreads();
     const double m = block_mean(lt, ng, red);
-    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < ng; i += nthreads())
         jb2[kGhost + i] = -r.dt * (lt[i] - m);
 }
 
@@ -241,17 +241,17 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
             rep_zero(aw.G1[q ^ 1], ng, nrep, ng);
     }
     if constexpr (STAGE >= 3) {
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             t4[kGhost + i] = rep_sum(aw.G2[q], i, nrep, ng);
         const double m = block_mean(t4 + kGhost, ng, red);
         if (blockIdx.x == 0) {
             // adjoint of E^n for step n - 1; clear the other parity's G2
-            for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            for (int i = threadIdx.x; i < ng; i += nthreads())
                 aw.lam[q ^ 1][i] = lt[i] + 0.5 * rep_sum(aw.G1[q], i, nrep, ng) + t4[kGhost + i];
             rep_zero(aw.G2[q ^ 1], ng, nrep, ng);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             t4[kGhost + i] = -r.hdt * (t4[kGhost + i] - m);
     } else {
         tile_zero(t4, tw);
@@ -310,8 +310,8 @@ __global__ __launch_bounds__(1024) void k_adj_sample(Run r, AdjParams ap, const 
                                                      const double *__restrict__ Gn, double *X,
                                                      double *V)
 {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < r.np;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t p = (int64_t)blockIdx.x * nthreads() + threadIdx.x; p < r.np;
+         p += (int64_t)gridDim.x * nthreads()) {
         const double target = U[p] * r.L;
         double x = target;
         for (int it = 0; it < 60 && ap.n_modes > 0; ++it) {
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_adj_grad(Run r, AdjWork aw, AdjParams 
     __shared__ double red[kRedSize];
     const int ng = r.ng, tw = r.tw;
     double *rb = smem;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < ng; i += nthreads())
         rb[kGhost + i] = -aw.rhobar[i];
     __syncthreads();
     ghost_fill(rb, 1, ng, tw);
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_adj_grad(Run r, AdjWork aw, AdjParams 
         acc[m] = 0.0;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double x = X0[p];
         const double q = (r.w ? r.w[p] : r.wu) * r.qs;
         const Stencil<ORDER> s = stencil<ORDER>(x * r.inv_h);
@@ -402,7 +402,7 @@ __global__ void k_adj_grad_final(AdjWork aw, int nblocks, int nparam, double *gr
     __shared__ double red[kRedSize];
     for (int m = 0; m < nparam; ++m) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int b = threadIdx.x; b < nblocks; b += nthreads())
             s += aw.gpart[(size_t)b * nparam + m];
         s = block_sum(s, red);
         if (threadIdx.x == 0)
@@ -415,7 +415,7 @@ __global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, doub
 {
     __shared__ double red[kRedSize];
     double s = 0.0;
-    for (int64_t n = 1 + threadIdx.x; n <= nsteps; n += blockDim.x)
+    for (int64_t n = 1 + threadIdx.x; n <= nsteps; n += nthreads())
         s += wk.rec[n % rec_cap].field_e;
     s = block_sum(s, red);
     if (threadIdx.x == 0)
@@ -427,7 +427,7 @@ __global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, doub
 __global__ void k_adj_save_grids(const double *E, const double *J1, const double *J2, int ng,
                                  int nrep, double *dst)
 {
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         dst[i] = E[i];
         dst[ng + i] = rep_sum(J1, i, nrep, 3 * ng);
         dst[2 * ng + i] = rep_sum(J2, i, nrep, 3 * ng);

@@ -47,7 +47,19 @@ template <int NV> constexpr int kWavesPerEU = NV == 1 ? 6 : 1;
 // Largest workgroup of the particle passes.
 template <int NV> constexpr int kMaxThreads = 1024;
 
-// A thread's batch of U particles, base + u * blockDim.x (u < U), loaded together.  The
+// Threads of the (1-D) workgroup: the group-size field of the implicit kernel arguments
+// (a 16-bit field at byte 12), read with a scalar load of the dword that holds it.
+// blockDim.x also allows for a partial last workgroup, which these launches never have,
+// and is read with a vector load; vector loads complete in order, so waiting for it
+// would also wait for every particle load issued before it.  (The dispatch packet holds
+// the same number but may sit in host memory.)
+__device__ __forceinline__ unsigned nthreads()
+{
+    typedef const __attribute__((address_space(4))) unsigned int *kernarg_ptr;
+    return ((kernarg_ptr)__builtin_amdgcn_implicitarg_ptr())[3] & 0xffffu;
+}
+
+// A thread's batch of U particles, base + u * nthreads() (u < U), loaded together.  The
 // particle loops keep the next batch's loads in flight while they compute on the current
 // one (and the first batch's loads in flight during the field prologue), so HBM latency
 // overlaps LDS and ALU work.
@@ -123,7 +135,7 @@ template <int U> struct WaveBatches {
     __device__ __forceinline__ void reset() const
     {
         if (threadIdx.x == 0)
-            *ctr = (int)(blockDim.x >> 6);
+            *ctr = (int)(nthreads() >> 6);
     }
     // first particle of this wavefront's first batch (the same in every lane)
     __device__ __forceinline__ int64_t first() const
@@ -334,7 +346,7 @@ __device__ __forceinline__ double gather_poly(const double *ct, const Cell<ORDER
 template <int ORDER>
 __device__ __forceinline__ void coef_fill(double *ct, const double *t, int ng, int tw)
 {
-    for (int s = threadIdx.x; s < tw - ORDER; s += blockDim.x) {
+    for (int s = threadIdx.x; s < tw - ORDER; s += nthreads()) {
         const double e0 = t[wrap_node(s - kGhost, ng)], e1 = t[wrap_node(s - kGhost + 1, ng)];
         if constexpr (ORDER == 1) {
             ct[2 * s] = e0;
@@ -358,7 +370,7 @@ __host__ __device__ constexpr int coef_offset(int doubles) { return (doubles + 1
 __device__ __forceinline__ void tile_flush(const double *tile, double *J, int ncomp, int ng,
                                            int tw)
 {
-    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < ncomp * tw; idx += nthreads()) {
         const double val = tile[idx];
         if (val != 0.0) {
             const int c = idx / tw, j = idx % tw;
@@ -427,7 +439,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
     __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
                                                int tw)
     {
-        for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < ncomp * tw; idx += nthreads()) {
             const double val = (double)__double_as_longlong(jt[idx]) * inv + side[idx];
             if (val != 0.0) {
                 const int c = idx / tw, j = idx % tw;
@@ -717,7 +729,7 @@ template <unsigned MAXMASK, int N>
 __device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
 {
     static_assert(N >= 1 && N * 16 <= kRedSize, "reduction too wide");
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (nthreads() + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k)
         v[k] = (MAXMASK >> k) & 1u ? wave_max(v[k]) : wave_sum(v[k]);
@@ -764,7 +776,7 @@ __device__ __forceinline__ double block_max(double v, double *red)
 __device__ __forceinline__ double block_mean(const double *a, int n, double *red)
 {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = threadIdx.x; i < n; i += nthreads())
         s += a[i];
     return block_sum(s, red) / n;
 }
@@ -791,7 +803,7 @@ __device__ __forceinline__ double rep_sum(const double *J, int i, int nrep, int 
 // Sum of the replicas of the first n values of J into dst (LDS or global).
 __device__ __forceinline__ void rep_gather(double *dst, const double *J, int n, int nrep, int rs)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = threadIdx.x; i < n; i += nthreads())
         dst[i] = rep_sum(J, i, nrep, rs);
 }
 
@@ -799,7 +811,7 @@ __device__ __forceinline__ void rep_gather(double *dst, const double *J, int n, 
 __device__ __forceinline__ void rep_zero(double *J, int n, int nrep, int rs)
 {
     for (int k = 0; k < nrep; ++k)
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
+        for (int i = threadIdx.x; i < n; i += nthreads())
             J[(size_t)k * rs + i] = 0.0;
 }
 
@@ -811,7 +823,7 @@ __device__ __forceinline__ void rep_zero_part(double *J, int n, int nrep, int rs
     const int64_t tot = (int64_t)nrep * n;
     const int64_t per = (tot + nparts - 1) / nparts;
     const int64_t e1 = min(tot, (part + 1) * per);
-    for (int64_t e = part * per + threadIdx.x; e < e1; e += blockDim.x)
+    for (int64_t e = part * per + threadIdx.x; e < e1; e += nthreads())
         J[(e / n) * rs + e % n] = 0.0;
 }
 
@@ -823,13 +835,13 @@ __device__ __forceinline__ double *rep_slot(double *J, int nrep, int ng)
 
 __device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = threadIdx.x; i < n; i += nthreads())
         dst[i] = src[i];
 }
 
 __device__ __forceinline__ void tile_zero(double *dst, int n)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = threadIdx.x; i < n; i += nthreads())
         dst[i] = 0.0;
 }
 
@@ -837,7 +849,7 @@ __device__ __forceinline__ void tile_zero(double *dst, int n)
 // interior must be written and visible).
 __device__ __forceinline__ void ghost_fill(double *tile, int ncomp, int ng, int tw)
 {
-    for (int idx = threadIdx.x; idx < ncomp * 2 * kGhost; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < ncomp * 2 * kGhost; idx += nthreads()) {
         const int c = idx / (2 * kGhost), j = idx % (2 * kGhost);
         const int slot = j < kGhost ? j : ng + j;
         tile[c * tw + slot] = tile[c * tw + wrap_node(slot - kGhost, ng) + kGhost];
@@ -848,7 +860,7 @@ __device__ __forceinline__ void ghost_fill(double *tile, int ncomp, int ng, int 
 __device__ __forceinline__ void tile_load_ghost(double *tile, const double *src, int ncomp,
                                                 int ng, int tw)
 {
-    for (int idx = threadIdx.x; idx < ncomp * tw; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < ncomp * tw; idx += nthreads()) {
         const int c = idx / tw, j = idx % tw;
         tile[idx] = src[c * ng + wrap_node(j - kGhost, ng)];
     }
@@ -877,22 +889,22 @@ __device__ __forceinline__ void predictor_fields(const Run &r, const double *E, 
     const int ng = r.ng, tw = r.tw, rs = 3 * ng;
     double *e0 = es + kGhost, *b0 = bs + kGhost;
     if (r.scheme == 1) {
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             e0[i] = E[i];
         return;
     }
     if (r.scheme == 0) {
         // the summed current goes through the tile (each thread rereads its own entries)
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             e0[i] = rep_sum(J, i, nrep, rs);
         const double mean = block_mean(e0, ng, red);
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             e0[i] = E[i] - r.hdt * (e0[i] - mean);
         return;
     }
     const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
     const double *By = B, *Bz = B + ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         e0[i] = Ex[i] - r.hdt * rep_sum(J, i, nrep, rs);
         e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - rep_sum(J, ng + i, nrep, rs));
         e0[2 * tw + i] = Ez[i] + r.hdt * (r.c2 * dminus(By, i, ng, r.inv_h) - rep_sum(J, 2 * ng + i, nrep, rs));
@@ -918,10 +930,10 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
     const int ng = r.ng, tw = r.tw, rs = 3 * ng;
     if (r.scheme != 2) {
         // the summed current goes through e1 (each thread rereads its own entries)
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < ng; i += nthreads())
             e1[i] = rep_sum(J, i, nrep, rs);
         const double mean = block_mean(e1, ng, red);
-        for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        for (int i = threadIdx.x; i < ng; i += nthreads()) {
             const double e0 = E[i];
             const double en = e0 - r.dt * (e1[i] - mean);
             e1[i] = en;
@@ -939,7 +951,7 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
     __syncthreads();
     const double a = r.hdt, s = a * a * r.c2, ih2 = r.inv_h * r.inv_h;
     const double *Ey = E0 + ng, *Ez = E0 + 2 * ng, *By = B0, *Bz = B0 + ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         const int ip = i + 1 == ng ? 0 : i + 1, im = i == 0 ? ng - 1 : i - 1;
         e1[i] = E0[i] - r.dt * rep_sum(J, i, nrep, rs);
         R[i] = Ey[i] + s * (Ey[ip] - 2.0 * Ey[i] + Ey[im]) * ih2
@@ -948,7 +960,7 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
                     + r.dt * r.c2 * dminus(By, i, ng, r.inv_h) - r.dt * rep_sum(J, 2 * ng + i, nrep, rs);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         double ay = 0.0, az = 0.0;
         for (int j = 0; j < ng; ++j) {
             int k = i - j;
@@ -960,15 +972,15 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
         e1[2 * ng + i] = az;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         const int ip = i + 1 == ng ? 0 : i + 1;
         b1[ng + i] = Bz[i] - a * ((Ey[ip] + e1[ng + ip]) - (Ey[i] + e1[ng + i])) * r.inv_h;
         b1[i] = By[i] + a * ((Ez[ip] + e1[2 * ng + ip]) - (Ez[i] + e1[2 * ng + i])) * r.inv_h;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < 3 * ng; i += nthreads())
         eb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (E0[i] + e1[i]);
-    for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
         bb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (B0[i] + b1[i]);
 }
 
@@ -984,7 +996,7 @@ __device__ __forceinline__ double esec2_predictor_load(const Run &r, const doubl
     const int ng = r.ng, rs = 3 * ng;
     double *e0 = es + kGhost;
     double m = 0.0;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         const double en0 = E[i];
         const double a = rep_sum(J1, i, nrep, rs);
         e0[i] = a;
@@ -1002,7 +1014,7 @@ __device__ __forceinline__ void esec2_predictor_finish(const Run &r, double *es,
     double m[1] = {part};
     block_reduce<0u>(m, red);
     const double mean = m[0] / ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < ng; i += nthreads())
         e0[i] = stash[i] - r.hdt * (e0[i] - mean);
 }
 
@@ -1022,7 +1034,7 @@ __device__ __forceinline__ Sums2 esec2_fields_load(const Run &r, const double *E
     const int ng = r.ng, rs = 3 * ng;
     double *e0 = es + kGhost, *ebi = eb + kGhost;
     Sums2 m = {0.0, 0.0};
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         const double en0 = E[i];
         const double a = rep_sum(J1, i, nrep, rs);
         const double b = rep_sum(J2, i, nrep, rs);
@@ -1043,7 +1055,7 @@ __device__ __forceinline__ void esec2_fields_finish(const Run &r, double *es, do
     double m[2] = {part.a, part.b};
     block_reduce<0u>(m, red);
     const double mean1 = m[0] / ng, mean2 = m[1] / ng;
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         const double en0 = ebi[i];
         e0[i] = en0 - r.hdt * (e0[i] - mean1);
         const double en = en0 - r.dt * (e1[i] - mean2);
@@ -1060,10 +1072,10 @@ __device__ __forceinline__ void field_energies(const Run &r, const double *E, co
     const bool em = r.scheme == 2;
     const int ng = r.ng, ne = em ? 3 : 1;
     double se = 0.0, sb = 0.0;
-    for (int i = threadIdx.x; i < ne * ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < ne * ng; i += nthreads())
         se += E[i] * E[i];
     if (em)
-        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
             sb += B[i] * B[i];
     *we = 0.5 * r.h * block_sum(se, red);
     *wb = em ? 0.5 * r.c2 * r.h * block_sum(sb, red) : 0.0;
@@ -1074,7 +1086,7 @@ __device__ __forceinline__ void field_energies(const Run &r, const double *E, co
 __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
 {
     double ke = 0.0, fb = 0.0, gd = 0.0, nf = 0.0;
-    for (int b = threadIdx.x; b < r.nblocks; b += blockDim.x) {
+    for (int b = threadIdx.x; b < r.nblocks; b += nthreads()) {
         ke += wk.spart[b * kNS + 0];
         fb += wk.spart[b * kNS + 1];
         gd = fmax(gd, wk.spart[b * kNS + 2]);
@@ -1361,10 +1373,10 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     const double *eg = EM ? es : cts;    // what half_step gathers E* from
     if (lead) {
         // publish E^{n+1} (B^{n+1}) and their energies; clear the other centred current
-        for (int i = threadIdx.x; i < T::ne * ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < T::ne * ng; i += nthreads())
             wk.Ef[par ^ 1][i] = e1[i];
         if constexpr (EM)
-            for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+            for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
                 wk.Bf[par ^ 1][i] = b1[i];
         double we, wb;
         field_energies(r, e1, b1, &we, &wb, red);
@@ -1507,10 +1519,10 @@ __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step,
 {
     if (step > wk.st->recorded)
         write_record(r, wk, step, red);
-    for (int i = threadIdx.x; i < 3 * r.ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < 3 * r.ng; i += nthreads())
         wk.E[i] = wk.Ef[par][i];
     if (r.scheme == 2)
-        for (int i = threadIdx.x; i < 2 * r.ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < 2 * r.ng; i += nthreads())
             wk.B[i] = wk.Bf[par][i];
 }
 
@@ -1535,7 +1547,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
     __syncthreads();
     Depo<ORDER, T::ncur, 0> dep;
     dep.init(side, r);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double q = (r.w ? r.w[p] : r.wu) * r.qs;
         double qv[T::ncur];
 #pragma unroll
@@ -1568,7 +1580,7 @@ __device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
     __syncthreads();
     Depo<ORDER, 1, 0> dep;
     dep.init(side, r);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double q[1] = {(r.w ? r.w[p] : r.wu) * r.qs};
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
     }
@@ -1605,15 +1617,15 @@ __global__ __launch_bounds__(1024) void k_rebin_count(Run r, Work wk, const doub
 {
     extern __shared__ int ihist[];
     const int nbins = kVBins * r.ng;
-    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    for (int i = threadIdx.x; i < nbins; i += nthreads())
         ihist[i] = 0;
     __syncthreads();
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads())
         atomicAdd(&ihist[sort_key(r, X[p], V[p])], 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    for (int i = threadIdx.x; i < nbins; i += nthreads())
         wk.hist[(int64_t)i * r.nblocks + blockIdx.x] = ihist[i];
 }
 
@@ -1625,7 +1637,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(const int64_t *a, int64_t n,
     __shared__ double red[kRedSize];
     const int64_t s0 = (int64_t)blockIdx.x * seg, s1 = min(n, s0 + seg);
     double acc = 0.0;     // counts are exact in double below 2^53
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x)
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += nthreads())
         acc += (double)a[i];
     acc = block_sum(acc, red);
     if (threadIdx.x == 0)
@@ -1640,7 +1652,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(int64_t *segsum, int nseg)
     const int64_t mine = t < nseg ? segsum[t] : 0;
     buf[t] = mine;
     __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    for (int off = 1; off < (int)nthreads(); off <<= 1) {
         const int64_t add = t >= off ? buf[t - off] : 0;
         __syncthreads();
         buf[t] += add;
@@ -1658,12 +1670,12 @@ __global__ __launch_bounds__(1024) void k_scan_apply(int64_t *a, int64_t n, int6
     const int t = threadIdx.x;
     const int64_t s0 = (int64_t)blockIdx.x * seg, s1 = min(n, s0 + seg);
     int64_t carry = segsum[blockIdx.x];
-    for (int64_t c0 = s0; c0 < s1; c0 += blockDim.x) {
+    for (int64_t c0 = s0; c0 < s1; c0 += nthreads()) {
         const int64_t i = c0 + t;
         const int64_t mine = i < s1 ? a[i] : 0;
         buf[t] = mine;
         __syncthreads();
-        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        for (int off = 1; off < (int)nthreads(); off <<= 1) {
             const int64_t add = t >= off ? buf[t - off] : 0;
             __syncthreads();
             buf[t] += add;
@@ -1671,7 +1683,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(int64_t *a, int64_t n, int6
         }
         if (i < s1)
             a[i] = carry + buf[t] - mine;
-        const int64_t total = buf[blockDim.x - 1];
+        const int64_t total = buf[nthreads() - 1];
         __syncthreads();
         carry += total;
     }
@@ -1686,12 +1698,12 @@ __global__ __launch_bounds__(1024) void k_rebin_scatter(Run r, Work wk, const do
 {
     extern __shared__ int64_t cursor[];
     const int nbins = kVBins * r.ng;
-    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    for (int i = threadIdx.x; i < nbins; i += nthreads())
         cursor[i] = wk.hist[(int64_t)i * r.nblocks + blockIdx.x];
     __syncthreads();
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double x = X[p];
         const int key = sort_key(r, x, V[p]);
         const int64_t d = (int64_t)atomicAdd((unsigned long long *)&cursor[key], 1ull);
@@ -1708,15 +1720,15 @@ __global__ __launch_bounds__(1024) void k_rebin_scatter(Run r, Work wk, const do
 
 __global__ void k_copy_i64(int64_t *dst, const int64_t *src, int64_t n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * nthreads() + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * nthreads())
         dst[i] = src[i];
 }
 
 __global__ void k_copy_f64(double *dst, const double *src, int64_t n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * nthreads() + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * nthreads())
         dst[i] = src[i];
 }
 
@@ -1730,7 +1742,7 @@ __device__ __forceinline__ void init_particles_body(const Run &r, const Work &wk
 {
     double ke = 0.0;
     int nonfinite = 0;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         double v2 = 0.0;
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
@@ -1771,7 +1783,7 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem)
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
     rep_gather(rho, wk.J2[0], ng, r.nrep, 3 * ng);
     __syncthreads();
-    for (int m = threadIdx.x; m < ng; m += blockDim.x) {
+    for (int m = threadIdx.x; m < ng; m += nthreads()) {
         double re = 0.0, im = 0.0;
         if (m != 0 && 2 * m != ng) {
             for (int l = 0; l < ng; ++l) {
@@ -1791,7 +1803,7 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem)
         ei[m] = im;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
         double acc = 0.0;
         for (int m = 1; m < ng; ++m) {
             const long long mi = ((long long)m * i) % ng;
@@ -1815,7 +1827,7 @@ __device__ void cn_init_body(const Run &r, const Work &wk)
 {
     const int ng = r.ng;
     const double s = r.hdt * r.hdt * r.c2;
-    for (int k = threadIdx.x; k < ng; k += blockDim.x) {
+    for (int k = threadIdx.x; k < ng; k += nthreads()) {
         double acc = 0.0;
         for (int m = 0; m < ng; ++m) {
             const double sn = sinpi((double)m / ng);
@@ -1833,10 +1845,10 @@ __global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk) { cn_init_body
 __device__ void init_finish_body(const Run &r, const Work &wk, double *red)
 {
     const int ng = r.ng;
-    for (int i = threadIdx.x; i < 3 * ng; i += blockDim.x)
+    for (int i = threadIdx.x; i < 3 * ng; i += nthreads())
         wk.Ef[0][i] = wk.E[i];
     if (r.scheme == 2)
-        for (int i = threadIdx.x; i < 2 * ng; i += blockDim.x)
+        for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
             wk.Bf[0][i] = wk.B[i];
     double we, wb;
     field_energies(r, wk.E, wk.B, &we, &wb, red);
@@ -1859,8 +1871,8 @@ __global__ __launch_bounds__(1024) void k_init_finish(Run r, Work wk)
 
 __global__ void k_fill(double *p, int64_t n, double v)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * nthreads() + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * nthreads())
         p[i] = v;
 }
 
