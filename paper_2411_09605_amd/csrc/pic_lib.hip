@@ -1141,6 +1141,12 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
         poff += q.n_particles;
         goff += q.n_cells;
     }
+    // largest items first: workgroups start in order as earlier ones finish, so the small
+    // last items of the runs fill in at the end of each pass instead of full ones starting
+    // late (the kernels find everything about an item in the item itself)
+    std::stable_sort(items.begin(), items.end(), [](const BatchItem &a, const BatchItem &b) {
+        return a.p1 - a.p0 > b.p1 - b.p0;
+    });
     c->bt.runs = (const BatchRun *)(ws + L.runs);
     c->bt.items = (const BatchItem *)(ws + L.items);
     c->bt.nitems = (int32_t)items.size();
