@@ -203,6 +203,8 @@ struct Work {
     double *J1[2];         // [nrep][3][ng] predictor current j^{n,*} (J1[n & 1])
     double *J2[2];         // [nrep][3][ng] centred current j^{*,n+1/2} (J2[n & 1])
     double *cninv;         // [ng] first row of the Crank-Nicolson inverse
+    double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
+                           // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
     DevState *st;
     DevRecord *rec;        // [rec_cap] ring
@@ -1029,7 +1031,7 @@ struct Sums2 {
 
 __device__ __forceinline__ Sums2 esec2_fields_load(const Run &r, const double *E, const double *J1,
                                                    const double *J2, double *es, double *e1,
-                                                   double *eb, int nrep)
+                                                   double *eb, int nrep, double *save)
 {
     const int ng = r.ng, rs = 3 * ng;
     double *e0 = es + kGhost, *ebi = eb + kGhost;
@@ -1041,6 +1043,11 @@ __device__ __forceinline__ Sums2 esec2_fields_load(const Run &r, const double *E
         e0[i] = a;
         ebi[i] = en0;
         e1[i] = b;
+        if (save) {
+            save[i] = en0;
+            save[ng + i] = a;
+            save[2 * ng + i] = b;
+        }
         m.a += a;
         m.b += b;
     }
@@ -1348,7 +1355,8 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     const double *Bn = EM ? wk.Bf[par] : nullptr;
     // the first particle batch is issued after the field loads (see esec2_predictor)
     if (!EM && r.scheme == 0) {
-        const Sums2 part = esec2_fields_load(r, En, wk.J1[par], wk.J2[par], es, e1, eb, r.nrep);
+        const Sums2 part = esec2_fields_load(r, En, wk.J1[par], wk.J2[par], es, e1, eb, r.nrep,
+                                             lead ? wk.grid_save : nullptr);
         load_batch(cur, X, V, r.vstride, bcur, p1);
         esec2_fields_finish(r, es, e1, eb, red, part);
     } else {

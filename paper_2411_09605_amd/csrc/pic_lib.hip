@@ -447,6 +447,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
         w.J2[k] = (double *)(ws + L.J2[k]);
     }
     w.cninv = (double *)(ws + L.cninv);
+    w.grid_save = nullptr;
     w.spart = (double *)(ws + L.spart);
     w.st = (DevState *)(ws + L.st);
     w.rec = (DevRecord *)(ws + L.rec);
@@ -1406,11 +1407,15 @@ void adj_pass_a(pic_adj *c, int par, int64_t step, const double *X, const double
                        lds_pass_a(&c->q), c->stream, c->run, c->wk, par, step, X, V);
 }
 
+// save: null, or where the lead workgroup copies the step's grids (k_adj_save_grids' layout)
 template <int ORDER>
-void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *Xo, double *Vo)
+void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *Xo, double *Vo,
+                double *save = nullptr)
 {
+    Work wk = c->wk;
+    wk.grid_save = save;
     hipLaunchKernelGGL((k_pass_b<ORDER, 1, false, true, 0>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_b(&c->q), c->stream, c->run, c->wk, par, X, V, Xo, Vo);
+                       lds_pass_b(&c->q), c->stream, c->run, wk, par, X, V, Xo, Vo);
 }
 
 template <int ORDER>
@@ -1499,10 +1504,14 @@ void adj_backward_launches(pic_adj *c)
             const int par = j & 1;
             double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
             adj_pass_a<ORDER>(c, par, -1, Xj, Vj);          // step -1: no record
-            hipLaunchKernelGGL(k_adj_save_grids, dim3(1), dim3(256), 0, c->stream, w.Ef[par], w.J1[par],
-                               w.J2[par], ng, r.nrep, c->segg + (int64_t)j * 3 * ng);
+            // the step's grids go to the segment store: from pass B's prologue, which sums
+            // the same replicas, or (last step of the segment, no pass B) on their own
+            double *gj = c->segg + (int64_t)j * 3 * ng;
             if (j + 1 < len)
-                adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np);
+                adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np, gj);
+            else
+                hipLaunchKernelGGL(k_adj_save_grids, dim3(1), dim3(256), 0, c->stream, w.Ef[par],
+                                   w.J1[par], w.J2[par], ng, r.nrep, gj);
         }
         // reverse steps of the segment: R1 of its last step, then per step R2 and R3 fused
         // with R1 of the step before (R3 alone for the segment's first step, whose
