@@ -1221,7 +1221,7 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
 // LDS: jt[ncur][tw] | es[ne][tw] | bs[nb][tw]
 // pass_a_body processes particles [p0, p1) of one run; `lead` marks the one workgroup
 // (per run and launch) that also clears the other predictor current and writes the record.
-template <int ORDER, int NV, bool EM, int DEP>
+template <int ORDER, int NV, bool EM, int DEP, int U = kUnrollA<NV>>
 __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int par, int64_t step,
                                             const double *__restrict__ X,
                                             const double *__restrict__ V, int64_t p0,
@@ -1229,7 +1229,6 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
                                             int *wctr)
 {
     using T = TileSizes<NV, EM>;
-    constexpr int U = kUnrollA<NV>;
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
     double *jt = smem;
@@ -1325,14 +1324,13 @@ void k_pass_a(Run r, Work wk, int par, int64_t step,
 //      b1[nb][ng] | EM scratch[8 ng]
 // pass_b_body processes particles [p0, p1) of one run and leaves its scalars in
 // spart[slot]; `lead` marks the workgroup that publishes the new fields of the run.
-template <int ORDER, int NV, bool EM, bool PRED, int DEP>
+template <int ORDER, int NV, bool EM, bool PRED, int DEP, int U = kUnrollB<NV>>
 __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int par, const double *X,
                                             const double *V, double *Xo, double *Vo,
                                             int64_t p0, int64_t p1, bool lead, int slot,
                                             double *smem, double *red, int *wctr)
 {
     using T = TileSizes<NV, EM>;
-    constexpr int U = kUnrollB<NV>;
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
     const WaveBatches<U> wb(p0, wctr);
@@ -1924,6 +1922,10 @@ template <typename T> __device__ __forceinline__ T uniform_copy(const T &g)
 // Workgroups of the batched passes hold at most 512 threads, so the persistent kernels,
 // which keep a run's scalars live across work items, have up to 256 VGPRs (no spills).
 constexpr int kBatchMaxThreads = 512;
+// Particles per thread per batch in the batched passes: the packed state of an ensemble is
+// usually larger than the Infinity Cache and streams from HBM, whose longer latency wants
+// more loads in flight than the plain passes (U = 2).
+template <int NV> constexpr int kBatchUnroll = NV == 1 ? 4 : 2;
 
 struct Batch {
     const BatchRun *runs;
@@ -1946,8 +1948,9 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
         const BatchRun &br = b.runs[item.run];
         const Run r = uniform_copy(br.r);
         const Work wk = uniform_copy(br.wk);
-        pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, b.X + br.poff, b.V + br.poff, item.p0,
-                                        item.p1, item.slot == 0, smem, red, &wctr);
+        pass_a_body<ORDER, NV, EM, DEP, kBatchUnroll<NV>>(r, wk, par, step, b.X + br.poff,
+                                                          b.V + br.poff, item.p0, item.p1,
+                                                          item.slot == 0, smem, red, &wctr);
         lds_barrier();
     }
 }
@@ -1964,9 +1967,9 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
         const BatchRun &br = b.runs[item.run];
         const Run r = uniform_copy(br.r);
         const Work wk = uniform_copy(br.wk);
-        pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, b.X + br.poff, b.V + br.poff,
-                                              b.X + br.poff, b.V + br.poff, item.p0, item.p1,
-                                              item.slot == 0, item.slot, smem, red, &wctr);
+        pass_b_body<ORDER, NV, EM, PRED, DEP, kBatchUnroll<NV>>(
+            r, wk, par, b.X + br.poff, b.V + br.poff, b.X + br.poff, b.V + br.poff, item.p0,
+            item.p1, item.slot == 0, item.slot, smem, red, &wctr);
         lds_barrier();
     }
 }
