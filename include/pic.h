@@ -164,7 +164,9 @@ int pic_validate_params(const pic_params *p);
  * the null stream) and enqueue the initial work: wrap x into [0, L); optionally the
  * Gauss solve for E_x^0; the energy record of step 0; for ESEC2/EMEC(LI) the predictor
  * deposit j^{0,*} and the predictor fields (eq. (good_translation), (EMbasic)).
- * On success *out receives the context. */
+ * On success *out receives the context.  The first init on a device (of any form) also
+ * checks, with two one-workgroup launches and a wait on the stream, that the runtime
+ * passes the workgroup size where the kernels read it; PIC_EUNSUPPORTED if not. */
 int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out);
 
 /* Enqueue n_steps steps (eq. (good_translation) / (naivetranslation)+(PICmodification) /

@@ -59,6 +59,16 @@ __device__ __forceinline__ unsigned nthreads()
     return ((kernarg_ptr)__builtin_amdgcn_implicitarg_ptr())[3] & 0xffffu;
 }
 
+// Written by k_group_size_probe: nthreads() as read in one-workgroup launches of 64 and
+// 256 threads (the library checks them once per device before its first launch).
+__device__ int g_group_size_probe[2];
+
+__global__ void k_group_size_probe(int slot)
+{
+    if (threadIdx.x == 0)
+        g_group_size_probe[slot] = (int)nthreads();
+}
+
 // A thread's batch of U particles, base + u * nthreads() (u < U), loaded together.  The
 // particle loops keep the next batch's loads in flight while they compute on the current
 // one (and the first batch's loads in flight during the field prologue), so HBM latency

@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -197,6 +198,8 @@ Layout layout_of(const pic_params *p)
 
 int fail(std::string *where, int code, const char *fmt, ...)
     __attribute__((format(printf, 3, 4)));
+
+constexpr int kMaxDevices = 64;   // devices whose workgroup-size check is remembered
 
 int fail(std::string *where, int code, const char *fmt, ...)
 {
@@ -469,6 +472,36 @@ int grid_threads(const pic_ctx *c)
     return std::max(t, 256);
 }
 
+// The kernels read their workgroup size from the implicit kernel arguments (nthreads()).
+// Check once per device that the runtime lays them out as assumed, so that a different
+// layout fails here instead of giving the kernels' loops a wrong stride.
+int check_group_size(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(nullptr, PIC_EDEVICE, "hipGetDevice failed");
+    static std::atomic<int> ok[kMaxDevices];
+    const bool known = dev >= 0 && dev < kMaxDevices;
+    if (known && ok[dev].load())
+        return PIC_OK;
+    hipLaunchKernelGGL(k_group_size_probe, dim3(1), dim3(64), 0, s, 0);
+    hipLaunchKernelGGL(k_group_size_probe, dim3(1), dim3(256), 0, s, 1);
+    int got[2] = {0, 0};
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyFromSymbolAsync(got, HIP_SYMBOL(g_group_size_probe), sizeof got, 0,
+                                 hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(nullptr, PIC_EDEVICE, "workgroup-size check: %s",
+                    hipGetErrorString(hipGetLastError()));
+    if (got[0] != 64 || got[1] != 256)
+        return fail(nullptr, PIC_EUNSUPPORTED,
+                    "implicit kernel arguments not laid out as this build assumes (group size "
+                    "read as %d and %d for 64 and 256)", got[0], got[1]);
+    if (known)
+        ok[dev].store(1);
+    return PIC_OK;
+}
+
 int check(pic_ctx *c, const char *what)
 {
     hipError_t e = hipGetLastError();
@@ -593,6 +626,8 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     const Layout L = layout_of(p);
     if (b->workspace_bytes < L.total)
         return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, L.total);
+    if ((rc = check_group_size((hipStream_t)hip_stream)) != PIC_OK)
+        return rc;
 
     pic_ctx *c = new (std::nothrow) pic_ctx();
     if (!c)
@@ -1051,6 +1086,8 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
     const BatchLayout L = batch_layout(p);
     if (b->workspace_bytes < L.total)
         return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, L.total);
+    if (int rcg = check_group_size((hipStream_t)hip_stream); rcg != PIC_OK)
+        return rcg;
 
     pic_batch *c = new (std::nothrow) pic_batch();
     if (!c)
@@ -1564,6 +1601,8 @@ int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_st
     const AdjLayout A = adj_layout(p);
     if (b->workspace_bytes < A.total)
         return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, A.total);
+    if (int rcg = check_group_size((hipStream_t)hip_stream); rcg != PIC_OK)
+        return rcg;
     pic_adj *c = new (std::nothrow) pic_adj();
     if (!c)
         return fail(nullptr, PIC_ENOMEM, "out of host memory");
