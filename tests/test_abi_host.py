@@ -25,6 +25,24 @@ def test_library_exports_every_declared_symbol():
     assert sorted(P.EXPORTS) == names
 
 
+def test_binding_requires_the_library(tmp_path):
+    """Without the built library the package refuses to import (no fallback path)."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2411_09605_amd")
+    dst = tmp_path / "paper_2411_09605_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "*.so.*", "__pycache__"))
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "try:\n    import paper_2411_09605_amd\nexcept ImportError as e:\n"
+            "    print('ImportError:', e); sys.exit(3)\n"
+            "sys.exit(0)\n")
+    r = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 3, (r.returncode, r.stdout, r.stderr)
+    assert "libpic.so is missing" in r.stdout
+
+
 def _good(**kw):
     import paper_2411_09605_amd as P
     base = dict(nv=1, scheme="esec2", shape_order=2, n_particles=1000, n_cells=64,
