@@ -1945,6 +1945,25 @@ struct Batch {
     int64_t *stepc;        // steps completed (device counter)
 };
 
+// The per-step arrays of a run with those of parity par at index 0: the pass bodies then
+// index them with constants (par = 0), which keeps the copied descriptor in registers
+// rather than in scratch memory.
+__device__ __forceinline__ Work by_parity(Work w, int par)
+{
+    if (par) {
+        const double *t[4] = {w.Ef[0], w.Bf[0], w.J1[0], w.J2[0]};
+        w.Ef[0] = w.Ef[1];
+        w.Bf[0] = w.Bf[1];
+        w.J1[0] = w.J1[1];
+        w.J2[0] = w.J2[1];
+        w.Ef[1] = const_cast<double *>(t[0]);
+        w.Bf[1] = const_cast<double *>(t[1]);
+        w.J1[1] = const_cast<double *>(t[2]);
+        w.J2[1] = const_cast<double *>(t[3]);
+    }
+    return w;
+}
+
 template <int ORDER, int NV, bool EM, int DEP>
 __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
 {
@@ -1957,8 +1976,8 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
         const Run r = uniform_copy(br.r);
-        const Work wk = uniform_copy(br.wk);
-        pass_a_body<ORDER, NV, EM, DEP, kBatchUnroll<NV>>(r, wk, par, step, b.X + br.poff,
+        const Work wk = by_parity(uniform_copy(br.wk), par);
+        pass_a_body<ORDER, NV, EM, DEP, kBatchUnroll<NV>>(r, wk, 0, step, b.X + br.poff,
                                                           b.V + br.poff, item.p0, item.p1,
                                                           item.slot == 0, smem, red, &wctr);
         lds_barrier();
@@ -1976,9 +1995,9 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
         const BatchItem item = b.items[it];
         const BatchRun &br = b.runs[item.run];
         const Run r = uniform_copy(br.r);
-        const Work wk = uniform_copy(br.wk);
+        const Work wk = by_parity(uniform_copy(br.wk), par);
         pass_b_body<ORDER, NV, EM, PRED, DEP, kBatchUnroll<NV>>(
-            r, wk, par, b.X + br.poff, b.V + br.poff, b.X + br.poff, b.V + br.poff, item.p0,
+            r, wk, 0, b.X + br.poff, b.V + br.poff, b.X + br.poff, b.V + br.poff, item.p0,
             item.p1, item.slot == 0, item.slot, smem, red, &wctr);
         lds_barrier();
     }
