@@ -1929,6 +1929,17 @@ template <typename T> __device__ __forceinline__ T uniform_copy(const T &g)
     return __builtin_bit_cast(T, w);
 }
 
+// A structure that no thread writes during the kernel and that the whole workgroup reads
+// at one address, read with scalar loads (through the constant address space): the
+// descriptors of the batched passes' work items, so that an item's prologue does not wait
+// on a chain of vector loads.
+template <typename T> __device__ __forceinline__ T uniform_load(const T *g)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    typedef const __attribute__((address_space(4))) Words<sizeof(T) / 4> *const_ptr;
+    return __builtin_bit_cast(T, *(const_ptr)g);
+}
+
 // Workgroups of the batched passes hold at most 512 threads, so the persistent kernels,
 // which keep a run's scalars live across work items, have up to 256 VGPRs (no spills).
 constexpr int kBatchMaxThreads = 512;
@@ -1970,13 +1981,13 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_a(Batch b)
     extern __shared__ double smem[];
     __shared__ double red[kRedSize];
     __shared__ int wctr;
-    const int64_t step = *b.stepc;
+    const int64_t step = uniform_load(b.stepc);
     const int par = (int)(step & 1);
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
-        const BatchItem item = b.items[it];
-        const BatchRun &br = b.runs[item.run];
-        const Run r = uniform_copy(br.r);
-        const Work wk = by_parity(uniform_copy(br.wk), par);
+        const BatchItem item = uniform_load(b.items + it);
+        const BatchRun br = uniform_load(b.runs + item.run);
+        const Run &r = br.r;
+        const Work wk = by_parity(br.wk, par);
         pass_a_body<ORDER, NV, EM, DEP, kBatchUnroll<NV>>(r, wk, 0, step, b.X + br.poff,
                                                           b.V + br.poff, item.p0, item.p1,
                                                           item.slot == 0, smem, red, &wctr);
@@ -1990,12 +2001,12 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batch_pass_b(Batch b)
     extern __shared__ double smem[];
     __shared__ double red[kRedSize];
     __shared__ int wctr;
-    const int par = (int)(*b.stepc & 1);
+    const int par = (int)(uniform_load(b.stepc) & 1);
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
-        const BatchItem item = b.items[it];
-        const BatchRun &br = b.runs[item.run];
-        const Run r = uniform_copy(br.r);
-        const Work wk = by_parity(uniform_copy(br.wk), par);
+        const BatchItem item = uniform_load(b.items + it);
+        const BatchRun br = uniform_load(b.runs + item.run);
+        const Run &r = br.r;
+        const Work wk = by_parity(br.wk, par);
         pass_b_body<ORDER, NV, EM, PRED, DEP, kBatchUnroll<NV>>(
             r, wk, 0, b.X + br.poff, b.V + br.poff, b.X + br.poff, b.V + br.poff, item.p0,
             item.p1, item.slot == 0, item.slot, smem, red, &wctr);
