@@ -15,7 +15,7 @@
 //           x^{n+1/2}, forms v-dagger and Gamma (eq. (opt_solution)) with the fallback,
 //           writes x^{n+1} (wrapped) and v^{n+1}, and - because x*_{n+1} = x^{n+1} +
 //           dt/2 v^{n+1} is then known - deposits the NEXT step's predictor current
-//           w v^{n+1} at x*_{n+1}; workgroup 0 stores E^{n+1} (B^{n+1}) and W_E, W_B
+//           w v^{n+1} at x*_{n+1}; the last workgroup stores E^{n+1} (B^{n+1}) and W_E, W_B
 //
 // The grid work is tiny (N_g nodes) and is repeated by every workgroup in its prologue,
 // which costs a few microseconds of L2 reads and saves the single-workgroup kernels and
@@ -1324,8 +1324,10 @@ void k_pass_a(Run r, Work wk, int par, int64_t step,
     __shared__ double red[kRedSize];
     __shared__ int wctr;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    // the lead (which also writes the record) is the last workgroup, whose chunk is the
+    // smallest when N_p is not a multiple of it, so its extra work does not lengthen the pass
     pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, X, V, p0, min(r.np, p0 + r.chunk),
-                                    blockIdx.x == 0, smem, red, &wctr);
+                                    (int)blockIdx.x == r.nblocks - 1, smem, red, &wctr);
 }
 
 // Pass B of step n (par = n & 1): new fields, second gather, Gamma, state write and
@@ -1526,7 +1528,8 @@ void k_pass_b(Run r, Work wk, int par, const double *X,
     __shared__ int wctr;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, X, V, Xo, Vo, p0, min(r.np, p0 + r.chunk),
-                                          blockIdx.x == 0, blockIdx.x, smem, red, &wctr);
+                                          (int)blockIdx.x == r.nblocks - 1, blockIdx.x, smem,
+                                          red, &wctr);
 }
 
 // End of a pic_step call (one workgroup): the record of the newest state and a copy of
