@@ -69,10 +69,10 @@ __global__ void k_group_size_probe(int slot)
         g_group_size_probe[slot] = (int)nthreads();
 }
 
-// A thread's batch of U particles, base + u * nthreads() (u < U), loaded together.  The
-// particle loops keep the next batch's loads in flight while they compute on the current
-// one (and the first batch's loads in flight during the field prologue), so HBM latency
-// overlaps LDS and ALU work.
+// A thread's batch of U particles (lane l of a wavefront takes b + l + 64 u, u < U; see
+// BatchAddr), loaded together.  The particle loops keep the next batch's loads in flight
+// while they compute on the current one (and the first batch's loads in flight during the
+// field prologue), so HBM latency overlaps LDS and ALU work.
 template <int U, int NV> struct PBatch {
     double x[U], v[U][NV];
 };
