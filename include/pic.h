@@ -68,7 +68,11 @@ enum pic_flag {
     PIC_F_INIT_GAUSS = 1u,   /* set E_x^0 from the particles: dE/dx = rho - 1 solved
                                 spectrally on the nodes (mean and Nyquist modes zero);
                                 otherwise the caller's E (and B) are E^0 (B^0)          */
-    PIC_F_TRACK_IDS = 2u     /* permute the caller's id array with the particles        */
+    PIC_F_TRACK_IDS = 2u,    /* permute the caller's id array with the particles        */
+    PIC_F_INTERLEAVE = 4u    /* deal particle batches to the workgroups round-robin
+                                instead of in contiguous chunks (faster once the state
+                                streams from HBM); chosen by itself when the state is
+                                larger than 192 MB.  Not with rebin_every > 0           */
 };
 
 /* Deposit strategies for the per-workgroup LDS current tiles (section 2.2 deposit).  All

@@ -130,18 +130,31 @@ __device__ __forceinline__ void load_weights(double (&w)[U], const double *__res
         w[u] = W ? (W + a.b0)[a.off(lane, u)] : wu;
 }
 
-// A workgroup's particles [p0, p1) go to its wavefronts in batches of 64 U consecutive
-// particles (lane l takes b + l + 64 u): wavefront w starts with batch w, and each then
-// claims the next unclaimed batch from a counter in LDS.  The hardware issues older
+// A workgroup's particles go to its wavefronts in batches of 64 U consecutive particles
+// (lane l takes b + l + 64 u): wavefront w starts with the workgroup's batch w, and each
+// then claims the next unclaimed batch from a counter in LDS.  The hardware issues older
 // wavefronts first, so a fixed split leaves the youngest ones finishing alone at the end
 // of the pass; claiming batches as they go, the wavefronts of a workgroup finish within
 // about one batch of each other.  The counter is set by reset() before a barrier that
 // precedes the first claim.
+//
+// Batch k of a workgroup starts at origin + k step.  Chunks (the default): the
+// workgroup's particles are [p0, p1), origin = p0 and step = one batch.  Interleaved:
+// batches are dealt to the workgroups round-robin, origin = b batches for workgroup b
+// and step = nblocks batches, so that at any moment the grid reads one region of the
+// state rather than nblocks separate ones; with the state streaming from HBM this reads
+// faster, with it in the Infinity Cache the chunks do (callers pass p1 = N_p).
 template <int U> struct WaveBatches {
     static constexpr int kBatch = 64 * U;
-    int64_t p0;
+    int64_t origin, step;
     int *ctr;
-    __device__ __forceinline__ WaveBatches(int64_t first, int *counter) : p0(first), ctr(counter) {}
+    __device__ __forceinline__ WaveBatches(int64_t p0, int *counter, int interleave = 0,
+                                           int nblocks = 1)
+        : ctr(counter)
+    {
+        origin = interleave ? (int64_t)blockIdx.x * kBatch : p0;
+        step = interleave ? (int64_t)nblocks * kBatch : (int64_t)kBatch;
+    }
     __device__ __forceinline__ void reset() const
     {
         if (threadIdx.x == 0)
@@ -150,7 +163,7 @@ template <int U> struct WaveBatches {
     // first particle of this wavefront's first batch (the same in every lane)
     __device__ __forceinline__ int64_t first() const
     {
-        return p0 + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * kBatch;
+        return origin + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * step;
     }
     // claim the next batch (every lane of the wavefront active)
     __device__ __forceinline__ int64_t claim() const
@@ -158,7 +171,7 @@ template <int U> struct WaveBatches {
         int k = 0;
         if ((threadIdx.x & 63) == 0)
             k = atomicAdd(ctr, 1);
-        return p0 + (int64_t)__builtin_amdgcn_readlane(k, 0) * kBatch;
+        return origin + (int64_t)__builtin_amdgcn_readlane(k, 0) * step;
     }
 };
 
@@ -191,7 +204,7 @@ struct Run {
     int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI)
     int32_t tw;            // LDS tile width: ng + 2 kGhost
     int32_t nrep;          // replicas of the current accumulators (see Work::J1)
-    int32_t pad0;
+    int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -1246,7 +1259,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     double *bs = es + T::ne * tw;
     double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
     double *ct = smem + coef_offset((2 * T::ncur + T::ne + T::nb) * tw);   // ES: coefficients
-    const WaveBatches<U> wb(p0, wctr);
+    const WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -1326,7 +1339,8 @@ void k_pass_a(Run r, Work wk, int par, int64_t step,
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     // the lead (which also writes the record) is the last workgroup, whose chunk is the
     // smallest when N_p is not a multiple of it, so its extra work does not lengthen the pass
-    pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, X, V, p0, min(r.np, p0 + r.chunk),
+    pass_a_body<ORDER, NV, EM, DEP>(r, wk, par, step, X, V, p0,
+                                    r.interleave ? r.np : min(r.np, p0 + r.chunk),
                                     (int)blockIdx.x == r.nblocks - 1, smem, red, &wctr);
 }
 
@@ -1345,7 +1359,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     using T = TileSizes<NV, EM>;
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
-    const WaveBatches<U> wb(p0, wctr);
+    const WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -1527,7 +1541,8 @@ void k_pass_b(Run r, Work wk, int par, const double *X,
     __shared__ double red[kRedSize];
     __shared__ int wctr;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, X, V, Xo, Vo, p0, min(r.np, p0 + r.chunk),
+    pass_b_body<ORDER, NV, EM, PRED, DEP>(r, wk, par, X, V, Xo, Vo, p0,
+                                          r.interleave ? r.np : min(r.np, p0 + r.chunk),
                                           (int)blockIdx.x == r.nblocks - 1, blockIdx.x, smem,
                                           red, &wctr);
 }

@@ -81,6 +81,7 @@ def test_validation_lds_limits():
     (dict(n_cells=100000), -6), (dict(nv=3, scheme="emec_li", n_cells=4096), -6),
     # 160 KB of LDS per workgroup: quadratic ES pass B needs 11 N_g + 80 doubles, EM 29 N_g + 128
     (dict(n_cells=1855), -6), (dict(nv=3, scheme="emec_li", n_cells=702), -6),
+    (dict(interleave=True, rebin_every=5), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P

@@ -117,6 +117,29 @@ def test_launch_shapes_agree():
         assert c == -(-(-(-wl.n_particles // gb)) // 64) * 64
 
 
+def test_interleaved_batches_agree():
+    """Batches dealt to the workgroups round-robin (the default for states beyond the
+    Infinity Cache, forced here on small runs): ES 1D-1V over several launch shapes, ES
+    1D-3V with weights and a ragged count, and EM, against the oracle."""
+    _say("case: interleaved batches")
+    wl = workloads.two_stream(n_particles=120_000, n_cells=128, steps=5)
+    for bt, gb in [(64, 7), (256, 13), (1024, 7), (1024, 0), (512, 300)]:
+        _say(f"  shape {bt} x {gb}")
+        gu.run_pair(wl, 5, block_threads=bt, grid_blocks=gb, interleave=True)
+    n = 30_001
+    w3 = workloads.landau(n_particles=n, n_cells=40, alpha=0.1, order=2)
+    w3.v = np.stack([w3.v[0], workloads.normals(9, 12, n), workloads.normals(9, 14, n)])
+    w3.nv = 3
+    w3.b_ext = (0.3, -0.6, 1.2)
+    w3.w = w3.length / n * (1.0 + 0.5 * workloads.uniforms(9, 20, n))
+    _say("  ES 3V weights ragged")
+    gu.run_pair(w3, 10, interleave=True)
+    _say("  EM")
+    we = workloads.weibel(n_particles=100_000, n_cells=256, order=2, steps=10)
+    we.B0 *= 50.0
+    gu.run_pair(we, 10, interleave=True)
+
+
 def test_fast_particles_cross_several_cells():
     """dt large enough that particles move several cells (and beyond the domain) per
     step: node wrapping far outside [0, L)."""
