@@ -281,7 +281,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the 1D grid would be all-reduced across GPUs; not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -59,7 +59,7 @@ enum pic_status {
     PIC_EDEVICE = -3,        /* a HIP call failed; the context is poisoned             */
     PIC_ESTATE = -4,         /* call on a poisoned or destroyed context                */
     PIC_ENONFINITE = -5,     /* a particle or field value became NaN/Inf (diagnostics) */
-    PIC_EUNSUPPORTED = -6    /* valid but outside what this build handles              */
+    PIC_EUNSUPPORTED = -6    /* valid but outside what this library handles            */
 };
 
 enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2 };

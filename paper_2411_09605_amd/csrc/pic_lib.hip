@@ -502,7 +502,7 @@ int check_group_size(hipStream_t s)
                     hipGetErrorString(hipGetLastError()));
     if (got[0] != 64 || got[1] != 256)
         return fail(nullptr, PIC_EUNSUPPORTED,
-                    "implicit kernel arguments not laid out as this build assumes (group size "
+                    "implicit kernel arguments not laid out as the kernels assume (group size "
                     "read as %d and %d for 64 and 256)", got[0], got[1]);
     if (known)
         ok[dev].store(1);
