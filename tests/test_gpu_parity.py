@@ -245,6 +245,21 @@ def test_two_stream_full_size_parity_and_energy():
     assert rec["nonfinite"].max() == 0
 
 
+def test_two_stream_beyond_cache_interleaved():
+    """Three times the two-stream particle count: 480 MB of state, above the 192 MB at
+    which the passes deal their batches round-robin across the workgroups by themselves
+    (the Weibel workload above, 640 MB, takes that path with three velocity components).
+    2 steps element by element against the oracle, then 20 more with the energy bar."""
+    _say("case: two-stream 3e7 x 512 (interleaved by size)")
+    wl = workloads.two_stream(n_particles=30_000_000)
+    assert wl.n_particles * 16 > 192 * 2**20
+    grec, orec, gpu, _ = gu.run_pair(wl, 2, every=2)
+    gpu.step(20)
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+    assert rec["nonfinite"].max() == 0
+
+
 def test_weibel_full_size_parity():
     """The 2e7-particle 1D-3V electromagnetic workload: 1 step against the oracle, then
     50 more with the energy bar."""
