@@ -306,8 +306,9 @@ typedef struct {
     double  length, dt;
     double  loss_weight;         /* usually dt (time integral of W_E)                     */
     double  k[PIC_ADJ_MAX_MODES];/* mode wavenumbers, each a multiple of 2 pi / L         */
-    int32_t block_threads;       /* as pic_params (0 = default)                           */
-    int32_t grid_blocks;         /* as pic_params (0 = default)                           */
+    int32_t block_threads;       /* as pic_params; both 0: 512 threads x 512 workgroups   */
+    int32_t grid_blocks;         /* (two per CU) from N_p >= 524288, else pic_params' own */
+                                 /* defaults                                              */
     int32_t reserved[2];         /* 0                                                     */
 } pic_adj_params;
 
