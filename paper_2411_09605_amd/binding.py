@@ -608,6 +608,10 @@ class PicAdjoint:
         _check(lib.pic_adj_init(ctypes.byref(p), ctypes.byref(b),
                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
+        # forward runs so far and the parameters of the newest one: pic_adj_backward
+        # differentiates the newest forward run of the context
+        self.forward_count = 0
+        self.theta = None
 
     @classmethod
     def from_workload(cls, wl, checkpoint_every=50, **kw):
@@ -623,6 +627,8 @@ class PicAdjoint:
         rc = lib.pic_adj_forward(self.ctx, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  float(v_beam), float(v_spread))
         _check(rc)
+        self.forward_count += 1
+        self.theta = (a.copy(), float(v_beam), float(v_spread))
         if sync:
             self.stream.synchronize()
             return float(self.loss.cpu()[0])
@@ -662,16 +668,25 @@ def _make_loss_function():
 
         @staticmethod
         def forward(ctx, theta, adj):
-            th = theta.detach().to("cpu", torch.float64).numpy()
+            th = theta.detach().to("cpu", torch.float64).numpy().copy()
             M = adj.n_modes
             J = adj.forward(th[:M], th[M], th[M + 1])
             ctx.adj = adj
+            ctx.theta = th
+            ctx.forward_count = adj.forward_count
             ctx.theta_device = theta.device
             return torch.tensor(J, dtype=torch.float64, device=theta.device)
 
         @staticmethod
         def backward(ctx, gJ):
-            g = ctx.adj.backward(float(gJ.detach().cpu()))
+            adj, th, M = ctx.adj, ctx.theta, ctx.adj.n_modes
+            if adj.forward_count != ctx.forward_count:
+                # another forward ran on the shared context since this one (a second loss,
+                # a probe, a line search): its checkpoints are the other run's, so run
+                # this loss's forward again before the reverse sweep
+                adj.forward(th[:M], th[M], th[M + 1])
+                ctx.forward_count = adj.forward_count
+            g = adj.backward(float(gJ.detach().cpu()))
             return torch.as_tensor(g, dtype=torch.float64, device=ctx.theta_device), None
 
     return TwoStreamLoss

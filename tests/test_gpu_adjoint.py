@@ -102,6 +102,34 @@ def test_autograd_function():
     assert np.abs(theta.grad.numpy() - 3.0 * g).max() <= 1e-11 * np.abs(g).max()
 
 
+def test_autograd_two_losses_on_one_context():
+    """Two losses built on one PicAdjoint before either backward: each backward gives the
+    gradient at its own parameters (the shared context's checkpoints belong to the newer
+    forward, so the older loss runs its forward again)."""
+    import torch
+    from paper_2411_09605_amd import PicAdjoint, two_stream_loss
+    _say("case: adjoint, two losses on one context")
+    wl = _wl(steps=25, n=5000, ng=32)
+    m = wl.meta
+    adj = PicAdjoint.from_workload(wl, checkpoint_every=10)
+    t1 = torch.tensor(list(m["alphas"]) + [m["v_beam"], m["v_spread"]], dtype=torch.float64,
+                      requires_grad=True)
+    t2 = torch.tensor(list(np.asarray(m["alphas"]) * 1.5) + [m["v_beam"] * 1.1, m["v_spread"]],
+                      dtype=torch.float64, requires_grad=True)
+    J1 = two_stream_loss(t1, adj)
+    J2 = two_stream_loss(t2, adj)
+    J1.backward()
+    J2.backward()
+    fresh = PicAdjoint.from_workload(wl, checkpoint_every=10)
+    for t, J in ((t1, J1), (t2, J2)):
+        th = t.detach().numpy()
+        Jr = fresh.forward(th[:-2], th[-2], th[-1])
+        gr = fresh.backward(1.0)
+        assert abs(J.item() - Jr) <= 1e-12 * abs(Jr)
+        assert np.abs(t.grad.numpy() - gr).max() <= 1e-11 * np.abs(gr).max()
+    assert np.abs(t1.grad.numpy() - t2.grad.numpy()).max() > 1e-3 * np.abs(t1.grad.numpy()).max()
+
+
 def test_gradient_matches_gpu_central_differences():
     """Central differences of the GPU loss (h = 1e-6 on each parameter, the draws held
     fixed) against the adjoint gradient."""
