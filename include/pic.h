@@ -216,6 +216,31 @@ int pic_destroy(pic_ctx *ctx);
 
 const char *pic_strerror(int status);
 
+/* ------------------------------------------------ allocation-free single run
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.
+ *
+ * Does what pic_init(p, b, hip_stream) followed by pic_step(n_steps) does, in one call
+ * and without a context, with the workspace taken from a static device array of the
+ * library (PIC_STATIC_SCRATCH_BYTES per device, held by every device the library runs
+ * on until the process ends) instead of the caller's: b->workspace must be NULL and
+ * b->workspace_bytes 0; every other field of b is as for pic_init (caller-owned device
+ * arrays, updated in place).  When diag_out (a DEVICE pointer to one pic_diag) is not
+ * NULL, the record of the newest step is written there.  Asynchronous: everything is
+ * enqueued on hip_stream.  No device or pinned memory is allocated and nothing is freed.
+ * Errors: PIC_ENOMEM when pic_workspace_size(p) exceeds PIC_STATIC_SCRATCH_BYTES (for
+ * example with rebins of many particles or a large record_capacity); otherwise as
+ * pic_init and pic_step, with messages from pic_last_error(NULL).
+ * Every call on one device shares that device's array, which keeps the previous call's
+ * contents (the call clears what must start at zero): calls that overlap on one device
+ * (other streams, other threads) race and give wrong results.  The first call on a
+ * device of any entry point waits once on the stream for the library's check of the
+ * kernels' launch layout, so make one call outside graph capture first. */
+#define PIC_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+
+int pic_run_static(const pic_params *p, const pic_buffers *b, void *hip_stream,
+                   int64_t n_steps, pic_diag *diag_out);
+
 /* ------------------------------------------------------------ batched ensemble form
  * Many independent runs of one scheme advanced together: each run has its own particle
  * count, cell count and length; all share the scheme, shape order, nv, dt, c and b_ext.

@@ -49,7 +49,9 @@ DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("fiel
 # Every function declared in include/pic.h.
 EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
            "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
-           "pic_launch_shape", "pic_destroy", "pic_strerror", "pic_last_error")
+           "pic_launch_shape", "pic_destroy", "pic_strerror", "pic_last_error",
+           "pic_run_static")
+STATIC_SCRATCH_BYTES = 16 << 20
 KERNEL_CLASSES = ("pass_a", "pass_b", "rebin")
 
 
@@ -93,6 +95,8 @@ def _load():
     lib.pic_strerror.restype = ctypes.c_char_p
     lib.pic_last_error.argtypes = [vp]
     lib.pic_last_error.restype = ctypes.c_char_p
+    lib.pic_run_static.argtypes = [P, ctypes.POINTER(PicBuffers), vp, ctypes.c_int64, vp]
+    lib.pic_run_static.restype = ctypes.c_int
     return lib
 
 
@@ -279,6 +283,35 @@ class Pic:
         return cls.from_arrays(wl.nv, scheme or wl.scheme, wl.order, wl.n_cells, wl.length,
                                wl.dt, wl.x, wl.v, E0=wl.E0, B0=wl.B0, w=wl.w, c=wl.c,
                                b_ext=wl.b_ext, init_gauss=wl.init_gauss, device=device, **knobs)
+
+
+def run_static(params: PicParams, x, v, E, B=None, w=None, ids=None, n_steps: int = 0,
+               diag=None, stream=None) -> int:
+    """``pic_run_static``: initialise and advance ``n_steps`` steps in one call, with the
+    library's static workspace (no allocation in the library).  Tensors as for ``Pic``;
+    ``diag`` is None or a CUDA tensor of at least ``DIAG_DTYPE.itemsize`` bytes that
+    receives the newest step's record.  Asynchronous on ``stream``; returns the status
+    (raises ``PicError`` on failure)."""
+    import torch
+    buf = PicBuffers()
+    buf.x, buf.v, buf.E = x.data_ptr(), v.data_ptr(), E.data_ptr()
+    buf.B = B.data_ptr() if B is not None else None
+    buf.w = w.data_ptr() if w is not None else None
+    buf.id = ids.data_ptr() if ids is not None else None
+    buf.workspace, buf.workspace_bytes = None, 0
+    if diag is not None and (not diag.is_cuda or diag.numel() * diag.element_size() < DIAG_DTYPE.itemsize):
+        raise ValueError("diag must be a CUDA tensor of at least one pic_diag")
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    rc = lib.pic_run_static(ctypes.byref(params), ctypes.byref(buf), ctypes.c_void_p(s.cuda_stream),
+                            int(n_steps), ctypes.c_void_p(diag.data_ptr()) if diag is not None else None)
+    _check(rc)
+    return rc
+
+
+def diag_from_tensor(diag) -> np.ndarray:
+    """The pic_diag a ``run_static`` call wrote into ``diag`` (synchronises)."""
+    raw = diag.detach().reshape(-1).view(dtype=__import__("torch").uint8)[:DIAG_DTYPE.itemsize]
+    return np.frombuffer(raw.cpu().numpy().tobytes(), dtype=DIAG_DTYPE)[0]
 
 
 # ---------------------------------------------------------------- batched ensemble

@@ -1566,6 +1566,13 @@ __global__ __launch_bounds__(1024) void k_finish(Run r, Work wk, int par, int64_
     finish_body(r, wk, par, step, red);
 }
 
+// Copy of the newest record into a caller's device pic_diag (one thread).
+__global__ void k_copy_record(Work wk, int rec_cap, DevRecord *dst)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *dst = wk.rec[wk.st->recorded % rec_cap];
+}
+
 // ------------------------------------------------------------------- initialisation
 // Predictor deposit of the initial state, w v^0 at x*_0 = x^0 + dt/2 v^0, into J1[0].
 template <int ORDER, int NV, bool EM>

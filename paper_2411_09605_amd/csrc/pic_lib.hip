@@ -609,46 +609,26 @@ void fill(pic_ctx *c, double *p, int64_t n, double v)
                        c->stream, p, n, v);
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t pic_workspace_size(const pic_params *p)
+// Everything pic_init does once its arguments are validated and the workspace is known to
+// be large enough: bind the context to the buffers and stream and enqueue the initial
+// work.  On failure the context is left for the caller to release.
+int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t stream,
+             const Layout &L)
 {
-    if (validate(p, nullptr) != PIC_OK)
-        return 0;
-    return layout_of(p).total;
-}
-
-int pic_validate_params(const pic_params *p) { return validate(p, nullptr); }
-
-int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out)
-{
-    if (!out)
-        return fail(nullptr, PIC_EINVAL, "out is NULL");
-    int rc = validate(p, nullptr);
-    if (rc != PIC_OK)
-        return rc;
-    if (!b || !b->x || !b->v || !b->E || !b->workspace)
-        return fail(nullptr, PIC_EINVAL, "x, v, E and workspace must be non-NULL");
+    if (!b->x || !b->v || !b->E)
+        return fail(nullptr, PIC_EINVAL, "x, v and E must be non-NULL");
     if (is_em(p) && !b->B)
         return fail(nullptr, PIC_EINVAL, "B must be non-NULL for PIC_EMEC_LI");
     if ((p->flags & PIC_F_TRACK_IDS) && !b->id)
         return fail(nullptr, PIC_EINVAL, "PIC_F_TRACK_IDS needs an id array");
     if ((uintptr_t)b->workspace % kAlign)
         return fail(nullptr, PIC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-    const Layout L = layout_of(p);
-    if (b->workspace_bytes < L.total)
-        return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, L.total);
-    if ((rc = check_group_size((hipStream_t)hip_stream)) != PIC_OK)
+    if (int rc = check_group_size(stream); rc != PIC_OK)
         return rc;
 
-    pic_ctx *c = new (std::nothrow) pic_ctx();
-    if (!c)
-        return fail(nullptr, PIC_ENOMEM, "out of host memory");
     c->p = *p;
     c->b = *b;
-    c->stream = (hipStream_t)hip_stream;
+    c->stream = stream;
     c->threads = threads_of(p);
     c->poisoned = 0;
     c->records_read = 0;
@@ -698,22 +678,15 @@ int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ct
     if (p->scheme != PIC_ESEC1)
         dispatch(c, D_PREDEPOSIT);
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
-    rc = check(c, "pic_init launches");
-    if (rc != PIC_OK) {
+    int rc = check(c, "pic_init launches");
+    if (rc != PIC_OK)
         g_last_error = c->err;
-        delete c;
-        return rc;
-    }
-    *out = c;
-    return PIC_OK;
+    return rc;
 }
 
-int pic_step(pic_ctx *c, int64_t n_steps)
+// Enqueue n_steps >= 0 steps of a live context (pic_step after its argument checks).
+int enqueue_steps(pic_ctx *c, int64_t n_steps)
 {
-    if (!c || c->poisoned)
-        return PIC_ESTATE;
-    if (n_steps < 0)
-        return fail(&c->err, PIC_EINVAL, "n_steps must be >= 0");
     const int K = c->p.rebin_every;
     for (int64_t s = 0; s < n_steps; ++s) {
         const int64_t n = c->steps_done;
@@ -746,6 +719,52 @@ int pic_step(pic_ctx *c, int64_t n_steps)
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(grid_threads(c)), 0, c->stream, c->run, c->wk,
                            (int)(c->steps_done & 1), c->steps_done);
     return check(c, "pic_step launches");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_workspace_size(const pic_params *p)
+{
+    if (validate(p, nullptr) != PIC_OK)
+        return 0;
+    return layout_of(p).total;
+}
+
+int pic_validate_params(const pic_params *p) { return validate(p, nullptr); }
+
+int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out)
+{
+    if (!out)
+        return fail(nullptr, PIC_EINVAL, "out is NULL");
+    int rc = validate(p, nullptr);
+    if (rc != PIC_OK)
+        return rc;
+    if (!b || !b->workspace)
+        return fail(nullptr, PIC_EINVAL, "workspace must be non-NULL");
+    const Layout L = layout_of(p);
+    if (b->workspace_bytes < L.total)
+        return fail(nullptr, PIC_ENOMEM, "workspace has %zu bytes, needs %zu", b->workspace_bytes, L.total);
+    pic_ctx *c = new (std::nothrow) pic_ctx();
+    if (!c)
+        return fail(nullptr, PIC_ENOMEM, "out of host memory");
+    rc = init_ctx(c, p, b, (hipStream_t)hip_stream, L);
+    if (rc != PIC_OK) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx *c, int64_t n_steps)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    if (n_steps < 0)
+        return fail(&c->err, PIC_EINVAL, "n_steps must be >= 0");
+    return enqueue_steps(c, n_steps);
 }
 
 int pic_diagnostics(pic_ctx *c, pic_diag *out, int64_t max_records, int64_t *n_written)
@@ -874,6 +893,86 @@ const char *pic_last_error(const pic_ctx *c)
     if (c)
         return c->err.c_str();
     return g_last_error.c_str();
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// Allocation-free run
+// =====================================================================================
+namespace {
+
+// Workspace of pic_run_static: one copy per device, held until the process ends.  Host
+// code never passes this name to a kernel or a copy (on the host it stands for a
+// host-side shadow, not the device array): it uses the device address that
+// hipGetSymbolAddress returns for it, kept per device below.
+static __device__ __align__(256) unsigned char scratch[PIC_STATIC_SCRATCH_BYTES];
+
+std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(nullptr, PIC_EDEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, PIC_EUNSUPPORTED, "device %d is beyond the %d this library tracks",
+                    dev, kMaxDevices);
+    void *ptr = g_scratch_addr[dev].load();
+    if (!ptr) {
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, PIC_EDEVICE, "hipGetSymbolAddress(scratch): %s",
+                        hipGetErrorString(e));
+        g_scratch_addr[dev].store(ptr);
+    }
+    *out = ptr;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_run_static(const pic_params *p, const pic_buffers *b, void *hip_stream, int64_t n_steps,
+                   pic_diag *diag_out)
+{
+    int rc = validate(p, nullptr);
+    if (rc != PIC_OK)
+        return rc;
+    const Layout L = layout_of(p);
+    if (L.total > (size_t)PIC_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, PIC_ENOMEM,
+                    "this run needs %zu bytes of workspace; the static workspace holds %zu",
+                    L.total, (size_t)PIC_STATIC_SCRATCH_BYTES);
+    if (n_steps < 0)
+        return fail(nullptr, PIC_EINVAL, "n_steps must be >= 0");
+    if (!b)
+        return fail(nullptr, PIC_EINVAL, "buffers are NULL");
+    if (b->workspace || b->workspace_bytes)
+        return fail(nullptr, PIC_EINVAL, "pic_run_static uses its own workspace: pass "
+                                         "workspace = NULL and workspace_bytes = 0");
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws)) != PIC_OK)
+        return rc;
+    pic_buffers bs = *b;
+    bs.workspace = ws;
+    bs.workspace_bytes = PIC_STATIC_SCRATCH_BYTES;
+    pic_ctx c;                      // lives for this call only
+    if ((rc = init_ctx(&c, p, &bs, (hipStream_t)hip_stream, L)) != PIC_OK)
+        return rc;
+    if ((rc = enqueue_steps(&c, n_steps)) != PIC_OK) {
+        g_last_error = c.err;
+        return rc;
+    }
+    if (diag_out)
+        hipLaunchKernelGGL(k_copy_record, dim3(1), dim3(64), 0, c.stream, c.wk, c.run.rec_cap,
+                           (DevRecord *)diag_out);
+    rc = check(&c, "pic_run_static launches");
+    if (rc != PIC_OK)
+        g_last_error = c.err;
+    return rc;
 }
 
 }  // extern "C"

@@ -194,3 +194,22 @@ def test_adjoint_null_handling():
     assert B.lib.pic_adj_forward(None, None, 0.0, 0.0) == -4
     assert B.lib.pic_adj_backward(None, 1.0) == -4
     assert B.lib.pic_adj_destroy(None) == -4
+
+
+def test_run_static_rejects_without_a_device():
+    """The allocation-free entry point checks its size limit and its buffers before it
+    touches a device: an oversized run is PIC_ENOMEM, a caller workspace PIC_EINVAL."""
+    import paper_2411_09605_amd.binding as B
+    lib = B.lib
+    big = _good(n_particles=10_000_000, rebin_every=5)
+    assert B.workspace_size(big) > B.STATIC_SCRATCH_BYTES
+    buf = B.PicBuffers()
+    assert lib.pic_run_static(ctypes.byref(big), ctypes.byref(buf), None, 1, None) == -2
+    assert "static workspace" in B.last_error()
+    small = _good()
+    assert 0 < B.workspace_size(small) <= B.STATIC_SCRATCH_BYTES
+    buf.workspace, buf.workspace_bytes = 4096, 1 << 20
+    assert lib.pic_run_static(ctypes.byref(small), ctypes.byref(buf), None, 1, None) == -1
+    assert "own workspace" in B.last_error()
+    assert lib.pic_run_static(ctypes.byref(small), None, None, 1, None) == -1
+    assert lib.pic_run_static(ctypes.byref(small), ctypes.byref(B.PicBuffers()), None, -1, None) == -1
