@@ -84,13 +84,16 @@ def copy_calibration():
 
 def energy_report(recs):
     """Energy error over the run: the largest |TE - TE0| / TE0, the largest before the
-    first Gamma fallback (the method conserves energy exactly until then), and the last
-    step at which the error is still within 1e-11."""
+    first Gamma fallback (the method conserves energy exactly until then), the last step
+    at which the error is still within 1e-11, and the largest of the paper's measure
+    delta^n = (TE^n - min_k TE^k) / TE^0 over the records (section 5.1)."""
     import numpy as np
     err = recs["rel_energy_err"]
     clean = recs["fallbacks_total"] == 0
     bad = np.nonzero(err > 1e-11)[0]
+    tot = recs["total"]
     return {"max_rel_err": float(err.max()),
+            "max_delta_n": float(((tot - tot.min()) / tot[0]).max()),
             "max_rel_err_before_first_fallback": float(err[clean].max()) if clean.any() else None,
             "first_fallback_step": int(recs["step"][~clean][0]) if (~clean).any() else None,
             "within_1e-11_through_step": int(recs["step"][bad[0] - 1]) if len(bad)
@@ -249,6 +252,21 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def host_info():
+    """The benchmark host's CPU: logical CPUs this process may use and the model name."""
+    info = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else os.cpu_count(), "cpu_count": os.cpu_count(), "cpu_model": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def workload_for(name):
     import workloads
     return workloads.by_name(name)
@@ -257,16 +275,22 @@ def workload_for(name):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream_1d1v_512c_10M")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--deposit-mode", default="auto")
     ap.add_argument("--rebin-every", type=int, default=0)
+    ap.add_argument("--deterministic", action="store_true",
+                    help="PIC_F_DETERMINISTIC (bit-reproducible current sums)")
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=8,
+    ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps of the same workload for the CPU baseline (0: skip)")
+    ap.add_argument("--late-start", type=int, default=1000,
+                    help="also time --late-steps steps from this step on, after the "
+                         "instability has saturated (0: skip)")
+    ap.add_argument("--late-steps", type=int, default=20)
     ap.add_argument("--form", choices=("plain", "batched", "adjoint"), default="plain")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batched form: steps per captured hipGraph")
@@ -299,7 +323,9 @@ def main():
           f"order {wl.order}, dt {wl.dt}", file=sys.stderr, flush=True)
     knobs = dict(block_threads=args.block_threads, grid_blocks=args.grid_blocks,
                  deposit_mode=args.deposit_mode, rebin_every=args.rebin_every,
-                 record_capacity=max(4096, args.steps + args.warmup + args.profile_steps + 8))
+                 deterministic=args.deterministic,
+                 record_capacity=max(4096, args.steps + args.warmup + args.profile_steps
+                                     + args.late_start + args.late_steps + 8))
     gpu = Pic.from_workload(wl, device="cuda:0", **knobs)
     gpu.step(args.warmup)
     warm_recs = gpu.diagnostics()
@@ -319,12 +345,34 @@ def main():
 
     # per-kernel durations from HIP events around each launch (separate segment)
     prof = None
+    prof_recs = []
     if args.profile_steps > 0:
         gpu.profile(True)
         gpu.step(args.profile_steps)
         prof = gpu.profile_read()
         gpu.profile(False)
-        gpu.diagnostics()
+        prof_recs = [gpu.diagnostics()]
+
+    # a window after the instability has saturated (particles no longer move as two
+    # beams; the fallback Gamma := 1 appears), reached by running the steps in between
+    late = None
+    done = args.warmup + args.steps + (args.profile_steps if args.profile_steps > 0 else 0)
+    if args.late_start > done:
+        gpu.step(args.late_start - done)
+        skip_recs = gpu.diagnostics()
+        torch.cuda.synchronize()
+        l0 = torch.cuda.Event(enable_timing=True)
+        l1 = torch.cuda.Event(enable_timing=True)
+        l0.record(stream)
+        gpu.step(args.late_steps)
+        l1.record(stream)
+        torch.cuda.synchronize()
+        lms = l0.elapsed_time(l1)
+        all_recs = np.concatenate([warm_recs, recs] + prof_recs + [skip_recs, gpu.diagnostics()])
+        late = {"start_step": args.late_start, "steps": args.late_steps,
+                "ms_per_step": lms / args.late_steps,
+                "value": wl.n_particles * args.late_steps / (lms * 1e-3),
+                "energy_through_window": energy_report(all_recs)}
 
     n = wl.n_particles
     value = n * args.steps / (ms * 1e-3)
@@ -357,10 +405,25 @@ def main():
         c0 = time.perf_counter()
         ost.run(args.cpu_steps)
         cs = time.perf_counter() - c0
+        # the oracle is plain single-threaded C: it uses one of the host's cores
         cpu = {"value": n * args.cpu_steps / cs, "unit": "particle-steps/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{args.cpu_steps} steps of the full {n}-particle workload, "
-                         f"single-threaded C oracle, {cs:.1f} s"}
+                         f"single-threaded C oracle, {cs:.1f} s",
+               "host": host_info()}
+
+    # the whole step against the same roofline: algorithmic bytes of both passes per step
+    ab_all = alg_bytes(wl.nv)
+    step_bytes = (ab_all["pass_a"] + ab_all["pass_b"]) * n
+    step_gbs = step_bytes / (ms / args.steps * 1e-3) / 1e9
+    state_bytes = n * 8 * (1 + wl.nv)
+    step_roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                 "alg_bytes_per_particle_step": ab_all["pass_a"] + ab_all["pass_b"],
+                 "state_bytes": state_bytes,
+                 # MI355X's Infinity Cache (MALL) holds 256 MB: a smaller state can stay in
+                 # it between the two passes, so part of the traffic never reaches HBM
+                 "state_fits_infinity_cache": state_bytes <= 256e6}
 
     out = {
         "metric": METRIC,
@@ -379,10 +442,12 @@ def main():
                    "shape_order": wl.order, "scheme": wl.scheme, "dt": wl.dt,
                    "nv": wl.nv, "block_threads": gpu.block_threads,
                    "grid_blocks": gpu.grid_blocks, "deposit_mode": args.deposit_mode,
-                   "rebin_every": args.rebin_every},
+                   "rebin_every": args.rebin_every, "deterministic": args.deterministic},
         "energy": energy,
         "roofline": roofline,
+        "step_roofline": step_roof,
         "kernels": kernels,
+        "late_window": late,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -69,10 +69,18 @@ enum pic_flag {
                                 spectrally on the nodes (mean and Nyquist modes zero);
                                 otherwise the caller's E (and B) are E^0 (B^0)          */
     PIC_F_TRACK_IDS = 2u,    /* permute the caller's id array with the particles        */
-    PIC_F_INTERLEAVE = 4u    /* deal particle batches to the workgroups round-robin
+    PIC_F_INTERLEAVE = 4u,   /* deal particle batches to the workgroups round-robin
                                 instead of in contiguous chunks (faster once the state
                                 streams from HBM); chosen by itself when the state is
                                 larger than 192 MB.  Not with rebin_every > 0           */
+    PIC_F_DETERMINISTIC = 8u /* bit-for-bit reproducible runs (and continuations through
+                                pic_save_state / pic_load_state with the same launch
+                                shape): each workgroup's deposit is summed exactly in
+                                fixed point and the workgroups' sums are added in
+                                workgroup order (an extra small launch per deposit);
+                                wavefronts take their particles in a fixed order.  Needs
+                                rebin_every == 0 and the LDS_ATOMIC deposit.  Results
+                                differ from the default mode only by rounding           */
 };
 
 /* Deposit strategies for the per-workgroup LDS current tiles (section 2.2 deposit).  All
@@ -186,6 +194,33 @@ int pic_diagnostics(pic_ctx *ctx, pic_diag *out, int64_t max_records, int64_t *n
 /* Synchronise and make the caller's x, v (and id) arrays hold the current particle
  * state (after a rebin the current state may sit in the workspace). */
 int pic_sync_state(pic_ctx *ctx);
+
+/* ----------------------------------------------------------- checkpoint / resume
+ * The complete state of a run between two steps: positions, velocities, ids (with
+ * PIC_F_TRACK_IDS), the library's permuted weights (rebins with non-uniform weights),
+ * E^n and B^n, the predictor current j^{n,*} that ESEC2 and EMEC(LI) carry from one step
+ * to the next (eq. (good_translation) with (doublestardef)), the step number n, the
+ * initial total energy, the fallback total, the deposit's fixed-point scales and the
+ * record of step n.  The saved state is a self-describing block of HOST memory in the
+ * library's own format (native byte order; not a portable file format). */
+
+/* Bytes pic_save_state writes for this context; 0 for a NULL or poisoned context. */
+size_t pic_state_size(const pic_ctx *ctx);
+
+/* Synchronise the stream and write the state into dst (HOST memory of at least
+ * pic_state_size(ctx) bytes; PIC_EINVAL if smaller or NULL). */
+int pic_save_state(pic_ctx *ctx, void *dst, size_t bytes);
+
+/* Synchronise and replace the context's state by a saved one (HOST memory): the caller's
+ * x, v (id) and E (B) arrays receive the saved values, and the next pic_step continues
+ * from step n exactly as the saving context would have (in PIC_F_DETERMINISTIC with the
+ * same launch shape, bit for bit; otherwise up to the order of the current sums).  The
+ * next pic_diagnostics returns the record of step n first.  The context must have been
+ * initialised with the same nv, scheme, shape order, N_p, N_g, L, dt, c, b_ext and the
+ * same PIC_F_DETERMINISTIC and PIC_F_TRACK_IDS bits (and non-uniform weights with rebins
+ * if the saver had them); otherwise, or for a damaged block, PIC_EINVAL with nothing
+ * modified.  The number of current replicas may differ (their sum is then restored). */
+int pic_load_state(pic_ctx *ctx, const void *src, size_t bytes);
 
 /* Kernel classes timed by the optional event profiler. */
 enum pic_kernel_class {

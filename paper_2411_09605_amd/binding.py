@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
-F_INIT_GAUSS, F_TRACK_IDS, F_INTERLEAVE = 1, 2, 4
+F_INIT_GAUSS, F_TRACK_IDS, F_INTERLEAVE, F_DETERMINISTIC = 1, 2, 4, 8
 DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3, "lds_f64": 4}
 ABI_VERSION = 1
 
@@ -50,7 +50,7 @@ DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("fiel
 EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
            "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
            "pic_launch_shape", "pic_destroy", "pic_strerror", "pic_last_error",
-           "pic_run_static")
+           "pic_run_static", "pic_state_size", "pic_save_state", "pic_load_state")
 STATIC_SCRATCH_BYTES = 16 << 20
 KERNEL_CLASSES = ("pass_a", "pass_b", "rebin")
 
@@ -97,6 +97,12 @@ def _load():
     lib.pic_last_error.restype = ctypes.c_char_p
     lib.pic_run_static.argtypes = [P, ctypes.POINTER(PicBuffers), vp, ctypes.c_int64, vp]
     lib.pic_run_static.restype = ctypes.c_int
+    lib.pic_state_size.argtypes = [vp]
+    lib.pic_state_size.restype = ctypes.c_size_t
+    lib.pic_save_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.pic_save_state.restype = ctypes.c_int
+    lib.pic_load_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.pic_load_state.restype = ctypes.c_int
     return lib
 
 
@@ -107,7 +113,8 @@ def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: in
                 length: float, dt: float, c: float = 1.0, b_ext=(0.0, 0.0, 0.0),
                 init_gauss: bool = False, track_ids: bool = False, rebin_every: int = 0,
                 block_threads: int = 0, grid_blocks: int = 0, deposit_mode="auto",
-                record_capacity: int = 0, interleave: bool = False) -> PicParams:
+                record_capacity: int = 0, interleave: bool = False,
+                deterministic: bool = False) -> PicParams:
     p = PicParams()
     p.abi_version = ABI_VERSION
     p.nv, p.scheme, p.shape_order = nv, SCHEMES.get(scheme, scheme), shape_order
@@ -116,7 +123,7 @@ def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: in
     for i in range(3):
         p.b_ext[i] = b_ext[i]
     p.flags = ((F_INIT_GAUSS if init_gauss else 0) | (F_TRACK_IDS if track_ids else 0)
-               | (F_INTERLEAVE if interleave else 0))
+               | (F_INTERLEAVE if interleave else 0) | (F_DETERMINISTIC if deterministic else 0))
     p.block_threads, p.grid_blocks = block_threads, grid_blocks
     p.deposit_mode = DEPOSIT_MODES.get(deposit_mode, deposit_mode)
     p.record_capacity, p.reserved = record_capacity, 0
@@ -226,6 +233,20 @@ class Pic:
 
     def sync_state(self):
         _check(lib.pic_sync_state(self.ctx), self.ctx)
+
+    def save_state(self) -> np.ndarray:
+        """The run's complete state (pic_save_state) as a uint8 host array."""
+        n = int(lib.pic_state_size(self.ctx))
+        if n == 0:
+            raise PicError(PIC_ESTATE, "no state to save")
+        buf = np.empty(n, dtype=np.uint8)
+        _check(lib.pic_save_state(self.ctx, buf.ctypes.data, n), self.ctx)
+        return buf
+
+    def load_state(self, buf):
+        """Continue from a state saved by ``save_state`` (pic_load_state)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib.pic_load_state(self.ctx, buf.ctypes.data, buf.size), self.ctx)
 
     def state(self) -> dict:
         self.sync_state()

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
     // wavefronts claim batches of 64 particles (the counter is set before the barriers below)
-    const WaveBatches<1> wb(p0, &wctr);
+    WaveBatches<1> wb(p0, &wctr);
     wb.reset();
     double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
     double *e1 = t4 + tw, *lt = e1 + ng;
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
     __syncthreads();
 
     Depo<ORDER, 1, 3> dep;          // adjoint values: FP64 atomics (no fixed-point scale)
-    dep.init(nullptr, r);
+    dep.init(nullptr, r, nullptr);
     for (int64_t b = wb.first(); b < p1; b = wb.claim()) {
         const int64_t p = b + (threadIdx.x & 63);
         if (p >= p1)

@@ -33,7 +33,9 @@
 namespace pic {
 
 constexpr int kMaxGrid = 8192;   // upper bound on particle-pass workgroups
-constexpr int kNS = 4;           // per-workgroup scalars: KE, fallbacks, max|G-1|, nonfinite
+// Per-workgroup scalars: KE, fallbacks, max|G-1|, nonfinite (every pass B), and at
+// initialisation also sum w, max w and max w |v| (slots 4-6, for the fixed-point scales).
+constexpr int kNS = 8;
 constexpr int kGhost = 4;        // ghost nodes on each side of an LDS field or current tile
 constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
 
@@ -144,16 +146,23 @@ __device__ __forceinline__ void load_weights(double (&w)[U], const double *__res
 // and step = nblocks batches, so that at any moment the grid reads one region of the
 // state rather than nblocks separate ones; with the state streaming from HBM this reads
 // faster, with it in the Infinity Cache the chunks do (callers pass p1 = N_p).
+//
+// Static (the deterministic mode): wavefront w takes batches w, w + W, w + 2W, ... of
+// its workgroup's W wavefronts, so every thread always sees the same particles in the
+// same order and its running sums (kinetic energy) are reproducible bit for bit.
 template <int U> struct WaveBatches {
     static constexpr int kBatch = 64 * U;
     int64_t origin, step;
     int *ctr;
+    int fixed;             // 1: static assignment
+    int k;                 // static: index of the wavefront's current batch
     __device__ __forceinline__ WaveBatches(int64_t p0, int *counter, int interleave = 0,
-                                           int nblocks = 1)
-        : ctr(counter)
+                                           int nblocks = 1, int static_order = 0)
+        : ctr(counter), fixed(static_order)
     {
         origin = interleave ? (int64_t)blockIdx.x * kBatch : p0;
         step = interleave ? (int64_t)nblocks * kBatch : (int64_t)kBatch;
+        k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     }
     __device__ __forceinline__ void reset() const
     {
@@ -166,12 +175,16 @@ template <int U> struct WaveBatches {
         return origin + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * step;
     }
     // claim the next batch (every lane of the wavefront active)
-    __device__ __forceinline__ int64_t claim() const
+    __device__ __forceinline__ int64_t claim()
     {
-        int k = 0;
+        if (fixed) {
+            k += (int)(nthreads() >> 6);
+            return origin + (int64_t)k * step;
+        }
+        int kc = 0;
         if ((threadIdx.x & 63) == 0)
-            k = atomicAdd(ctr, 1);
-        return origin + (int64_t)__builtin_amdgcn_readlane(k, 0) * step;
+            kc = atomicAdd(ctr, 1);
+        return origin + (int64_t)__builtin_amdgcn_readlane(kc, 0) * step;
     }
 };
 
@@ -189,7 +202,11 @@ struct DevState {
     int64_t fb_total;
     double we, wb;         // field energies of the newest fields (written by pass B)
     int32_t nonfinite_sticky;
-    int32_t pad;
+    int32_t flag_a;        // set by a pass A whose deposit met a value it cannot hold
+                           // (deterministic mode); taken into the next record
+    // Fixed-point scales 2^S and 2^-S of the LDS deposit tiles (Depo<., ., 0>), chosen at
+    // initialisation from the particles (k_fx_setup): [0] currents, [1] charge density.
+    double fx_scale[2], fx_inv[2];
 };
 
 // Scalars of a run, passed by value to every kernel.
@@ -205,12 +222,13 @@ struct Run {
     int32_t tw;            // LDS tile width: ng + 2 kGhost
     int32_t nrep;          // replicas of the current accumulators (see Work::J1)
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
+    int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
+    int32_t pad0;
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
-    double fx_scale;       // 2^S: fixed-point scale of the LDS current tiles (Depo<., ., 0>)
-    double fx_inv;         // 2^-S
-    double fx_lim;         // contributions with |c| 2^S >= fx_lim go to the FP64 side tile
+    double fx_lim;         // contributions with |c| 2^S >= fx_lim leave the fixed-point tile
+                           // (each tile entry then stays below 2^62: fx_lim <= 2^62 / chunk)
     double bext[3];
     const double *w;       // [N_p] weights or nullptr (uniform)
 };
@@ -229,6 +247,8 @@ struct Work {
     double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
                            // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
+    double *part;          // deterministic mode: [nblocks][3][ng] per-workgroup deposits,
+                           // summed in workgroup order by k_reduce_partials
     DevState *st;
     DevRecord *rec;        // [rec_cap] ring
     // counting-sort rebin (only when enabled)
@@ -420,21 +440,41 @@ template <int ORDER, int NC, int DEP> struct Depo;
 // DEP = 0.  A contribution c is stored as round(c 2^S): one FMA against 1.5 2^52 rounds
 // c 2^S to an integer exactly while |c 2^S| < 2^51, and the integer is added with
 // ds_add_u64, which runs at about twice the rate of FP64 LDS atomics on random addresses.
-// Sums inside a workgroup are then exact and independent of the order of the adds.  S is
-// chosen per run (Run::fx_*) so that no tile entry can overflow: each entry receives at most
-// one contribution per particle of the workgroup.  A contribution at or beyond the bound
-// (or not finite) is added to an FP64 side tile instead, so any input is deposited.
+// Sums inside a workgroup are then exact and independent of the order of the adds.  The
+// scale 2^S is chosen at initialisation (k_fx_setup) so that twice the largest
+// contribution of the initial particles, 2 max_p w_p |v_p| / h, stays below Run::fx_lim
+// (<= 2^62 / chunk): each entry receives at most one contribution per particle of the
+// workgroup, so no entry can overflow.  A contribution at or beyond the bound (a particle
+// more than twice as fast as the fastest initial one, or a non-finite value) leaves the
+// fixed-point path:
+//   default            - it is added to an FP64 side tile with FP64 LDS atomics;
+//   deterministic mode - it is rounded to a coarser fixed point, 2^(S - kFxCoarse), in the
+//                        same side tile (as integers; exact and order-independent too),
+//                        while |c| 2^(S - kFxCoarse) < fx_lim; beyond that (or not finite)
+//                        it is dropped and `over` is set (the step is then reported as
+//                        non-finite).
 constexpr double kFxMagic = 6755399441055744.0;   // 1.5 * 2^52
+constexpr int kFxCoarse = 12;
+
+__device__ __forceinline__ long long fx_round(double v)
+{
+    return __double_as_longlong(v + kFxMagic) - __double_as_longlong(kFxMagic);
+}
 
 template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
     double *side;
     double scale, lim, inv;
-    __device__ __forceinline__ void init(double *side_tile, const Run &r)
+    int det;
+    int over;              // deterministic mode: a contribution was out of range
+    __device__ __forceinline__ void init(double *side_tile, const Run &r, const DevState *st,
+                                         int which = 0)
     {
         side = side_tile;
-        scale = r.fx_scale;
+        scale = st->fx_scale[which];
+        inv = st->fx_inv[which];
         lim = r.fx_lim;
-        inv = r.fx_inv;
+        det = r.det;
+        over = 0;
     }
     __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
                                         const double (&q)[NC], bool = true, bool = true)
@@ -451,21 +491,50 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
                     const long long iv = __double_as_longlong(m) - __double_as_longlong(kFxMagic);
                     atomicAdd(&ti[c * tw + sl.n[k]], (unsigned long long)iv);
                 }
-            } else {
+            } else if (!det) {
 #pragma unroll
                 for (int k = 0; k <= ORDER; ++k)
                     atomicAdd(&side[c * tw + sl.n[k]], q[c] * s.w[k]);
+            } else {
+                const double qc = qs * (1.0 / (double)(1 << kFxCoarse));
+                if (fabs(qc) < lim) {
+                    unsigned long long *si = reinterpret_cast<unsigned long long *>(side);
+#pragma unroll
+                    for (int k = 0; k <= ORDER; ++k)
+                        atomicAdd(&si[c * tw + sl.n[k]], (unsigned long long)fx_round(qc * s.w[k]));
+                } else {
+                    over = 1;
+                }
             }
         }
     }
     __device__ __forceinline__ void finish(double *, int, int) {}
-    // each entry back to a double (integer sum times 2^-S plus the side tile) on its way
-    // into the global current
+    // Tile slot `idx` as a double: the integer sum times 2^-S plus the side tile.
+    __device__ __forceinline__ double value(const double *jt, int idx) const
+    {
+        const double fine = (double)__double_as_longlong(jt[idx]) * inv;
+        if (!det)
+            return fine + side[idx];
+        return fine + (double)__double_as_longlong(side[idx]) * (inv * (double)(1 << kFxCoarse));
+    }
+    // Default: each entry back to a double on its way into the global current (FP64
+    // atomics).  Deterministic mode: J is this workgroup's row of the partial sums; node i
+    // receives its interior slot and its periodic ghost images, added in slot order.
     __device__ __forceinline__ void flush_tile(const double *jt, double *J, int ncomp, int ng,
                                                int tw)
     {
+        if (det) {
+            for (int idx = threadIdx.x; idx < ncomp * ng; idx += nthreads()) {
+                const int c = idx / ng, i = idx % ng;
+                double acc = 0.0;
+                for (int j = (i + kGhost) % ng; j < tw; j += ng)
+                    acc += value(jt, c * tw + j);
+                J[c * ng + i] = acc;
+            }
+            return;
+        }
         for (int idx = threadIdx.x; idx < ncomp * tw; idx += nthreads()) {
-            const double val = (double)__double_as_longlong(jt[idx]) * inv + side[idx];
+            const double val = value(jt, idx);
             if (val != 0.0) {
                 const int c = idx / tw, j = idx % tw;
                 unsafeAtomicAdd(&J[c * ng + wrap_node(j - kGhost, ng)], val);
@@ -475,7 +544,8 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 0> {
 };
 
 template <int ORDER, int NC> struct Depo<ORDER, NC, 3> {
-    __device__ __forceinline__ void init(double *, const Run &) {}
+    int over = 0;
+    __device__ __forceinline__ void init(double *, const Run &, const DevState *, int = 0) {}
     __device__ __forceinline__ void add(double *jt, int tw, int ng, const Stencil<ORDER> &s,
                                         const double (&q)[NC], bool = true, bool = true)
     {
@@ -499,6 +569,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
     static constexpr int W = ORDER + 3;
     int anchor;
     bool live;
+    int over = 0;
     double acc[NC][W];
     __device__ __forceinline__ void clear()
     {
@@ -508,7 +579,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 1> {
             for (int j = 0; j < W; ++j)
                 acc[c][j] = 0.0;
     }
-    __device__ __forceinline__ void init(double *, const Run &)
+    __device__ __forceinline__ void init(double *, const Run &, const DevState *, int = 0)
     {
         live = false;
         anchor = 0;
@@ -593,6 +664,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 2> {
     static constexpr int W = ORDER + 3;
     int anchor;            // the same in every lane of the wavefront
     bool live;
+    int over = 0;
     double acc[NC][W];
     __device__ __forceinline__ void clear()
     {
@@ -602,7 +674,7 @@ template <int ORDER, int NC> struct Depo<ORDER, NC, 2> {
             for (int j = 0; j < W; ++j)
                 acc[c][j] = 0.0;
     }
-    __device__ __forceinline__ void init(double *, const Run &)
+    __device__ __forceinline__ void init(double *, const Run &, const DevState *, int = 0)
     {
         live = false;
         anchor = 0;
@@ -856,6 +928,20 @@ __device__ __forceinline__ void rep_zero_part(double *J, int n, int nrep, int rs
 __device__ __forceinline__ double *rep_slot(double *J, int nrep, int ng)
 {
     return J + (size_t)(blockIdx.x % nrep) * 3 * ng;
+}
+
+// Where a workgroup's deposit tile goes: its replica of the current J, or in the
+// deterministic mode its own row of the partial sums (k_reduce_partials then writes J).
+__device__ __forceinline__ double *dep_target(const Run &r, const Work &wk, double *J)
+{
+    return r.det ? wk.part + (size_t)blockIdx.x * 3 * r.ng : rep_slot(J, r.nrep, r.ng);
+}
+
+// A deterministic-mode deposit met a value it cannot hold: report it with the next record.
+template <typename D> __device__ __forceinline__ void flag_over(const D &dep, const Work &wk)
+{
+    if (dep.over)
+        atomicOr(&wk.st->flag_a, 1);
 }
 
 __device__ __forceinline__ void tile_load(double *dst, const double *src, int n)
@@ -1128,6 +1214,10 @@ __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64
     nf = block_max(nf, red);
     if (threadIdx.x == 0) {
         DevState *st = wk.st;
+        if (st->flag_a) {
+            nf = 1.0;
+            st->flag_a = 0;
+        }
         if (step == 0) {
             st->fb_total = 0;
             st->nonfinite_sticky = 0;
@@ -1259,7 +1349,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     double *bs = es + T::ne * tw;
     double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
     double *ct = smem + coef_offset((2 * T::ncur + T::ne + T::nb) * tw);   // ES: coefficients
-    const WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks);
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -1295,7 +1385,7 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     const double *eg = EM ? es : ct;     // what half_step gathers E from
 
     Depo<ORDER, T::ncur, DEP> dep;
-    dep.init(side, r);
+    dep.init(side, r, wk.st);
     // whole wavefronts run the loop (DEP = 2 needs them in its deposit); particles past the
     // end are masked with `valid`
     while (bcur < p1) {
@@ -1323,8 +1413,9 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
         bcur = bnxt;
     }
     dep.finish(jt, tw, ng);
+    flag_over(dep, wk);
     lds_barrier();
-    dep.flush_tile(jt, rep_slot(wk.J2[par], r.nrep, ng), T::ncur, ng, tw);
+    dep.flush_tile(jt, dep_target(r, wk, wk.J2[par]), T::ncur, ng, tw);
 }
 
 template <int ORDER, int NV, bool EM, int DEP>
@@ -1359,7 +1450,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     using T = TileSizes<NV, EM>;
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
-    const WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks);
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -1404,7 +1495,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     }
     const double *eg = EM ? es : cts;    // what half_step gathers E* from
     if (lead) {
-        // publish E^{n+1} (B^{n+1}) and their energies; clear the other centred current
+        // publish E^{n+1} (B^{n+1}) and their energies (pass A clears the next currents)
         for (int i = threadIdx.x; i < T::ne * ng; i += nthreads())
             wk.Ef[par ^ 1][i] = e1[i];
         if constexpr (EM)
@@ -1420,7 +1511,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     lds_barrier();
 
     Depo<ORDER, T::ncur, DEP> dep;
-    dep.init(side, r);
+    dep.init(side, r, wk.st);
     double ke = 0.0, gdev = 0.0;
     int fb = 0, nonfinite = 0;
     while (bcur < p1) {
@@ -1515,8 +1606,10 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
         cur = nxt;
         bcur = bnxt;
     }
-    if constexpr (PRED)
+    if constexpr (PRED) {
         dep.finish(jt, tw, ng);
+        nonfinite |= dep.over;
+    }
     // kinetic energy and fallbacks (sums), max |Gamma - 1| and the non-finite flag (maxima)
     double sc[4] = {ke, (double)fb, gdev, (double)nonfinite};
     block_reduce<0xcu>(sc, red);
@@ -1528,7 +1621,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     }
     if constexpr (PRED) {
         lds_barrier();
-        dep.flush_tile(jt, rep_slot(wk.J1[par ^ 1], r.nrep, ng), T::ncur, ng, tw);
+        dep.flush_tile(jt, dep_target(r, wk, wk.J1[par ^ 1]), T::ncur, ng, tw);
     }
 }
 
@@ -1587,7 +1680,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
     tile_zero(jt, 2 * T::ncur * r.tw);
     __syncthreads();
     Depo<ORDER, T::ncur, 0> dep;
-    dep.init(side, r);
+    dep.init(side, r, wk.st);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double q = (r.w ? r.w[p] : r.wu) * r.qs;
         double qv[T::ncur];
@@ -1596,8 +1689,9 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
             qv[c] = q * V[c * r.vstride + p];
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
     }
+    flag_over(dep, wk);
     __syncthreads();
-    dep.flush_tile(jt, rep_slot(wk.J1[0], r.nrep, r.ng), T::ncur, r.ng, r.tw);
+    dep.flush_tile(jt, dep_target(r, wk, wk.J1[0]), T::ncur, r.ng, r.tw);
 }
 
 template <int ORDER, int NV, bool EM>
@@ -1620,13 +1714,14 @@ __device__ __forceinline__ void deposit_rho_body(const Run &r, const Work &wk,
     tile_zero(jt, 2 * r.tw);
     __syncthreads();
     Depo<ORDER, 1, 0> dep;
-    dep.init(side, r);
+    dep.init(side, r, wk.st, 1);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
         const double q[1] = {(r.w ? r.w[p] : r.wu) * r.qs};
         dep.add(jt, r.tw, r.ng, stencil<ORDER>(X[p] * r.inv_h), q);
     }
+    flag_over(dep, wk);
     __syncthreads();
-    dep.flush_tile(jt, rep_slot(wk.J2[0], r.nrep, r.ng), 1, r.ng, r.tw);
+    dep.flush_tile(jt, dep_target(r, wk, wk.J2[0]), 1, r.ng, r.tw);
 }
 
 template <int ORDER>
@@ -1781,28 +1876,37 @@ __device__ __forceinline__ void init_particles_body(const Run &r, const Work &wk
                                                     const double *__restrict__ V, int64_t p0,
                                                     int64_t p1, int slot, double *red)
 {
-    double ke = 0.0;
+    double ke = 0.0, ws = 0.0, wmax = 0.0, wvmax = 0.0;
     int nonfinite = 0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
-        double v2 = 0.0;
+        double v2 = 0.0, vm = 0.0;
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
             const double vc = V[c * r.vstride + p];
             v2 += vc * vc;
+            vm = fmax(vm, fabs(vc));
         }
         const double x = X[p];
         if (!isfinite(x) || !isfinite(v2))
             nonfinite = 1;
         X[p] = wrap_pos(x, r.L);
-        ke += (r.w ? r.w[p] : r.wu) * v2;
+        const double wp = r.w ? r.w[p] : r.wu;
+        ke += wp * v2;
+        ws += wp;
+        wmax = fmax(wmax, fabs(wp));
+        wvmax = fmax(wvmax, fabs(wp) * vm);
     }
-    const double bke = block_sum(ke, red);
-    const double bnf = block_max((double)nonfinite, red);
+    double sums[2] = {ke, ws}, maxes[3] = {(double)nonfinite, wmax, wvmax};
+    block_reduce<0u>(sums, red);
+    block_reduce<7u>(maxes, red);
     if (threadIdx.x == 0) {
-        wk.spart[slot * kNS + 0] = 0.5 * bke;
+        wk.spart[slot * kNS + 0] = 0.5 * sums[0];
         wk.spart[slot * kNS + 1] = 0.0;
         wk.spart[slot * kNS + 2] = 0.0;
-        wk.spart[slot * kNS + 3] = bnf;
+        wk.spart[slot * kNS + 3] = maxes[0];
+        wk.spart[slot * kNS + 4] = sums[1];
+        wk.spart[slot * kNS + 5] = maxes[1];
+        wk.spart[slot * kNS + 6] = maxes[2];
     }
 }
 
@@ -1813,6 +1917,81 @@ __global__ __launch_bounds__(1024) void k_init_particles(Run r, Work wk, double 
     __shared__ double red[kRedSize];
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     init_particles_body<NV>(r, wk, X, V, p0, min(r.np, p0 + r.chunk), blockIdx.x, red);
+}
+
+// Fixed-point scales of the deposit tiles (one workgroup per run), from the initial
+// particles' slots 4-6: the charge density's from the largest weight (a charge
+// contribution is at most w / h), the currents' from twice the largest w |v| (or w, if
+// that is larger: speeds are in thermal units).  2^S is the largest power of two with
+// q 2^S <= Run::fx_lim for that reference contribution q.
+__device__ void fx_setup_body(const Run &r, const Work &wk, double *red)
+{
+    double wmax = 0.0, wvmax = 0.0;
+    for (int b = threadIdx.x; b < r.nblocks; b += nthreads()) {
+        wmax = fmax(wmax, wk.spart[b * kNS + 5]);
+        wvmax = fmax(wvmax, wk.spart[b * kNS + 6]);
+    }
+    double m[2] = {wmax, wvmax};
+    block_reduce<3u>(m, red);
+    if (threadIdx.x == 0) {
+        const double qref[2] = {2.0 * fmax(m[1], m[0]) * r.inv_h, m[0] * r.inv_h};
+        for (int k = 0; k < 2; ++k) {
+            int S = 0;
+            if (qref[k] > 0.0 && isfinite(qref[k]))
+                S = (int)floor(log2(r.fx_lim / qref[k]));
+            S = max(-1000, min(1000, S));
+            wk.st->fx_scale[k] = ldexp(1.0, S);
+            wk.st->fx_inv[k] = ldexp(1.0, -S);
+        }
+        wk.st->flag_a = 0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_fx_setup(Run r, Work wk)
+{
+    __shared__ double red[kRedSize];
+    fx_setup_body(r, wk, red);
+}
+
+// Deterministic mode: J[c][i] = the sum over the workgroups b of part[b][c][i] (replica 0
+// of a current; the deterministic mode keeps one replica), always in the same order: a
+// workgroup of 256 threads takes 32 consecutive entries; for each entry, 8 threads sum
+// consecutive eighths of the rows in row order, and the 8 sums are then added in order.
+constexpr int kRedEntries = 32, kRedSegments = 8;
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ part,
+                                                         double *__restrict__ J, int nblocks,
+                                                         int n, int rowlen)
+{
+    __shared__ double seg[kRedSegments][kRedEntries];
+    const int t = threadIdx.x, e = t % kRedEntries, sg = t / kRedEntries;
+    const int idx = blockIdx.x * kRedEntries + e;
+    const int per = (nblocks + kRedSegments - 1) / kRedSegments;
+    const int b0 = min(nblocks, sg * per), b1 = min(nblocks, b0 + per);
+    double acc = 0.0;
+    if (idx < n) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                v[k] = part[(size_t)(b + k) * rowlen + idx];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                acc += v[k];
+        }
+        for (; b < b1; ++b)
+            acc += part[(size_t)b * rowlen + idx];
+    }
+    seg[sg][e] = acc;
+    __syncthreads();
+    if (sg == 0 && idx < n) {
+        double s = seg[0][e];
+#pragma unroll
+        for (int k = 1; k < kRedSegments; ++k)
+            s += seg[k][e];
+        J[idx] = s;
+    }
 }
 
 // Initial Gauss solve: dE/dx = rho - 1 with rho in J2[0], into the caller's E_x.
@@ -2101,6 +2280,15 @@ __global__ __launch_bounds__(1024) void k_batch_predeposit(Batch b)
 }
 
 // One workgroup per run.
+__global__ __launch_bounds__(1024) void k_batch_fx_setup(Batch b)
+{
+    __shared__ double red[kRedSize];
+    const BatchRun &br = b.runs[blockIdx.x];
+    const Run r = uniform_copy(br.r);
+    const Work wk = uniform_copy(br.wk);
+    fx_setup_body(r, wk, red);
+}
+
 __global__ __launch_bounds__(1024) void k_batch_gauss(Batch b)
 {
     extern __shared__ double smem[];

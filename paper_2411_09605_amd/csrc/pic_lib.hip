@@ -45,13 +45,17 @@ constexpr int kDefaultRecords = 4096;
 constexpr int kAdjThreads = 512;
 constexpr int kAdjGroupsPerCU = 2;
 constexpr size_t kAlign = 256;
-// LDS a workgroup may use on gfx950 (160 KB per CU, all of it available to one workgroup)
-constexpr size_t kMaxLds = 160 * 1024;
+// LDS a workgroup may use on gfx950 (160 KB per CU, all of it available to one workgroup),
+// less what the kernels declare statically (reduction scratch, counters: under 1 KB); this
+// bounds the dynamic LDS of a launch.
+constexpr size_t kMaxLds = 160 * 1024 - 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+bool is_det(const pic_params *p) { return (p->flags & PIC_F_DETERMINISTIC) != 0; }
+
 struct Layout {
-    size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, st, rec;
+    size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, part, st, rec;
     size_t x2, v2, id2, wcur, w2, hist, segsum;     // rebin (0 when unused)
     size_t total;
 };
@@ -129,24 +133,22 @@ size_t lds_need(const pic_params *p)
     return m;
 }
 
-// Fixed-point scale of the LDS current tiles (Depo<., ., 0>): every tile entry receives at
-// most one contribution per particle of a workgroup (chunk of them), so contributions
-// below lim = min(2^50, 2^62 / chunk) cannot overflow 64 bits; 2^S puts the contribution
-// (w/h)|v| of a particle with uniform weight and |v| = 16 at lim / 16.
-void fixed_point_of(int64_t n_particles, int n_cells, int64_t chunk, Run &r)
+// Bound on the fixed-point contributions of the LDS deposit tiles (Depo<., ., 0>): every
+// tile entry receives at most one contribution per particle of a workgroup (chunk of
+// them), so contributions below lim = min(2^50, 2^62 / chunk) cannot overflow 64 bits.
+// The scale itself is set on the device from the particles (k_fx_setup).
+void fixed_point_of(int64_t chunk, Run &r)
 {
-    const double lim = std::min(std::ldexp(1.0, 50),
-                                std::ldexp(1.0, 62) / (double)std::max<int64_t>(chunk, 1));
-    const double qref = (double)n_cells / (double)n_particles * 16.0;
-    const int S = (int)std::floor(std::log2(lim / qref)) - 4;
-    r.fx_scale = std::ldexp(1.0, S);
-    r.fx_inv = std::ldexp(1.0, -S);
-    r.fx_lim = lim;
+    r.fx_lim = std::min(std::ldexp(1.0, 50),
+                        std::ldexp(1.0, 62) / (double)std::max<int64_t>(chunk, 1));
 }
 
-// Replicas of the current accumulators: about 32 workgroups' atomics per address.
+// Replicas of the current accumulators: about 32 workgroups' atomics per address (one in
+// the deterministic mode, where an ordered reduction writes the current).
 int nrep_of(const pic_params *p)
 {
+    if (is_det(p))
+        return 1;
     const int nb = blocks_of(p, nullptr);
     return std::min(kMaxRep, std::max(1, (nb + 31) / 32));
 }
@@ -187,6 +189,7 @@ Layout layout_of(const pic_params *p)
     }
     L.cninv = take(ng * 8);
     L.spart = take((size_t)blocks_of(p, nullptr) * kNS * 8);
+    L.part = is_det(p) ? take((size_t)blocks_of(p, nullptr) * 3 * ng * 8) : 0;
     L.st = take(sizeof(DevState));
     L.rec = take((size_t)records_of(p) * sizeof(DevRecord));
     L.x2 = L.v2 = L.id2 = L.wcur = L.w2 = L.hist = L.segsum = 0;
@@ -257,8 +260,14 @@ int validate(const pic_params *p, std::string *err)
             return fail(err, PIC_EINVAL, "b_ext must be finite");
     if (p->rebin_every < 0)
         return fail(err, PIC_EINVAL, "rebin_every must be >= 0");
-    if (p->flags & ~(uint32_t)(PIC_F_INIT_GAUSS | PIC_F_TRACK_IDS | PIC_F_INTERLEAVE))
+    if (p->flags & ~(uint32_t)(PIC_F_INIT_GAUSS | PIC_F_TRACK_IDS | PIC_F_INTERLEAVE |
+                               PIC_F_DETERMINISTIC))
         return fail(err, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if ((p->flags & PIC_F_DETERMINISTIC) && p->rebin_every > 0)
+        return fail(err, PIC_EINVAL, "PIC_F_DETERMINISTIC needs rebin_every == 0");
+    if ((p->flags & PIC_F_DETERMINISTIC) && p->deposit_mode != PIC_DEPOSIT_AUTO &&
+        p->deposit_mode != PIC_DEPOSIT_LDS_ATOMIC)
+        return fail(err, PIC_EINVAL, "PIC_F_DETERMINISTIC needs the LDS_ATOMIC deposit");
     if ((p->flags & PIC_F_INTERLEAVE) && p->rebin_every > 0)
         return fail(err, PIC_EINVAL, "PIC_F_INTERLEAVE needs rebin_every == 0");
     if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > 1024))
@@ -341,6 +350,15 @@ void launch_pre(pic_ctx *c)
 
 enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO };
 
+// Deterministic mode: the ordered sum of the workgroups' partial deposits into replica 0
+// of J (ncomp components).
+void reduce_partials(pic_ctx *c, double *J, int ncomp)
+{
+    const int n = ncomp * c->p.n_cells;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + kRedEntries - 1) / kRedEntries)),
+                       dim3(256), 0, c->stream, c->wk.part, J, c->run.nblocks, n, 3 * c->p.n_cells);
+}
+
 template <int ORDER, int DEP>
 void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
@@ -397,6 +415,18 @@ void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0, const double 
         dispatch_order<1>(c, what, par, step, X, V);
     else
         dispatch_order<2>(c, what, par, step, X, V);
+    if (!c->run.det)
+        return;
+    const int ncur = is_em(&c->p) ? 3 : 1;
+    switch (what) {
+    case D_PASS_A: reduce_partials(c, c->wk.J2[par], ncur); break;
+    case D_PASS_B:
+        if (c->p.scheme != PIC_ESEC1)
+            reduce_partials(c, c->wk.J1[par ^ 1], ncur);
+        break;
+    case D_PREDEPOSIT: reduce_partials(c, c->wk.J1[0], ncur); break;
+    case D_RHO: reduce_partials(c, c->wk.J2[0], 1); break;
+    }
 }
 
 // Counting-sort rebin of the caller's state into the second buffers (x2, v2, id2, w2);
@@ -441,6 +471,8 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.tw = (int32_t)tile_width(p);
     r.nrep = nrep_of(p);
     r.interleave = 0;
+    r.det = is_det(p) ? 1 : 0;
+    r.pad0 = 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -453,7 +485,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     for (int i = 0; i < 3; ++i)
         r.bext[i] = p->nv == 3 ? p->b_ext[i] : 0.0;
     r.w = b->w;
-    fixed_point_of(p->n_particles, p->n_cells, r.chunk, r);
+    fixed_point_of(r.chunk, r);
 
     w.E = b->E;
     w.B = b->B;
@@ -466,6 +498,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     w.cninv = (double *)(ws + L.cninv);
     w.grid_save = nullptr;
     w.spart = (double *)(ws + L.spart);
+    w.part = L.part ? (double *)(ws + L.part) : nullptr;
     w.st = (DevState *)(ws + L.st);
     w.rec = (DevRecord *)(ws + L.rec);
     const bool rb = p->rebin_every > 0;
@@ -648,7 +681,7 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         // a workgroup then takes up to one batch more than its chunk
         constexpr int64_t umax = std::max({kUnrollA<1>, kUnrollA<3>, kUnrollB<1>, kUnrollB<3>});
         r.interleave = 1;
-        fixed_point_of(p->n_particles, p->n_cells, r.chunk + 64 * umax, r);
+        fixed_point_of(r.chunk + 64 * umax, r);
     }
     if (w.wcur) {
         // the library permutes its own copy of the weights
@@ -669,6 +702,7 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
     else
         hipLaunchKernelGGL((k_init_particles<3>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w,
                            b->x, b->v);
+    hipLaunchKernelGGL(k_fx_setup, dim3(1), dim3(256), 0, c->stream, r, w);
     if (p->flags & PIC_F_INIT_GAUSS) {
         dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
@@ -809,6 +843,196 @@ int pic_sync_state(pic_ctx *c)
         return PIC_ESTATE;
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return check(c, "pic_sync_state");
+    return PIC_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- checkpoint / resume
+namespace {
+
+// Layout of a saved state (host memory): this header, then the payload arrays in the
+// order x[N_p], v[nv][N_p], id[N_p] (ids tracked), w[N_p] (the library's permuted copy of
+// non-uniform weights, rebins only), E[3][N_g], B[2][N_g] (EM), j^{n,*} replicas
+// [nrep][3][N_g].
+constexpr char kStateMagic[8] = {'P', 'I', 'C', 'S', 'T', 'A', 'T', '1'};
+
+struct StateHeader {
+    char magic[8];
+    int32_t abi_version, nv, scheme, shape_order;
+    int64_t n_particles;
+    int32_t n_cells, nrep, det, has_ids;
+    int32_t has_w, pad;
+    double length, dt, c, b_ext[3];
+    int64_t step;          // the state is (x^n, v^n, E^n, B^n) and j^{n,*} of this step n
+    DevState st;           // energies, counters and fixed-point scales
+    DevRecord last;        // record of step n
+    uint64_t payload_bytes;
+};
+
+struct StateParts {
+    size_t x, v, id, w, E, B, J1, total;
+};
+
+StateParts state_parts(const pic_ctx *c)
+{
+    StateParts o;
+    const size_t np = (size_t)c->p.n_particles, ng = (size_t)c->p.n_cells;
+    size_t at = sizeof(StateHeader);
+    auto take = [&](size_t n) { size_t a = at; at += n * 8; return a; };
+    o.x = take(np);
+    o.v = take(np * c->p.nv);
+    o.id = (c->p.flags & PIC_F_TRACK_IDS) ? take(np) : 0;
+    o.w = c->wk.wcur ? take(np) : 0;
+    o.E = take(3 * ng);
+    o.B = is_em(&c->p) ? take(2 * ng) : 0;
+    o.J1 = take((size_t)c->run.nrep * 3 * ng);
+    o.total = at;
+    return o;
+}
+
+int copy_in(pic_ctx *c, void *dst, const void *src, size_t bytes, const char *what)
+{
+    if (bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream) != hipSuccess)
+        return check(c, what);
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_state_size(const pic_ctx *c)
+{
+    if (!c || c->poisoned)
+        return 0;
+    return state_parts(c).total;
+}
+
+int pic_save_state(pic_ctx *c, void *dst, size_t bytes)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    const StateParts sp = state_parts(c);
+    if (!dst || bytes < sp.total)
+        return fail(&c->err, PIC_EINVAL, "dst must hold pic_state_size() = %zu bytes", sp.total);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return check(c, "pic_save_state sync");
+    char *out = (char *)dst;
+    StateHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.abi_version = PIC_ABI_VERSION;
+    h.nv = c->p.nv;
+    h.scheme = c->p.scheme;
+    h.shape_order = c->p.shape_order;
+    h.n_particles = c->p.n_particles;
+    h.n_cells = c->p.n_cells;
+    h.nrep = c->run.nrep;
+    h.det = c->run.det;
+    h.has_ids = (c->p.flags & PIC_F_TRACK_IDS) ? 1 : 0;
+    h.has_w = c->wk.wcur ? 1 : 0;
+    h.length = c->p.length;
+    h.dt = c->p.dt;
+    h.c = c->p.c;
+    for (int i = 0; i < 3; ++i)
+        h.b_ext[i] = c->p.b_ext[i];
+    h.step = c->steps_done;
+    h.payload_bytes = sp.total - sizeof h;
+    const int par = (int)(c->steps_done & 1);
+    const size_t np = (size_t)c->p.n_particles, ng = (size_t)c->p.n_cells;
+    int rc = copy_in(c, &h.st, c->wk.st, sizeof h.st, "pic_save_state copy");
+    if (rc == PIC_OK)
+        rc = copy_in(c, &h.last, c->wk.rec + c->steps_done % c->run.rec_cap, sizeof h.last,
+                     "pic_save_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, out + sp.x, c->b.x, np * 8, "pic_save_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, out + sp.v, c->b.v, np * 8 * c->p.nv, "pic_save_state copy");
+    if (rc == PIC_OK && sp.id) rc = copy_in(c, out + sp.id, c->b.id, np * 8, "pic_save_state copy");
+    if (rc == PIC_OK && sp.w) rc = copy_in(c, out + sp.w, c->wk.wcur, np * 8, "pic_save_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, out + sp.E, c->wk.Ef[par], 3 * ng * 8, "pic_save_state copy");
+    if (rc == PIC_OK && sp.B) rc = copy_in(c, out + sp.B, c->wk.Bf[par], 2 * ng * 8, "pic_save_state copy");
+    if (rc == PIC_OK)
+        rc = copy_in(c, out + sp.J1, c->wk.J1[par], (size_t)c->run.nrep * 3 * ng * 8,
+                     "pic_save_state copy");
+    if (rc == PIC_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = check(c, "pic_save_state sync");
+    if (rc != PIC_OK)
+        return rc;
+    std::memcpy(out, &h, sizeof h);
+    return PIC_OK;
+}
+
+int pic_load_state(pic_ctx *c, const void *src, size_t bytes)
+{
+    if (!c || c->poisoned)
+        return PIC_ESTATE;
+    const StateParts sp = state_parts(c);
+    if (!src || bytes < sizeof(StateHeader))
+        return fail(&c->err, PIC_EINVAL, "src is NULL or shorter than a state header");
+    StateHeader h;
+    std::memcpy(&h, src, sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.abi_version != PIC_ABI_VERSION)
+        return fail(&c->err, PIC_EINVAL, "src is not a saved state of this library version");
+    bool same = h.nv == c->p.nv && h.scheme == c->p.scheme && h.shape_order == c->p.shape_order &&
+                h.n_particles == c->p.n_particles && h.n_cells == c->p.n_cells &&
+                h.det == c->run.det && h.has_ids == ((c->p.flags & PIC_F_TRACK_IDS) ? 1 : 0) &&
+                h.has_w == (c->wk.wcur ? 1 : 0) && h.length == c->p.length && h.dt == c->p.dt &&
+                h.c == c->p.c && h.step >= 0;
+    for (int i = 0; i < 3; ++i)
+        same = same && h.b_ext[i] == c->p.b_ext[i];
+    if (!same)
+        return fail(&c->err, PIC_EINVAL, "the saved state belongs to a run with other parameters");
+    // the payload as this context would write it, except for the number of replicas
+    const size_t ng = (size_t)c->p.n_cells, np = (size_t)c->p.n_particles;
+    const size_t need = sp.total - (size_t)c->run.nrep * 3 * ng * 8 + (size_t)h.nrep * 3 * ng * 8;
+    if (h.nrep < 1 || h.payload_bytes + sizeof h != need || bytes < need)
+        return fail(&c->err, PIC_EINVAL, "src holds %zu bytes, the saved state needs %zu", bytes,
+                    need);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return check(c, "pic_load_state sync");
+    const char *in = (const char *)src;
+    const int par = (int)(h.step & 1);
+    int rc = PIC_OK;
+    // all current buffers start from zero; j^{n,*} is then restored
+    fill(c, c->wk.J1[0], (int64_t)c->run.nrep * 3 * ng, 0.0);
+    fill(c, c->wk.J1[1], (int64_t)c->run.nrep * 3 * ng, 0.0);
+    fill(c, c->wk.J2[0], (int64_t)c->run.nrep * 3 * ng, 0.0);
+    fill(c, c->wk.J2[1], (int64_t)c->run.nrep * 3 * ng, 0.0);
+    if (rc == PIC_OK) rc = copy_in(c, c->b.x, in + sp.x, np * 8, "pic_load_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, c->b.v, in + sp.v, np * 8 * c->p.nv, "pic_load_state copy");
+    if (rc == PIC_OK && sp.id) rc = copy_in(c, c->b.id, in + sp.id, np * 8, "pic_load_state copy");
+    if (rc == PIC_OK && sp.w) rc = copy_in(c, c->wk.wcur, in + sp.w, np * 8, "pic_load_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, c->wk.Ef[par], in + sp.E, 3 * ng * 8, "pic_load_state copy");
+    if (rc == PIC_OK) rc = copy_in(c, c->b.E, in + sp.E, 3 * ng * 8, "pic_load_state copy");
+    if (rc == PIC_OK && sp.B) rc = copy_in(c, c->wk.Bf[par], in + sp.B, 2 * ng * 8, "pic_load_state copy");
+    if (rc == PIC_OK && sp.B) rc = copy_in(c, c->b.B, in + sp.B, 2 * ng * 8, "pic_load_state copy");
+    std::vector<double> jsum;
+    if (rc == PIC_OK) {
+        if (h.nrep == c->run.nrep) {
+            rc = copy_in(c, c->wk.J1[par], in + sp.J1, (size_t)h.nrep * 3 * ng * 8, "pic_load_state copy");
+        } else {
+            // another number of replicas: their sum, in replica order, goes to replica 0
+            jsum.assign(3 * ng, 0.0);
+            const double *J = (const double *)(in + sp.J1);
+            for (int k = 0; k < h.nrep; ++k)
+                for (size_t i = 0; i < 3 * ng; ++i)
+                    jsum[i] += J[(size_t)k * 3 * ng + i];
+            rc = copy_in(c, c->wk.J1[par], jsum.data(), 3 * ng * 8, "pic_load_state copy");
+        }
+    }
+    DevState st = h.st;
+    st.recorded = h.step;
+    st.flag_a = 0;
+    if (rc == PIC_OK) rc = copy_in(c, c->wk.st, &st, sizeof st, "pic_load_state copy");
+    if (rc == PIC_OK)
+        rc = copy_in(c, c->wk.rec + h.step % c->run.rec_cap, &h.last, sizeof h.last,
+                     "pic_load_state copy");
+    if (rc == PIC_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = check(c, "pic_load_state sync");
+    if (rc != PIC_OK)
+        return rc;
+    c->steps_done = h.step;
+    c->records_read = h.step;
     return PIC_OK;
 }
 
@@ -1158,6 +1382,7 @@ template <int ORDER, int NV, bool EM>
 void batch_init_kind(pic_batch *c)
 {
     hipLaunchKernelGGL((k_batch_init_particles<NV>), dim3(c->grid), dim3(c->threads), 0, c->stream, c->bt);
+    hipLaunchKernelGGL(k_batch_fx_setup, dim3(c->p.n_runs), dim3(256), 0, c->stream, c->bt);
     if (c->p.flags & PIC_BF_INIT_GAUSS) {
         hipLaunchKernelGGL((k_batch_deposit_rho<ORDER>), dim3(c->grid), dim3(c->threads), c->lds_dep,
                            c->stream, c->bt);
@@ -1266,7 +1491,7 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
         R.c2 = q.c * q.c;
         R.qs = 1.0 / R.h;
         R.wu = q.length / (double)q.n_particles;
-        fixed_point_of(q.n_particles, q.n_cells, chunk, R);
+        fixed_point_of(chunk, R);
         for (int i = 0; i < 3; ++i)
             R.bext[i] = q.nv == 3 ? q.b_ext[i] : 0.0;
         R.w = b->w ? b->w + poff : nullptr;
@@ -1618,6 +1843,7 @@ void adj_forward_launches(pic_adj *c)
     fill_range(c->stream, w.Ef[0], (int64_t)(c->A.fwd.cninv - c->A.fwd.Ef[0]) / 8);
     fill_range(c->stream, c->b.E + ng, 2 * (int64_t)ng);
     hipLaunchKernelGGL((k_init_particles<1>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w, X, V);
+    hipLaunchKernelGGL(k_fx_setup, dim3(1), dim3(256), 0, c->stream, r, w);
     hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(r.nblocks), dim3(c->threads), lds_deposit(&c->q),
                        c->stream, r, w, X);
     hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w);

@@ -57,17 +57,20 @@ def test_validation_accepts_and_sizes():
                dict(nv=3, b_ext=(1.0, 0.0, 0.0)), dict(shape_order=1, n_cells=3),
                dict(n_particles=1), dict(block_threads=1024, grid_blocks=8192),
                dict(rebin_every=10), dict(rebin_every=1, deposit_mode="lds_atomic"),
-               dict(deposit_mode="window"), dict(rebin_every=8, deposit_mode="wave")]:
+               dict(deposit_mode="window"), dict(rebin_every=8, deposit_mode="wave"),
+               dict(deterministic=True), dict(deterministic=True, deposit_mode="lds_atomic"),
+               dict(nv=3, scheme="emec_li", n_cells=256, deterministic=True)]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
 
 
 def test_validation_lds_limits():
-    """The largest grids the particle passes fit in LDS (160 KB per workgroup)."""
+    """The largest grids the particle passes fit in LDS (160 KB per workgroup, less 1 KB
+    for the kernels' static LDS)."""
     import paper_2411_09605_amd as P
-    for kw in [dict(n_cells=1854), dict(shape_order=1, n_cells=2200),
-               dict(nv=3, scheme="emec_li", n_cells=701)]:
+    for kw in [dict(n_cells=1842), dict(shape_order=1, n_cells=2254),
+               dict(nv=3, scheme="emec_li", n_cells=697)]:
         assert P.validate(_good(**kw)) == 0, (kw, P.last_error())
 
 
@@ -79,9 +82,14 @@ def test_validation_lds_limits():
     (dict(nv=3, b_ext=(float("inf"), 0, 0)), -1), (dict(block_threads=100), -1),
     (dict(grid_blocks=100000), -1), (dict(deposit_mode=9), -1), (dict(rebin_every=-1), -1),
     (dict(n_cells=100000), -6), (dict(nv=3, scheme="emec_li", n_cells=4096), -6),
-    # 160 KB of LDS per workgroup: quadratic ES pass B needs 11 N_g + 80 doubles, EM 29 N_g + 128
-    (dict(n_cells=1855), -6), (dict(nv=3, scheme="emec_li", n_cells=702), -6),
+    # 159 KB of dynamic LDS per workgroup: quadratic ES pass B needs 11 N_g + 80 doubles,
+    # EM 29 N_g + 128
+    (dict(n_cells=1843), -6), (dict(nv=3, scheme="emec_li", n_cells=698), -6),
+    (dict(shape_order=1, n_cells=2255), -6),
     (dict(interleave=True, rebin_every=5), -1),
+    (dict(deterministic=True, rebin_every=5), -1),
+    (dict(deterministic=True, deposit_mode="window"), -1),
+    (dict(deterministic=True, deposit_mode="lds_f64"), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P
@@ -213,3 +221,12 @@ def test_run_static_rejects_without_a_device():
     assert "own workspace" in B.last_error()
     assert lib.pic_run_static(ctypes.byref(small), None, None, 1, None) == -1
     assert lib.pic_run_static(ctypes.byref(small), ctypes.byref(B.PicBuffers()), None, -1, None) == -1
+
+
+def test_deterministic_workspace_holds_partials():
+    """The deterministic mode keeps one current replica and a row of partial deposits per
+    workgroup (3 N_g doubles each)."""
+    import paper_2411_09605_amd as P
+    a = _good(n_particles=1_000_000, n_cells=512)
+    b = _good(n_particles=1_000_000, n_cells=512, deterministic=True)
+    assert P.workspace_size(b) > P.workspace_size(a) + 200 * 3 * 512 * 8

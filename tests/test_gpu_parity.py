@@ -150,13 +150,26 @@ def test_fast_particles_cross_several_cells():
 
 
 def test_fixed_point_side_tile_and_f64_mode():
-    """Velocities far beyond the fixed-point range of the LDS current tile (the side-tile
-    path, and positions wrapping several periods per step), and the FP64-atomic mode."""
-    _say("case: huge velocities (side tile), FP64 LDS mode")
+    """The fixed-point scale of the LDS current tile comes from the initial particles (twice
+    the largest w |v|): a few very fast particles set a coarse scale (positions wrapping
+    several periods per step); a cold plasma in a strong imposed field accelerates far
+    past the scale, so its contributions take the side tile (FP64 atomics by default,
+    a coarser fixed point in the deterministic mode); and the FP64-atomic mode."""
+    _say("case: huge velocities, side tile, FP64 LDS mode")
     wl = workloads.landau(n_particles=5000, n_cells=16, dt=0.01, alpha=0.1, order=2)
     wl.v = wl.v.copy()
     wl.v[0, ::50] *= 2000.0
     gu.run_pair(wl, 10)
+    cold = workloads.landau(n_particles=20_000, n_cells=32, dt=0.05, alpha=0.1, order=2)
+    cold.v = 1e-3 * cold.v
+    xn = np.arange(32) * cold.length / 32
+    cold.E0 = np.zeros((3, 32))
+    cold.E0[0] = 15.0 * np.sin(2 * np.pi * xn / cold.length)
+    cold.init_gauss = False
+    for det in (False, True):
+        _say(f"  cold plasma, strong field, deterministic={det}")
+        grec, _, gpu, _ = gu.run_pair(cold, 10, deterministic=det)
+        assert np.abs(gpu.state()["v"]).max() > 4.0        # well past 2 max w|v| / w
     wl2 = workloads.two_stream(n_particles=100_003, n_cells=64, steps=10)
     gu.run_pair(wl2, 10, deposit_mode="lds_f64")
 

@@ -265,6 +265,8 @@ def catalogue() -> Dict[str, dict]:
     return {
         "landau_1d1v_64c_100k": dict(builder="landau"),
         "two_stream_1d1v_512c_10M": dict(builder="two_stream"),
+        # four times the particles: the 640 MB state no longer fits the Infinity Cache
+        "two_stream_1d1v_512c_40M": dict(builder="two_stream", n_particles=40_000_000),
         "weibel_1d3v_256c_20M": dict(builder="weibel"),
         "batched_landau_512runs": dict(builder="batched_landau"),
         "adjoint_two_stream_256c_1M": dict(builder="adjoint_two_stream"),
