@@ -33,9 +33,12 @@ METRIC = "particle-steps/s (FP64, 10M particles) at ≤1e-11 energy error; % HBM
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per particle and launch of each particle pass (structure of
-# arrays, FP64): pass A reads x and v; pass B reads x, v and writes x, v.
-def alg_bytes(nv):
+# arrays, FP64): pass A reads x and v; pass B reads x, v and writes x, v.  ESEC1 runs one
+# pass per step (reported as pass B), which reads and writes the state once.
+def alg_bytes(nv, scheme="esec2"):
     state = 8 * (1 + nv)
+    if scheme == "esec1":
+        return {"pass_b": 2 * state}
     return {"pass_a": state, "pass_b": 2 * state}
 
 
@@ -64,7 +67,7 @@ def stored_traffic(workload, config):
         return None
     if doc.get("source_digest") != source_digest():
         return None
-    for k in ("block_threads", "grid_blocks", "rebin_every", "deposit_mode"):
+    for k in ("block_threads", "grid_blocks", "rebin_every", "deposit_mode", "scheme"):
         if doc.get("config", {}).get(k) != config.get(k):
             return None
     return doc.get("traffic_bytes_per_launch")
@@ -278,6 +281,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream_1d1v_512c_10M")
+    ap.add_argument("--scheme", default=None, choices=("esec2", "esec1", "emec_li"),
+                    help="scheme to run the workload with (default: the workload's own)")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--deposit-mode", default="auto")
@@ -319,6 +324,8 @@ def main():
     from paper_2411_09605_amd import Pic
 
     wl = workload_for(args.workload)
+    if args.scheme:
+        wl.scheme = args.scheme
     print(f"[bench] workload {args.workload}: {wl.n_particles} particles, {wl.n_cells} cells, "
           f"order {wl.order}, dt {wl.dt}", file=sys.stderr, flush=True)
     knobs = dict(block_threads=args.block_threads, grid_blocks=args.grid_blocks,
@@ -379,7 +386,7 @@ def main():
     kernels = {}
     roofline = None
     if prof:
-        ab = alg_bytes(wl.nv)
+        ab = alg_bytes(wl.nv, wl.scheme)
         for k, (tms, cnt) in prof.items():
             if cnt:
                 avg_us = tms / cnt * 1e3
@@ -390,12 +397,14 @@ def main():
                 kernels[k] = entry
         b = kernels["pass_b"]
         shape = {"block_threads": gpu.block_threads, "grid_blocks": gpu.grid_blocks,
-                 "rebin_every": args.rebin_every, "deposit_mode": args.deposit_mode}
+                 "rebin_every": args.rebin_every, "deposit_mode": args.deposit_mode,
+                 "scheme": wl.scheme}
         roofline = {"bound": "hbm", "achieved": b["alg_GBps"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(b["alg_GBps"] / HBM_PEAK_GBS, 4),
-                    "traffic": stored_traffic(args.workload, shape), "kernel": "k_pass_b",
-                    "alg_bytes_per_particle": alg_bytes(wl.nv)["pass_b"],
-                    "alg_bytes_per_launch": alg_bytes(wl.nv)["pass_b"] * n}
+                    "traffic": stored_traffic(args.workload, shape),
+                    "kernel": "k_esec1" if wl.scheme == "esec1" else "k_pass_b",
+                    "alg_bytes_per_particle": ab["pass_b"],
+                    "alg_bytes_per_launch": ab["pass_b"] * n}
 
     cpu = None
     if args.cpu_steps > 0:
@@ -413,13 +422,13 @@ def main():
                "host": host_info()}
 
     # the whole step against the same roofline: algorithmic bytes of both passes per step
-    ab_all = alg_bytes(wl.nv)
-    step_bytes = (ab_all["pass_a"] + ab_all["pass_b"]) * n
+    ab_all = alg_bytes(wl.nv, wl.scheme)
+    step_bytes = sum(ab_all.values()) * n
     step_gbs = step_bytes / (ms / args.steps * 1e-3) / 1e9
     state_bytes = n * 8 * (1 + wl.nv)
     step_roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
-                 "alg_bytes_per_particle_step": ab_all["pass_a"] + ab_all["pass_b"],
+                 "alg_bytes_per_particle_step": sum(ab_all.values()),
                  "state_bytes": state_bytes,
                  # MI355X's Infinity Cache (MALL) holds 256 MB: a smaller state can stay in
                  # it between the two passes, so part of the traffic never reaches HBM

@@ -21,7 +21,9 @@
  *               x^{n+1/2} with v*, Ampere update, provisional v-dagger, and the
  *               energy-restoring factor Gamma of eq. (opt_solution).
  *   PIC_ESEC1   eq. (naivetranslation) + eq. (PICmodification): as ESEC2 without the
- *               predictor deposit (v* uses E^n).
+ *               predictor deposit (v* uses E^n).  Its one grid-wide dependency per step
+ *               lets one launch finish step n and deposit step n+1's centred current,
+ *               so the state is read and written once per step.
  *   PIC_EMEC_LI eq. (EMbasic): ESEC2's particle update with the Crank-Nicolson
  *               (linearly implicit) Maxwell update; requires nv == 3.
  * Electrostatic Ampere form (eq. (ampere), 1D): E^{n+1} = E^n - dt (j - mean(j)); the
@@ -199,7 +201,8 @@ int pic_sync_state(pic_ctx *ctx);
  * The complete state of a run between two steps: positions, velocities, ids (with
  * PIC_F_TRACK_IDS), the library's permuted weights (rebins with non-uniform weights),
  * E^n and B^n, the predictor current j^{n,*} that ESEC2 and EMEC(LI) carry from one step
- * to the next (eq. (good_translation) with (doublestardef)), the step number n, the
+ * to the next (eq. (good_translation) with (doublestardef); for ESEC1 the centred current
+ * j^{n+1/2} its previous launch deposited), the step number n, the
  * initial total energy, the fallback total, the deposit's fixed-point scales and the
  * record of step n.  The saved state is a self-describing block of HOST memory in the
  * library's own format (native byte order; not a portable file format). */
@@ -226,7 +229,9 @@ int pic_load_state(pic_ctx *ctx, const void *src, size_t bytes);
 enum pic_kernel_class {
     PIC_K_PASS_A = 0,      /* gather at x*, v*, centred deposit; its last workgroup does
                               the Ampere / Crank-Nicolson field update                 */
-    PIC_K_PASS_B = 1,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit;
+    PIC_K_PASS_B = 1,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit
+                              (ESEC1: the one launch per step, which ends with the next
+                              step's centred deposit);
                               its last workgroup writes the step record and E* (B*)    */
     PIC_K_REBIN = 2,       /* counting-sort rebin (all of its kernels)                 */
     PIC_K_COUNT = 3

@@ -1640,6 +1640,174 @@ void k_pass_b(Run r, Work wk, int par, const double *X,
                                           red, &wctr);
 }
 
+// ------------------------------------------------------------ ESEC1 in one pass
+// ESEC1 (eq. (naivetranslation) with eq. (PICmodification)) has a single grid-wide
+// dependency per step: v* uses E^n, which is known before the step, so only the centred
+// current j^{n+1/2} -> E^{n+1} needs every particle.  One launch per step therefore
+// suffices: it finishes step n (E^{n+1} from j^{n+1/2}, v-dagger, Gamma, the state
+// write) and, with x^{n+1}, v^{n+1} still in registers, already computes step n+1's v*
+// (gathering the E^{n+1} it has just built) and deposits j^{n+3/2}.  The state is read
+// once and written once per step (32 B per particle in 1D-1V).  Step n + 1 recomputes that
+// v* from the stored x^{n+1}, v^{n+1} and the stored E^{n+1} with the same instructions,
+// so the deposit and the later gather see a bit-identical x^{n+3/2}.  The first step's
+// current j^{1/2} is deposited at initialisation by a pass A.
+// Currents rotate through three buffers: the pass reads j^{n+1/2} (Jr), deposits
+// j^{n+3/2} (Jd) and clears the buffer that held j^{n-1/2} (Jc), which step n + 1 deposits
+// into.  The per-workgroup scalars alternate between two arrays as well: this pass's lead
+// writes the record of step n from the scalars of the previous pass (wk.spart) while
+// the other workgroups write theirs for step n + 1 (spw).
+// LDS: jt[ncur][tw] | es[tw] | eb[tw] | e1[ng] | side[ncur][tw] | three coefficient tiles
+//      (E^n, E-bar, E^{n+1}), ES only.
+template <int ORDER, int NV, int DEP, int U = kUnrollB<NV>>
+__device__ __forceinline__ void esec1_body(const Run &r, const Work &wk, int par, int64_t step,
+                                           const double *X, const double *V, double *Xo,
+                                           double *Vo, const double *Jr, double *Jd, double *Jc,
+                                           double *spw, int64_t p0, int64_t p1, bool lead,
+                                           int slot, double *smem, double *red, int *wctr)
+{
+    const int ng = r.ng, tw = r.tw;
+    const unsigned lane = threadIdx.x & 63;
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
+    PBatch<U, NV> cur, nxt;
+    int64_t bcur = wb.first();
+    wb.reset();
+    double *jt = smem;
+    double *es = jt + tw;
+    double *eb = es + tw;
+    double *e1 = eb + tw;
+    double *side = e1 + ng;
+    double *ctn = smem + coef_offset(4 * tw + ng);     // E^n
+    double *ctb = ctn + (ORDER + 1) * tw;               // E-bar
+    double *ct1 = ctb + (ORDER + 1) * tw;               // E^{n+1}
+    const double *En = wk.Ef[par];
+    // fields: E^n into es, E^{n+1} into e1, E-bar into eb (field_update, as in pass B)
+    for (int i = threadIdx.x; i < ng; i += nthreads())
+        es[kGhost + i] = En[i];
+    load_batch(cur, X, V, r.vstride, bcur, p1);
+    field_update(r, wk, En, nullptr, Jr, e1, nullptr, eb, nullptr, nullptr, red, r.nrep);
+    tile_zero(jt, tw);
+    tile_zero(side, tw);
+    {
+        const int64_t part = p0 / r.chunk, nparts = r.nblocks;
+        rep_zero_part(Jc, ng, r.nrep, 3 * ng, part, nparts);
+    }
+    lds_barrier();
+    coef_fill<ORDER>(ctn, es + kGhost, ng, tw);
+    coef_fill<ORDER>(ctb, eb + kGhost, ng, tw);
+    coef_fill<ORDER>(ct1, e1, ng, tw);
+    if (lead) {
+        // the record of step n (its kinetic energy from the previous pass's scalars, its
+        // field energy from st->we), then E^{n+1} and its energy for step n + 1
+        if (step > wk.st->recorded)
+            write_record(r, wk, step, red);
+        for (int i = threadIdx.x; i < ng; i += nthreads())
+            wk.Ef[par ^ 1][i] = e1[i];
+        double we, wbv;
+        field_energies(r, e1, nullptr, &we, &wbv, red);
+        if (threadIdx.x == 0) {
+            wk.st->we = we;
+            wk.st->wb = 0.0;
+        }
+    }
+    lds_barrier();
+
+    Depo<ORDER, 1, DEP> dep;
+    dep.init(side, r, wk.st);
+    double ke = 0.0, gdev = 0.0;
+    int fb = 0, nonfinite = 0;
+    while (bcur < p1) {
+        const int64_t bnxt = wb.claim();
+        const unsigned nval = (unsigned)min(p1 - bcur, (int64_t)(64 * U));
+        double w[U];
+        load_weights(w, r.w, r.wu, bcur, p1);
+        load_batch(nxt, X, V, r.vstride, bnxt, p1);   // the last one is discarded
+        double *Xob = Xo + bcur;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned o = lane + 64u * u;
+            const bool valid = o < nval;
+            if constexpr (DEP != 2) {
+                if (!valid)
+                    break;
+            }
+            const double *v = cur.v[u];
+            const Half<ORDER, NV, false> hs = half_step<ORDER, NV, false>(r, cur.x[u], v, ctn, nullptr);
+            double vd[NV];
+            const double eh = gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
+            if constexpr (NV == 1) {
+                vd[0] = fma(r.dt, eh, v[0]);
+            } else {
+                const double *b = r.bext;
+                vd[0] = v[0] + r.dt * (eh + (hs.vs[1] * b[2] - hs.vs[2] * b[1]));
+                vd[1] = v[1] + r.dt * (hs.vs[2] * b[0] - hs.vs[0] * b[2]);
+                vd[2] = v[2] + r.dt * (hs.vs[0] * b[1] - hs.vs[1] * b[0]);
+            }
+            double num2 = 0.0, den = 0.0;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const double a2 = fma(2.0, hs.vs[c], -(vd[c] + v[c]));
+                num2 = fma(a2, vd[c] - v[c], num2);
+                den = fma(vd[c], vd[c], den);
+            }
+            int fbp = 0;
+            const double g = gamma_factor(num2, den, fbp);
+            double vn[NV];
+            double v2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                vn[c] = g * vd[c];
+                v2 = fma(vn[c], vn[c], v2);
+            }
+            const double xw = wrap_pos(hs.x1, r.L);
+            const double wp = valid ? w[u] : 0.0;
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < NV; ++c)
+                    __hip_atomic_store(&(Vo + c * r.vstride + bcur)[o], vn[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&Xob[o], xw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                fb += fbp;
+                gdev = fmax(gdev, fabs(g - 1.0));
+                ke = fma(wp, v2, ke);
+                if (!isfinite(v2) || !isfinite(hs.x1))
+                    nonfinite = 1;
+            }
+            // step n + 1: v* from E^{n+1} at x*_{n+1}, and the centred deposit j^{n+3/2}
+            const Half<ORDER, NV, false> h1 = half_step<ORDER, NV, false>(r, xw, vn, ct1, nullptr);
+            const double q[1] = {wp * r.qs * h1.vs[0]};
+            dep.add(jt, tw, ng, stencil<ORDER>(h1.xh * r.inv_h), q, valid, u == 0);
+        }
+        cur = nxt;
+        bcur = bnxt;
+    }
+    dep.finish(jt, tw, ng);
+    nonfinite |= dep.over;
+    double sc[4] = {ke, (double)fb, gdev, (double)nonfinite};
+    block_reduce<0xcu>(sc, red);
+    if (threadIdx.x == 0) {
+        spw[slot * kNS + 0] = 0.5 * sc[0];
+        spw[slot * kNS + 1] = sc[1];
+        spw[slot * kNS + 2] = sc[2];
+        spw[slot * kNS + 3] = sc[3];
+    }
+    lds_barrier();
+    dep.flush_tile(jt, dep_target(r, wk, Jd), 1, ng, tw);
+}
+
+template <int ORDER, int NV, int DEP>
+__global__ __launch_bounds__(kMaxThreads<NV>) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NV>)))
+void k_esec1(Run r, Work wk, int par, int64_t step, const double *X, const double *V, double *Xo,
+             double *Vo, const double *Jr, double *Jd, double *Jc, double *spw)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    esec1_body<ORDER, NV, DEP>(r, wk, par, step, X, V, Xo, Vo, Jr, Jd, Jc, spw, p0,
+                               r.interleave ? r.np : min(r.np, p0 + r.chunk),
+                               (int)blockIdx.x == r.nblocks - 1, blockIdx.x, smem, red, &wctr);
+}
+
 // End of a pic_step call (one workgroup): the record of the newest state and a copy of
 // the newest fields into the caller's arrays.
 __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step, double *red)

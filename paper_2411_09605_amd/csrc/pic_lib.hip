@@ -115,6 +115,13 @@ size_t lds_pass_b_of(bool em, int order, size_t ng)
               : ((size_t)pic::coef_offset((int)(4 * tw + ng)) + 2 * (order + 1) * tw) * 8;
 }
 
+// ESEC1 in one pass (esec1_body): jt | es | eb | e1[ng] | side | three coefficient tiles
+size_t lds_esec1_of(int order, size_t ng)
+{
+    const size_t tw = ng + 2 * kGhost;
+    return ((size_t)pic::coef_offset((int)(4 * tw + ng)) + 3 * (order + 1) * tw) * 8;
+}
+
 size_t lds_pass_a(const pic_params *p) { return lds_pass_a_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
 
 size_t lds_deposit(const pic_params *p) { return 2 * (is_em(p) ? 3 : 1) * tile_width(p) * 8; }
@@ -125,7 +132,8 @@ size_t lds_rebin(const pic_params *p) { return (size_t)kVBins * p->n_cells * 8; 
 
 size_t lds_need(const pic_params *p)
 {
-    size_t m = std::max(lds_pass_a(p), lds_pass_b(p));
+    size_t m = p->scheme == PIC_ESEC1 ? std::max(lds_pass_a(p), lds_esec1_of(p->shape_order, (size_t)p->n_cells))
+                                      : std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
     m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
@@ -188,7 +196,8 @@ Layout layout_of(const pic_params *p)
         L.J2[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
     }
     L.cninv = take(ng * 8);
-    L.spart = take((size_t)blocks_of(p, nullptr) * kNS * 8);
+    // two arrays of per-workgroup scalars (the one-pass ESEC1 alternates between them)
+    L.spart = take(2 * (size_t)blocks_of(p, nullptr) * kNS * 8);
     L.part = is_det(p) ? take((size_t)blocks_of(p, nullptr) * 3 * ng * 8) : 0;
     L.st = take(sizeof(DevState));
     L.rec = take((size_t)records_of(p) * sizeof(DevRecord));
@@ -348,7 +357,23 @@ void launch_pre(pic_ctx *c)
                        lds_deposit(&c->p), c->stream, c->run, c->wk, c->b.x, c->b.v);
 }
 
-enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO };
+enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO, D_ESEC1 };
+
+// The three current buffers the one-pass ESEC1 rotates through (j^{n+1/2} of step n is in
+// esec1_current(c, n)); ESEC1 has no predictor current, so J1[0] is the third.
+double *esec1_current(pic_ctx *c, int64_t n)
+{
+    const int k = (int)(n % 3);
+    return k == 0 ? c->wk.J2[0] : (k == 1 ? c->wk.J2[1] : c->wk.J1[0]);
+}
+
+// The per-workgroup scalars that hold the state of step m: the one-pass ESEC1 alternates
+// between the two arrays; the two-pass schemes use the first.
+double *spart_of(const pic_ctx *c, int64_t m)
+{
+    return (c->p.scheme == PIC_ESEC1 && (m & 1)) ? c->wk.spart + (size_t)c->run.nblocks * kNS
+                                                 : c->wk.spart;
+}
 
 // Deterministic mode: the ordered sum of the workgroups' partial deposits into replica 0
 // of J (ncomp components).
@@ -359,12 +384,26 @@ void reduce_partials(pic_ctx *c, double *J, int ncomp)
                        dim3(256), 0, c->stream, c->wk.part, J, c->run.nblocks, n, 3 * c->p.n_cells);
 }
 
+template <int ORDER, int NV, int DEP>
+void launch_esec1(pic_ctx *c, int64_t n, const double *X, const double *V)
+{
+    Work wk = c->wk;
+    wk.spart = spart_of(c, n);
+    launch_pass(c, k_esec1<ORDER, NV, DEP>,
+                (uint32_t)lds_esec1_of(ORDER, (size_t)c->p.n_cells), c->run, wk, (int)(n & 1), n, X, V,
+                c->b.x, c->b.v, (const double *)esec1_current(c, n), esec1_current(c, n + 1),
+                esec1_current(c, n + 2), spart_of(c, n + 1));
+}
+
 template <int ORDER, int DEP>
 void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, const double *V)
 {
     const int kind = kind_of(&c->p);
-    const bool pred = c->p.scheme != PIC_ESEC1;
     switch (what) {
+    case D_ESEC1:
+        if (kind == 0) launch_esec1<ORDER, 1, DEP>(c, step, X, V);
+        else launch_esec1<ORDER, 3, DEP>(c, step, X, V);
+        break;
     case D_PASS_A:
         if (kind == 0) launch_a<ORDER, 1, false, DEP>(c, par, step, X, V);
         else if (kind == 1) launch_a<ORDER, 3, false, DEP>(c, par, step, X, V);
@@ -372,11 +411,9 @@ void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, 
         break;
     case D_PASS_B:
         if (kind == 0) {
-            if (pred) launch_b<ORDER, 1, false, true, DEP>(c, par, X, V);
-            else launch_b<ORDER, 1, false, false, DEP>(c, par, X, V);
+            launch_b<ORDER, 1, false, true, DEP>(c, par, X, V);
         } else if (kind == 1) {
-            if (pred) launch_b<ORDER, 3, false, true, DEP>(c, par, X, V);
-            else launch_b<ORDER, 3, false, false, DEP>(c, par, X, V);
+            launch_b<ORDER, 3, false, true, DEP>(c, par, X, V);
         } else {
             launch_b<ORDER, 3, true, true, DEP>(c, par, X, V);
         }
@@ -420,10 +457,8 @@ void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0, const double 
     const int ncur = is_em(&c->p) ? 3 : 1;
     switch (what) {
     case D_PASS_A: reduce_partials(c, c->wk.J2[par], ncur); break;
-    case D_PASS_B:
-        if (c->p.scheme != PIC_ESEC1)
-            reduce_partials(c, c->wk.J1[par ^ 1], ncur);
-        break;
+    case D_PASS_B: reduce_partials(c, c->wk.J1[par ^ 1], ncur); break;
+    case D_ESEC1: reduce_partials(c, esec1_current(c, step + 1), 1); break;
     case D_PREDEPOSIT: reduce_partials(c, c->wk.J1[0], ncur); break;
     case D_RHO: reduce_partials(c, c->wk.J2[0], 1); break;
     }
@@ -712,6 +747,8 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
     if (p->scheme != PIC_ESEC1)
         dispatch(c, D_PREDEPOSIT);
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
+    if (p->scheme == PIC_ESEC1)
+        dispatch(c, D_PASS_A, 0, 0);    // j^{1/2}, read by the first one-pass step
     int rc = check(c, "pic_init launches");
     if (rc != PIC_OK)
         g_last_error = c->err;
@@ -733,13 +770,18 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
             X = c->wk.x2;
             V = c->wk.v2;
         }
-        {
-            Timer t(c, PIC_K_PASS_A, true);
-            dispatch(c, D_PASS_A, par, n, X, V);
-        }
-        {
+        if (c->p.scheme == PIC_ESEC1) {
             Timer t(c, PIC_K_PASS_B, true);
-            dispatch(c, D_PASS_B, par, n, X, V);
+            dispatch(c, D_ESEC1, par, n, X, V);
+        } else {
+            {
+                Timer t(c, PIC_K_PASS_A, true);
+                dispatch(c, D_PASS_A, par, n, X, V);
+            }
+            {
+                Timer t(c, PIC_K_PASS_B, true);
+                dispatch(c, D_PASS_B, par, n, X, V);
+            }
         }
         c->steps_done = n + 1;
         if (c->profiling && c->timed.size() > 4096) {
@@ -749,9 +791,12 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
             collect(c);
         }
     }
-    if (n_steps > 0)
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(grid_threads(c)), 0, c->stream, c->run, c->wk,
+    if (n_steps > 0) {
+        Work wk = c->wk;
+        wk.spart = spart_of(c, c->steps_done);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(grid_threads(c)), 0, c->stream, c->run, wk,
                            (int)(c->steps_done & 1), c->steps_done);
+    }
     return check(c, "pic_step launches");
 }
 
@@ -891,6 +936,13 @@ StateParts state_parts(const pic_ctx *c)
     return o;
 }
 
+// The current a step n starts from and that only the previous step produces: j^{n,*}
+// (ESEC2, EMEC(LI)) or, for the one-pass ESEC1, j^{n+1/2}.
+double *carried_current(pic_ctx *c, int64_t n)
+{
+    return c->p.scheme == PIC_ESEC1 ? esec1_current(c, n) : c->wk.J1[n & 1];
+}
+
 int copy_in(pic_ctx *c, void *dst, const void *src, size_t bytes, const char *what)
 {
     if (bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream) != hipSuccess)
@@ -952,8 +1004,8 @@ int pic_save_state(pic_ctx *c, void *dst, size_t bytes)
     if (rc == PIC_OK) rc = copy_in(c, out + sp.E, c->wk.Ef[par], 3 * ng * 8, "pic_save_state copy");
     if (rc == PIC_OK && sp.B) rc = copy_in(c, out + sp.B, c->wk.Bf[par], 2 * ng * 8, "pic_save_state copy");
     if (rc == PIC_OK)
-        rc = copy_in(c, out + sp.J1, c->wk.J1[par], (size_t)c->run.nrep * 3 * ng * 8,
-                     "pic_save_state copy");
+        rc = copy_in(c, out + sp.J1, carried_current(c, c->steps_done),
+                     (size_t)c->run.nrep * 3 * ng * 8, "pic_save_state copy");
     if (rc == PIC_OK && hipStreamSynchronize(c->stream) != hipSuccess)
         rc = check(c, "pic_save_state sync");
     if (rc != PIC_OK)
@@ -1009,7 +1061,8 @@ int pic_load_state(pic_ctx *c, const void *src, size_t bytes)
     std::vector<double> jsum;
     if (rc == PIC_OK) {
         if (h.nrep == c->run.nrep) {
-            rc = copy_in(c, c->wk.J1[par], in + sp.J1, (size_t)h.nrep * 3 * ng * 8, "pic_load_state copy");
+            rc = copy_in(c, carried_current(c, h.step), in + sp.J1, (size_t)h.nrep * 3 * ng * 8,
+                         "pic_load_state copy");
         } else {
             // another number of replicas: their sum, in replica order, goes to replica 0
             jsum.assign(3 * ng, 0.0);
@@ -1017,7 +1070,8 @@ int pic_load_state(pic_ctx *c, const void *src, size_t bytes)
             for (int k = 0; k < h.nrep; ++k)
                 for (size_t i = 0; i < 3 * ng; ++i)
                     jsum[i] += J[(size_t)k * 3 * ng + i];
-            rc = copy_in(c, c->wk.J1[par], jsum.data(), 3 * ng * 8, "pic_load_state copy");
+            rc = copy_in(c, carried_current(c, h.step), jsum.data(), 3 * ng * 8,
+                         "pic_load_state copy");
         }
     }
     DevState st = h.st;

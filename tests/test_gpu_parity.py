@@ -49,6 +49,55 @@ def test_esec1_10_steps(order):
     gu.run_pair(wl, 10, scheme="esec1")
 
 
+def _es3v(n=30_001):
+    wl = workloads.landau(n_particles=n, n_cells=40, alpha=0.1, order=2)
+    wl.v = np.stack([wl.v[0], workloads.normals(9, 12, n), workloads.normals(9, 14, n)])
+    wl.nv = 3
+    wl.b_ext = (0.3, -0.6, 1.2)
+    wl.w = wl.length / n * (1.0 + 0.5 * workloads.uniforms(9, 20, n))
+    return wl
+
+
+@pytest.mark.parametrize("case", ["3v_weights", "rebin_window", "rebin_wave", "interleave",
+                                  "shapes", "det", "tiny", "fast"])
+def test_esec1_one_pass_variants(case):
+    """ESEC1 runs one launch per step (its centred deposit for step n+1 is made at the end
+    of step n): 1D-3V with an imposed B and weights, rebins with ids, interleaved batches,
+    other launch shapes, the deterministic mode, tiny grids, particles crossing cells."""
+    _say(f"case: esec1 one pass, {case}")
+    ts = workloads.two_stream(n_particles=120_000, n_cells=128, steps=10)
+    if case == "3v_weights":
+        gu.run_pair(_es3v(), 10, scheme="esec1")
+    elif case == "rebin_window":
+        gu.run_pair(ts, 10, scheme="esec1", rebin_every=3, deposit_mode="window")
+    elif case == "rebin_wave":
+        gu.run_pair(_es3v(), 10, scheme="esec1", rebin_every=4, deposit_mode="wave")
+    elif case == "interleave":
+        gu.run_pair(ts, 10, scheme="esec1", interleave=True)
+        gu.run_pair(_es3v(), 6, scheme="esec1", interleave=True, block_threads=256, grid_blocks=13)
+    elif case == "shapes":
+        for bt, gb in [(64, 7), (512, 300), (1024, 3000)]:
+            gu.run_pair(ts, 4, scheme="esec1", block_threads=bt, grid_blocks=gb)
+    elif case == "det":
+        gu.run_pair(ts, 10, scheme="esec1", deterministic=True)
+    elif case == "tiny":
+        for n, ng, order in [(1, 3, 1), (2, 5, 2), (65, 7, 2)]:
+            gu.run_pair(workloads.landau(n_particles=n, n_cells=ng, order=order, alpha=0.2),
+                        10, scheme="esec1")
+    else:
+        wl = workloads.landau(n_particles=5000, n_cells=16, dt=0.5, alpha=0.1)
+        wl.v = wl.v * 6.0
+        gu.run_pair(wl, 10, scheme="esec1")
+
+
+@pytest.mark.timeout(900)
+def test_esec1_full_size_two_stream():
+    """ESEC1 on the two-stream benchmark workload (1e7 x 512, default launch): 10 steps
+    element by element against the oracle (fallback counts exactly)."""
+    _say("case: esec1 two-stream FULL 1e7 x 512, 10 steps")
+    gu.run_pair(workloads.two_stream(), 10, scheme="esec1", every=5)
+
+
 def test_es_3v_external_field_weights_ragged():
     """1D-3V electrostatic with an imposed uniform B, non-uniform weights and a particle
     count that leaves a ragged last workgroup."""
