@@ -177,6 +177,62 @@ def energy(state: State) -> np.void:
     return rec[0]
 
 
+# ------------------------------------------------ standard explicit PIC (comparison)
+def _std_sig():
+    L = lib()
+    if not getattr(L, "_std_ready", False):
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_std_run.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, ctypes.c_int64,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        L.oracle_std_run.restype = ctypes.c_int
+        L.oracle_binomial.argtypes = [ctypes.c_int, dp, dp]
+        L._std_ready = True
+    return L
+
+
+class StdState:
+    """A run of the standard explicit PIC scheme (Vlasov-Poisson, symmetric leapfrog/Boris,
+    section 5's comparison scheme) in the oracle; same host layout as ``State``.  E holds
+    the newest half-step field E^{n-1/2} (E^0 before the first step); ``records`` the
+    initial record and one per step."""
+
+    def __init__(self, wl, filter_rho: bool = False):
+        self.cfg = make_cfg(wl.nv, "esec2", wl.order, wl.n_cells, wl.n_particles, wl.length,
+                            wl.dt, wl.c, wl.b_ext)
+        self.x = np.ascontiguousarray(wl.x, dtype=np.float64).copy()
+        self.v = np.ascontiguousarray(wl.v, dtype=np.float64).reshape(wl.nv, -1).copy()
+        self.w = None if wl.w is None else np.ascontiguousarray(wl.w, dtype=np.float64).copy()
+        self.E = np.zeros((3, wl.n_cells))
+        self.B = np.zeros((2, wl.n_cells))
+        self.filter = bool(filter_rho)
+        self.records = []
+
+    def run(self, nsteps: int) -> np.ndarray:
+        """Advance ``nsteps``; returns the records (the current state's first)."""
+        first = not self.records
+        rec = np.zeros(nsteps + 1, dtype=DIAG_DTYPE)
+        e = np.ascontiguousarray(self.E[0]).copy()
+        rc = _std_sig().oracle_std_run(ctypes.byref(self.cfg), _p(self.x), _p(self.v),
+                                       _p(self.w), _p(e), nsteps, int(self.filter), int(first),
+                                       rec.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle rejected the configuration")
+        self.E[0] = e
+        if first:
+            self.records.append(rec[0])
+        else:
+            rec[0] = self.records[-1]
+        self.records.extend(rec[1:])
+        return rec
+
+
+def binomial(f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    _std_sig().oracle_binomial(f.size, _p(f), _p(out))
+    return out
+
+
 # ------------------------------------------------------------ tangent-linear derivative
 def _tlm_sig():
     L = lib()

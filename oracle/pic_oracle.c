@@ -571,6 +571,141 @@ int oracle_run(const ocfg *cfg, double *x, double *v, const double *w, double *E
 }
 
 /* ====================================================================================
+ * Standard explicit PIC, the comparison scheme of section 5: the Vlasov-Poisson system
+ * with the leapfrog/Boris push in its symmetric form, eq. (symm_Boris):
+ *   x* = x^n + dt/2 v^n,
+ *   v^{n+1} = v^n + dt (E(x*, t^{n+1/2}) + v^{n+1/2} x B),  v^{n+1/2} = (v^n + v^{n+1}) / 2,
+ *   x^{n+1} = x* + dt/2 v^{n+1}.
+ * E(., t^{n+1/2}) is the Poisson (Gauss) field of the charge density deposited at the
+ * positions x* (section 2.2), solved spectrally as in oracle_gauss_rho; optionally the
+ * density first passes once through the binomial filter (1/4, 1/2, 1/4), which section 5
+ * applies to the standard scheme.  B is the uniform imposed field (1D-3V); with nv = 1
+ * there is no B.  The velocity update is linear in v^{n+1}: v^{n+1/2} = u + v^{n+1/2} x t
+ * with u = v^n + dt/2 E, t = dt/2 B, solved in closed form (solve_vstar).
+ *
+ * Energy records (section 5.1's TE, with the leapfrog's fields at half steps):
+ *   rec[0]     = KE(v^0) + W_E(E^0), E^0 the Gauss field of the density at x^0;
+ *   rec[n + 1] = (KE(v^n) + KE(v^{n+1})) / 2 + W_E(E^{n+1/2})   (time (n + 1/2) dt).
+ * Fallbacks and max |Gamma - 1| are zero (there is no Gamma).
+ * ==================================================================================== */
+
+/* One pass of the periodic binomial filter: out_i = (f_{i-1} + 2 f_i + f_{i+1}) / 4. */
+void oracle_binomial(int ng, const double *f, double *out)
+{
+    for (int i = 0; i < ng; ++i)
+        out[i] = 0.25 * f[(i + ng - 1) % ng] + 0.5 * f[i] + 0.25 * f[(i + 1) % ng];
+}
+
+/* Field of the particles at positions pos: deposit, optional filter, Gauss solve. */
+static void std_field(const ocfg *cfg, const double *pos, const double *wv, const double *ones,
+                      int filter, double *rho, double *tmp, double *E)
+{
+    const int ng = cfg->n_cells;
+    const double h = cfg->length / ng;
+    oracle_deposit(cfg->order, cfg->n_particles, pos, wv, ones, ng, h, 0.0, rho);
+    if (filter) {
+        oracle_binomial(ng, rho, tmp);
+        memcpy(rho, tmp, sizeof(double) * (size_t)ng);
+    }
+    oracle_gauss_rho(ng, cfg->length, rho, E);
+}
+
+static double kinetic(const ocfg *cfg, const double *v, const double *wv)
+{
+    const int64_t np = cfg->n_particles;
+    nsum ke = {0.0, 0.0};
+    for (int64_t p = 0; p < np; ++p) {
+        double v2 = 0.0;
+        for (int c = 0; c < cfg->nv; ++c)
+            v2 += v[c * np + p] * v[c * np + p];
+        nadd(&ke, 0.5 * wv[p] * v2);
+    }
+    return ke.s + ke.c;
+}
+
+static double field_energy(const ocfg *cfg, const double *E)
+{
+    const double h = cfg->length / cfg->n_cells;
+    nsum we = {0.0, 0.0};
+    for (int i = 0; i < cfg->n_cells; ++i)
+        nadd(&we, 0.5 * h * E[i] * E[i]);
+    return we.s + we.c;
+}
+
+/* Run n steps of the standard scheme (nv = 1, or 3 with the uniform B of cfg->b_ext).
+ * x, v: the state in, the state n steps later out.  E: the newest field out (E^{n-1/2},
+ * or E^0 after a first call with n = 0).  first != 0: the state is the initial one (x is
+ * wrapped, rec[0] is the initial record); otherwise the run continues and rec[0] is not
+ * written.  rec[1..n] as described above.  Returns 0, or -1 for a bad configuration. */
+int oracle_std_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
+                   int64_t nsteps, int filter, int first, odiag *rec)
+{
+    if (oracle_check(cfg) || cfg->scheme == 2)
+        return -1;
+    const int64_t np = cfg->n_particles;
+    const int ng = cfg->n_cells, nv = cfg->nv;
+    const double L = cfg->length, h = L / ng, dt = cfg->dt;
+    const size_t P = sizeof(double) * (size_t)np, G = sizeof(double) * (size_t)ng;
+    double *wv = malloc(P), *ones = malloc(P), *xs = malloc(P), *gE = malloc(P);
+    double *rho = malloc(G), *tmp = malloc(G);
+    const double wu = L / (double)np;
+    for (int64_t p = 0; p < np; ++p) {
+        wv[p] = w ? w[p] : wu;
+        ones[p] = 1.0;
+        if (first)
+            x[p] = wrap(x[p], L);
+    }
+    double ke_old = kinetic(cfg, v, wv);
+    if (first) {
+        /* record 0: the field of the initial positions */
+        std_field(cfg, x, wv, ones, filter, rho, tmp, E);
+        memset(&rec[0], 0, sizeof(odiag));
+        rec[0].kinetic = ke_old;
+        rec[0].field_e = field_energy(cfg, E);
+        rec[0].total = rec[0].kinetic + rec[0].field_e;
+    }
+    for (int64_t n = 0; n < nsteps; ++n) {
+        /* x* = x^n + dt/2 v^n and the field E^{n+1/2} of the density there */
+        for (int64_t p = 0; p < np; ++p)
+            xs[p] = x[p] + 0.5 * dt * v[p];
+        std_field(cfg, xs, wv, ones, filter, rho, tmp, E);
+        oracle_gather(cfg->order, np, xs, E, ng, h, 0.0, gE);
+        int nonfinite = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            if (nv == 1) {
+                v[p] = v[p] + dt * gE[p];
+            } else {
+                double u[3], t[3], vh[3];
+                for (int c = 0; c < 3; ++c) {
+                    u[c] = v[c * np + p] + (c == 0 ? 0.5 * dt * gE[p] : 0.0);
+                    t[c] = 0.5 * dt * cfg->b_ext[c];
+                }
+                solve_vstar(u, t, vh);                      /* v^{n+1/2} */
+                for (int c = 0; c < 3; ++c)
+                    v[c * np + p] = 2.0 * vh[c] - v[c * np + p];
+            }
+            const double x1 = xs[p] + 0.5 * dt * v[p];
+            for (int c = 0; c < nv; ++c)
+                if (!isfinite(v[c * np + p]))
+                    nonfinite = 1;
+            if (!isfinite(x1))
+                nonfinite = 1;
+            x[p] = wrap(x1, L);
+        }
+        const double ke_new = kinetic(cfg, v, wv);
+        odiag *d = &rec[n + 1];
+        memset(d, 0, sizeof(odiag));
+        d->kinetic = 0.5 * (ke_old + ke_new);
+        d->field_e = field_energy(cfg, E);
+        d->total = d->kinetic + d->field_e;
+        d->nonfinite = nonfinite;
+        ke_old = ke_new;
+    }
+    free(wv); free(ones); free(xs); free(gE); free(rho); free(tmp);
+    return 0;
+}
+
+/* ====================================================================================
  * Tangent-linear (forward-mode) derivative of an ESEC2 run, 1D-1V electrostatic.
  *
  * The run is the map (x^0, v^0) -> (x^n, v^n, E^n), n = 1..N, of eq. (good_translation)
