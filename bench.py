@@ -37,7 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # pass per step (reported as pass B), which reads and writes the state once.
 def alg_bytes(nv, scheme="esec2"):
     state = 8 * (1 + nv)
-    if scheme == "esec1":
+    if scheme in ("esec1", "standard"):
+        # one particle pass per step (the standard scheme's field launch, timed as
+        # pass A, moves no particle data)
         return {"pass_b": 2 * state}
     return {"pass_a": state, "pass_b": 2 * state}
 
@@ -281,7 +283,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream_1d1v_512c_10M")
-    ap.add_argument("--scheme", default=None, choices=("esec2", "esec1", "emec_li"),
+    ap.add_argument("--scheme", default=None, choices=("esec2", "esec1", "emec_li", "standard"),
                     help="scheme to run the workload with (default: the workload's own)")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
@@ -402,7 +404,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": b["alg_GBps"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(b["alg_GBps"] / HBM_PEAK_GBS, 4),
                     "traffic": stored_traffic(args.workload, shape),
-                    "kernel": "k_esec1" if wl.scheme == "esec1" else "k_pass_b",
+                    "kernel": {"esec1": "k_esec1", "standard": "k_std_pass"}.get(wl.scheme, "k_pass_b"),
                     "alg_bytes_per_particle": ab["pass_b"],
                     "alg_bytes_per_launch": ab["pass_b"] * n}
 

@@ -26,6 +26,15 @@
  *               so the state is read and written once per step.
  *   PIC_EMEC_LI eq. (EMbasic): ESEC2's particle update with the Crank-Nicolson
  *               (linearly implicit) Maxwell update; requires nv == 3.
+ *   PIC_STANDARD the comparison scheme of section 5 (not energy-conserving): Vlasov-Poisson
+ *               with the leapfrog/Boris push in its symmetric form, eq. (symm_Boris):
+ *               x* = x^n + dt/2 v^n, E^{n+1/2} the Gauss field (spectral, as the initial
+ *               field) of the charge density at the x*, v^{n+1} = v^n + dt (E^{n+1/2}(x*)
+ *               + v^{n+1/2} x b_ext), x^{n+1} = x* + dt/2 v^{n+1}.  Needs
+ *               PIC_F_INIT_GAUSS; electrostatic only.  Its fields live at half steps:
+ *               after step n the caller's E holds E^{n-1/2}, and the record of step
+ *               n >= 1 is TE at (n - 1/2) dt, the mean of the kinetic energies of steps
+ *               n - 1 and n plus the field energy of E^{n-1/2}.
  * Electrostatic Ampere form (eq. (ampere), 1D): E^{n+1} = E^n - dt (j - mean(j)); the
  * mean is removed because E = -d(phi)/dx has zero mean in a periodic domain.
  * Correction (eq. (opt_solution)): r = 1 + 2 (v* - (v-dagger + v^n)/2).(v-dagger - v^n)
@@ -64,7 +73,7 @@ enum pic_status {
     PIC_EUNSUPPORTED = -6    /* valid but outside what this library handles            */
 };
 
-enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2 };
+enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2, PIC_STANDARD = 3 };
 
 enum pic_flag {
     PIC_F_INIT_GAUSS = 1u,   /* set E_x^0 from the particles: dE/dx = rho - 1 solved
@@ -75,6 +84,9 @@ enum pic_flag {
                                 instead of in contiguous chunks (faster once the state
                                 streams from HBM); chosen by itself when the state is
                                 larger than 192 MB.  Not with rebin_every > 0           */
+    PIC_F_FILTER_RHO = 16u,  /* PIC_STANDARD: one pass of the binomial filter (1/4, 1/2,
+                                1/4) on the charge density before each field solve
+                                (section 5 filters the standard scheme's density)       */
     PIC_F_DETERMINISTIC = 8u /* bit-for-bit reproducible runs (and continuations through
                                 pic_save_state / pic_load_state with the same launch
                                 shape): each workgroup's deposit is summed exactly in
@@ -227,7 +239,8 @@ int pic_load_state(pic_ctx *ctx, const void *src, size_t bytes);
 
 /* Kernel classes timed by the optional event profiler. */
 enum pic_kernel_class {
-    PIC_K_PASS_A = 0,      /* gather at x*, v*, centred deposit; its last workgroup does
+    PIC_K_PASS_A = 0,      /* (PIC_STANDARD: the field solve of each step)
+                              gather at x*, v*, centred deposit; its last workgroup does
                               the Ampere / Crank-Nicolson field update                 */
     PIC_K_PASS_B = 1,      /* gather at x^{n+1/2}, Gamma, state write, predictor deposit
                               (ESEC1: the one launch per step, which ends with the next

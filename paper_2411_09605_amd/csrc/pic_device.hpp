@@ -223,7 +223,7 @@ struct Run {
     int32_t nrep;          // replicas of the current accumulators (see Work::J1)
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
     int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
-    int32_t pad0;
+    int32_t filter_rho;    // standard scheme: binomial filter on the charge density
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -817,6 +817,9 @@ __device__ __forceinline__ double wave_max(double v)
 
 // LDS for the block reductions: up to 4 values per wavefront of a 1024-thread workgroup.
 constexpr int kRedSize = 64;
+// Ordered sums over many rows (k_reduce_partials, k_std_field): a workgroup of 256 threads
+// takes kRedEntries consecutive entries, kRedSegments threads per entry.
+constexpr int kRedEntries = 32, kRedSegments = 8;
 
 // Deterministic reduction of N values over the workgroup in one round of LDS: value k is
 // summed, or maximised where bit k of MAXMASK is set, always in the same fixed order for a
@@ -1199,11 +1202,17 @@ __device__ __forceinline__ void field_energies(const Run &r, const double *E, co
 
 // Write the record of `step` from the pass-B scalars of every workgroup (summed in a
 // fixed order) and the field energies in st; run by one workgroup.
+// The standard scheme (Run::scheme == kStandard) has its fields at half steps: its record
+// of step n >= 1 is TE at (n - 1/2) dt, the mean of the kinetic energies of steps n - 1
+// (slot 4, written by the same pass) and n plus the field energy of E^{n-1/2}.
+constexpr int kStandard = 3;
+
 __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
 {
+    const bool half = r.scheme == kStandard && step > 0;
     double ke = 0.0, fb = 0.0, gd = 0.0, nf = 0.0;
     for (int b = threadIdx.x; b < r.nblocks; b += nthreads()) {
-        ke += wk.spart[b * kNS + 0];
+        ke += half ? 0.5 * (wk.spart[b * kNS + 0] + wk.spart[b * kNS + 4]) : wk.spart[b * kNS + 0];
         fb += wk.spart[b * kNS + 1];
         gd = fmax(gd, wk.spart[b * kNS + 2]);
         nf = fmax(nf, wk.spart[b * kNS + 3]);
@@ -1229,7 +1238,7 @@ __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64
         st->nonfinite_sticky |= (nf != 0.0);
         DevRecord rec;
         rec.step = step;
-        rec.time = (double)step * r.dt;
+        rec.time = ((double)step - (half ? 0.5 : 0.0)) * r.dt;
         rec.kinetic = ke;
         rec.field_e = st->we;
         rec.field_b = st->wb;
@@ -1808,6 +1817,245 @@ void k_esec1(Run r, Work wk, int par, int64_t step, const double *X, const doubl
                                (int)blockIdx.x == r.nblocks - 1, blockIdx.x, smem, red, &wctr);
 }
 
+// ------------------------------------------------ standard explicit PIC (comparison)
+// The scheme section 5 compares against: Vlasov-Poisson with the leapfrog/Boris push in
+// its symmetric form, eq. (symm_Boris): x* = x^n + dt/2 v^n; v^{n+1} = v^n + dt (E^{n+1/2}(x*)
+// + v^{n+1/2} x B); x^{n+1} = x* + dt/2 v^{n+1}; E^{n+1/2} is the Gauss field of the charge
+// density at the positions x*.  Each step is a field launch (k_std_field: density ->
+// E^{n+1/2}) and one particle pass (k_std_pass), which ends by depositing the density at
+// x*_{n+1} = x^{n+1} + dt/2 v^{n+1} for the next field launch; the next pass recomputes
+// that x* from the stored state with the same instruction.  32 B per particle-step.
+
+// Row of the spectral Gauss solve as a convolution, E_i = sum_j G_{(i - j) mod N} rho_j:
+// G_d = (2/N) sum_{m=1}^{M} sin(2 pi m d / N) / k_m, k_m = 2 pi m / L, with M the largest
+// mode below the Nyquist mode (the mean and Nyquist modes of E are zero, as in gauss_body).
+__device__ void std_green_body(const Run &r, const Work &wk)
+{
+    const int ng = r.ng;
+    for (int d = threadIdx.x; d < ng; d += nthreads()) {
+        double acc = 0.0;
+        for (int m = 1; 2 * m < ng; ++m) {
+            const long long md = ((long long)m * d) % ng;
+            const double k = 2.0 * M_PI * m / r.L;
+            acc += sinpi(2.0 * (double)md / ng) / k;
+        }
+        wk.cninv[d] = 2.0 * acc / ng;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_std_green(Run r, Work wk) { std_green_body(r, wk); }
+
+// E^{n+1/2} from the density replicas in rho (optionally binomial-filtered once, (1/4,
+// 1/2, 1/4)) into E.  A workgroup of 256 threads computes 32 consecutive nodes; for each,
+// 8 threads sum consecutive eighths of the convolution in node order and the 8 sums are
+// added in order, so the field does not depend on the launch.
+// LDS: rho[ng] | g[2 ng] (the Green's row twice, so that (i - j) needs no modulo) |
+//      filtered rho[ng].
+__global__ __launch_bounds__(256) void k_std_field(Run r, Work wk, const double *rho_rep, double *E,
+                                                   int filter)
+{
+    extern __shared__ double smem[];
+    __shared__ double seg[kRedSegments][kRedEntries];
+    const int ng = r.ng;
+    double *rho = smem, *g = smem + ng, *rf = smem + 3 * ng;
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
+        rho[i] = rep_sum(rho_rep, i, r.nrep, 3 * ng);
+        const double gi = wk.cninv[i];
+        g[i] = gi;
+        g[ng + i] = gi;
+    }
+    __syncthreads();
+    if (filter) {
+        for (int i = threadIdx.x; i < ng; i += nthreads())
+            rf[i] = 0.25 * rho[i == 0 ? ng - 1 : i - 1] + 0.5 * rho[i] + 0.25 * rho[i + 1 == ng ? 0 : i + 1];
+        __syncthreads();
+        rho = rf;
+    }
+    const int t = threadIdx.x, e = t % kRedEntries, sg = t / kRedEntries;
+    const int i = blockIdx.x * kRedEntries + e;
+    const int per = (ng + kRedSegments - 1) / kRedSegments;
+    const int j0 = min(ng, sg * per), j1 = min(ng, j0 + per);
+    double acc = 0.0;
+    if (i < ng)
+        for (int j = j0; j < j1; ++j)
+            acc = fma(g[i - j + ng], rho[j], acc);
+    seg[sg][e] = acc;
+    __syncthreads();
+    if (sg == 0 && i < ng) {
+        double s2 = seg[0][e];
+#pragma unroll
+        for (int k2 = 1; k2 < kRedSegments; ++k2)
+            s2 += seg[k2][e];
+        E[i] = s2;
+    }
+}
+
+// Charge density at x*_0 = x^0 + dt/2 v^0 into J (the first field launch's input).
+template <int ORDER>
+__device__ __forceinline__ void std_prime_body(const Run &r, const Work &wk,
+                                               const double *__restrict__ X,
+                                               const double *__restrict__ V, double *J,
+                                               int64_t p0, int64_t p1, double *smem)
+{
+    double *jt = smem;
+    double *side = jt + r.tw;
+    tile_zero(jt, 2 * r.tw);
+    __syncthreads();
+    Depo<ORDER, 1, 0> dep;
+    dep.init(side, r, wk.st, 1);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nthreads()) {
+        const double q[1] = {(r.w ? r.w[p] : r.wu) * r.qs};
+        dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), q);
+    }
+    flag_over(dep, wk);
+    __syncthreads();
+    dep.flush_tile(jt, dep_target(r, wk, J), 1, r.ng, r.tw);
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(1024) void k_std_prime(Run r, Work wk, const double *__restrict__ X,
+                                                    const double *__restrict__ V, double *J)
+{
+    extern __shared__ double smem[];
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    std_prime_body<ORDER>(r, wk, X, V, J, p0, min(r.np, p0 + r.chunk), smem);
+}
+
+// One particle pass of step n: gather E^{n+1/2} at x*, the Boris velocity update, the new
+// state, the kinetic energies before and after, and the density at x*_{n+1}.
+// LDS: jt[tw] | es[tw] | side[tw] | coefficient tile of E^{n+1/2}.
+template <int ORDER, int NV, int DEP, int U = kUnrollB<NV>>
+__device__ __forceinline__ void std_pass_body(const Run &r, const Work &wk, int par, int64_t step,
+                                              const double *X, const double *V, double *Xo,
+                                              double *Vo, double *Jd, double *Jc, double *spw,
+                                              int64_t p0, int64_t p1, bool lead, int slot,
+                                              double *smem, double *red, int *wctr)
+{
+    const int ng = r.ng, tw = r.tw;
+    const unsigned lane = threadIdx.x & 63;
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
+    PBatch<U, NV> cur, nxt;
+    int64_t bcur = wb.first();
+    wb.reset();
+    double *jt = smem;
+    double *es = jt + tw;
+    double *side = es + tw;
+    double *ct = smem + coef_offset(3 * tw);
+    const double *Eh = wk.Ef[par];
+    for (int i = threadIdx.x; i < ng; i += nthreads())
+        es[kGhost + i] = Eh[i];
+    load_batch(cur, X, V, r.vstride, bcur, p1);
+    tile_zero(jt, tw);
+    tile_zero(side, tw);
+    {
+        const int64_t part = p0 / r.chunk, nparts = r.nblocks;
+        rep_zero_part(Jc, ng, r.nrep, 3 * ng, part, nparts);
+    }
+    lds_barrier();
+    coef_fill<ORDER>(ct, es + kGhost, ng, tw);
+    if (lead) {
+        if (step > wk.st->recorded)
+            write_record(r, wk, step, red);
+        double we, wbv;
+        field_energies(r, es + kGhost, nullptr, &we, &wbv, red);
+        if (threadIdx.x == 0) {
+            wk.st->we = we;
+            wk.st->wb = 0.0;
+        }
+    }
+    lds_barrier();
+
+    Depo<ORDER, 1, DEP> dep;
+    dep.init(side, r, wk.st, 1);
+    double ke1 = 0.0, ke0 = 0.0;
+    int nonfinite = 0;
+    while (bcur < p1) {
+        const int64_t bnxt = wb.claim();
+        const unsigned nval = (unsigned)min(p1 - bcur, (int64_t)(64 * U));
+        double w[U];
+        load_weights(w, r.w, r.wu, bcur, p1);
+        load_batch(nxt, X, V, r.vstride, bnxt, p1);   // the last one is discarded
+        double *Xob = Xo + bcur;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned o = lane + 64u * u;
+            const bool valid = o < nval;
+            if constexpr (DEP != 2) {
+                if (!valid)
+                    break;
+            }
+            const double *v = cur.v[u];
+            const double xs = fma(r.hdt, v[0], cur.x[u]);
+            const double ep = gather_poly<ORDER>(ct, cell_of<ORDER>(xs * r.inv_h, ng));
+            double vn[NV];
+            if constexpr (NV == 1) {
+                vn[0] = fma(r.dt, ep, v[0]);
+            } else {
+                // v^{n+1/2} = u + v^{n+1/2} x t, u = v^n + dt/2 E, t = dt/2 B; v^{n+1} = 2 v^{n+1/2} - v^n
+                const double uu[3] = {fma(r.hdt, ep, v[0]), v[1], v[2]};
+                const double tt[3] = {r.hdt * r.bext[0], r.hdt * r.bext[1], r.hdt * r.bext[2]};
+                double vh[3];
+                rotate_half(uu, tt, vh);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    vn[c] = fma(2.0, vh[c], -v[c]);
+            }
+            const double x1 = fma(r.hdt, vn[0], xs);
+            const double xw = wrap_pos(x1, r.L);
+            const double wp = valid ? w[u] : 0.0;
+            double v2 = 0.0, v20 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                v2 = fma(vn[c], vn[c], v2);
+                v20 = fma(v[c], v[c], v20);
+            }
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < NV; ++c)
+                    __hip_atomic_store(&(Vo + c * r.vstride + bcur)[o], vn[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&Xob[o], xw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                ke1 = fma(wp, v2, ke1);
+                ke0 = fma(wp, v20, ke0);
+                if (!isfinite(v2) || !isfinite(x1))
+                    nonfinite = 1;
+            }
+            // the density of step n + 1 at x*_{n+1}
+            const double q[1] = {wp * r.qs};
+            dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h), q, valid, u == 0);
+        }
+        cur = nxt;
+        bcur = bnxt;
+    }
+    dep.finish(jt, tw, ng);
+    nonfinite |= dep.over;
+    double sc[3] = {ke1, ke0, (double)nonfinite};
+    block_reduce<4u>(sc, red);
+    if (threadIdx.x == 0) {
+        spw[slot * kNS + 0] = 0.5 * sc[0];
+        spw[slot * kNS + 1] = 0.0;
+        spw[slot * kNS + 2] = 0.0;
+        spw[slot * kNS + 3] = sc[2];
+        spw[slot * kNS + 4] = 0.5 * sc[1];
+    }
+    lds_barrier();
+    dep.flush_tile(jt, dep_target(r, wk, Jd), 1, ng, tw);
+}
+
+template <int ORDER, int NV, int DEP>
+__global__ __launch_bounds__(kMaxThreads<NV>) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NV>)))
+void k_std_pass(Run r, Work wk, int par, int64_t step, const double *X, const double *V, double *Xo,
+                double *Vo, double *Jd, double *Jc, double *spw)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kRedSize];
+    __shared__ int wctr;
+    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
+    std_pass_body<ORDER, NV, DEP>(r, wk, par, step, X, V, Xo, Vo, Jd, Jc, spw, p0,
+                                  r.interleave ? r.np : min(r.np, p0 + r.chunk),
+                                  (int)blockIdx.x == r.nblocks - 1, blockIdx.x, smem, red, &wctr);
+}
+
 // End of a pic_step call (one workgroup): the record of the newest state and a copy of
 // the newest fields into the caller's arrays.
 __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step, double *red)
@@ -2125,7 +2373,6 @@ __global__ __launch_bounds__(1024) void k_fx_setup(Run r, Work wk)
 // of a current; the deterministic mode keeps one replica), always in the same order: a
 // workgroup of 256 threads takes 32 consecutive entries; for each entry, 8 threads sum
 // consecutive eighths of the rows in row order, and the 8 sums are then added in order.
-constexpr int kRedEntries = 32, kRedSegments = 8;
 
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ part,
                                                          double *__restrict__ J, int nblocks,
@@ -2171,6 +2418,15 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem)
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
     rep_gather(rho, wk.J2[0], ng, r.nrep, 3 * ng);
     __syncthreads();
+    if (r.filter_rho) {
+        // the standard scheme's filtered density (as in k_std_field), through ei
+        for (int i = threadIdx.x; i < ng; i += nthreads())
+            ei[i] = 0.25 * rho[i == 0 ? ng - 1 : i - 1] + 0.5 * rho[i] + 0.25 * rho[i + 1 == ng ? 0 : i + 1];
+        __syncthreads();
+        for (int i = threadIdx.x; i < ng; i += nthreads())
+            rho[i] = ei[i];
+        __syncthreads();
+    }
     for (int m = threadIdx.x; m < ng; m += nthreads()) {
         double re = 0.0, im = 0.0;
         if (m != 0 && 2 * m != ng) {

@@ -53,6 +53,7 @@ constexpr size_t kMaxLds = 160 * 1024 - 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 bool is_det(const pic_params *p) { return (p->flags & PIC_F_DETERMINISTIC) != 0; }
+bool is_std(const pic_params *p) { return p->scheme == PIC_STANDARD; }
 
 struct Layout {
     size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, part, st, rec;
@@ -122,6 +123,16 @@ size_t lds_esec1_of(int order, size_t ng)
     return ((size_t)pic::coef_offset((int)(4 * tw + ng)) + 3 * (order + 1) * tw) * 8;
 }
 
+// standard scheme: the particle pass (jt | es | side | coefficient tile) and the field
+// launch (rho | Green's row twice | filtered rho)
+size_t lds_std_pass_of(int order, size_t ng)
+{
+    const size_t tw = ng + 2 * kGhost;
+    return ((size_t)pic::coef_offset((int)(3 * tw)) + (order + 1) * tw) * 8;
+}
+
+size_t lds_std_field_of(size_t ng) { return 4 * ng * 8; }
+
 size_t lds_pass_a(const pic_params *p) { return lds_pass_a_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
 
 size_t lds_deposit(const pic_params *p) { return 2 * (is_em(p) ? 3 : 1) * tile_width(p) * 8; }
@@ -133,7 +144,9 @@ size_t lds_rebin(const pic_params *p) { return (size_t)kVBins * p->n_cells * 8; 
 size_t lds_need(const pic_params *p)
 {
     size_t m = p->scheme == PIC_ESEC1 ? std::max(lds_pass_a(p), lds_esec1_of(p->shape_order, (size_t)p->n_cells))
-                                      : std::max(lds_pass_a(p), lds_pass_b(p));
+               : is_std(p) ? std::max(lds_std_pass_of(p->shape_order, (size_t)p->n_cells),
+                                      lds_std_field_of((size_t)p->n_cells))
+                           : std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
     m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
@@ -246,8 +259,12 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "abi_version %d != %d", p->abi_version, PIC_ABI_VERSION);
     if (p->nv != 1 && p->nv != 3)
         return fail(err, PIC_EINVAL, "nv must be 1 or 3 (got %d)", p->nv);
-    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_EMEC_LI)
+    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_STANDARD)
         return fail(err, PIC_EINVAL, "unknown scheme %d", p->scheme);
+    if (p->scheme == PIC_STANDARD && !(p->flags & PIC_F_INIT_GAUSS))
+        return fail(err, PIC_EINVAL, "PIC_STANDARD needs PIC_F_INIT_GAUSS (its field comes from the density)");
+    if ((p->flags & PIC_F_FILTER_RHO) && p->scheme != PIC_STANDARD)
+        return fail(err, PIC_EINVAL, "PIC_F_FILTER_RHO is for PIC_STANDARD only");
     if (p->scheme == PIC_EMEC_LI && p->nv != 3)
         return fail(err, PIC_EINVAL, "PIC_EMEC_LI needs nv == 3");
     if (p->shape_order != 1 && p->shape_order != 2)
@@ -270,7 +287,7 @@ int validate(const pic_params *p, std::string *err)
     if (p->rebin_every < 0)
         return fail(err, PIC_EINVAL, "rebin_every must be >= 0");
     if (p->flags & ~(uint32_t)(PIC_F_INIT_GAUSS | PIC_F_TRACK_IDS | PIC_F_INTERLEAVE |
-                               PIC_F_DETERMINISTIC))
+                               PIC_F_DETERMINISTIC | PIC_F_FILTER_RHO))
         return fail(err, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
     if ((p->flags & PIC_F_DETERMINISTIC) && p->rebin_every > 0)
         return fail(err, PIC_EINVAL, "PIC_F_DETERMINISTIC needs rebin_every == 0");
@@ -357,7 +374,7 @@ void launch_pre(pic_ctx *c)
                        lds_deposit(&c->p), c->stream, c->run, c->wk, c->b.x, c->b.v);
 }
 
-enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO, D_ESEC1 };
+enum { D_PASS_A, D_PASS_B, D_PREDEPOSIT, D_RHO, D_ESEC1, D_STD_PASS, D_STD_PRIME };
 
 // The three current buffers the one-pass ESEC1 rotates through (j^{n+1/2} of step n is in
 // esec1_current(c, n)); ESEC1 has no predictor current, so J1[0] is the third.
@@ -367,12 +384,21 @@ double *esec1_current(pic_ctx *c, int64_t n)
     return k == 0 ? c->wk.J2[0] : (k == 1 ? c->wk.J2[1] : c->wk.J1[0]);
 }
 
+// Which of the double-buffered fields holds the newest field after m steps: E^m in
+// Ef[m & 1], or for the standard scheme E^{m-1/2} in Ef[(m - 1) & 1] (E^0 in Ef[0]).
+int field_parity(const pic_ctx *c, int64_t m)
+{
+    if (c->p.scheme == PIC_STANDARD)
+        return m > 0 ? (int)((m - 1) & 1) : 0;
+    return (int)(m & 1);
+}
+
 // The per-workgroup scalars that hold the state of step m: the one-pass ESEC1 alternates
 // between the two arrays; the two-pass schemes use the first.
 double *spart_of(const pic_ctx *c, int64_t m)
 {
-    return (c->p.scheme == PIC_ESEC1 && (m & 1)) ? c->wk.spart + (size_t)c->run.nblocks * kNS
-                                                 : c->wk.spart;
+    const bool alt = c->p.scheme == PIC_ESEC1 || c->p.scheme == PIC_STANDARD;
+    return (alt && (m & 1)) ? c->wk.spart + (size_t)c->run.nblocks * kNS : c->wk.spart;
 }
 
 // Deterministic mode: the ordered sum of the workgroups' partial deposits into replica 0
@@ -382,6 +408,31 @@ void reduce_partials(pic_ctx *c, double *J, int ncomp)
     const int n = ncomp * c->p.n_cells;
     hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + kRedEntries - 1) / kRedEntries)),
                        dim3(256), 0, c->stream, c->wk.part, J, c->run.nblocks, n, 3 * c->p.n_cells);
+}
+
+// The standard scheme's step n: the field launch (E^{n+1/2} into Ef[n & 1] from the density
+// in J2[n & 1]) and the particle pass (density of step n + 1 into J2[(n + 1) & 1]).
+template <int ORDER, int NV, int DEP>
+void launch_std_pass(pic_ctx *c, int64_t n, const double *X, const double *V)
+{
+    const int par = (int)(n & 1);
+    Work wk = c->wk;
+    wk.spart = spart_of(c, n);
+    launch_pass(c, k_std_pass<ORDER, NV, DEP>,
+                (uint32_t)lds_std_pass_of(ORDER, (size_t)c->p.n_cells), c->run, wk, par, n, X, V,
+                c->b.x, c->b.v, c->wk.J2[par ^ 1], c->wk.J2[par], spart_of(c, n + 1));
+}
+
+void launch_std_field(pic_ctx *c, int64_t n)
+{
+    const int par = (int)(n & 1);
+    hipEvent_t e0 = c->kev[0], e1 = c->kev[1];
+    c->kev[0] = c->kev[1] = nullptr;
+    const unsigned grid = (unsigned)((c->p.n_cells + kRedEntries - 1) / kRedEntries);
+    hipExtLaunchKernelGGL(k_std_field, dim3(grid), dim3(256),
+                          (uint32_t)lds_std_field_of((size_t)c->p.n_cells), c->stream, e0, e1, 0u,
+                          c->run, c->wk, (const double *)c->wk.J2[par], c->wk.Ef[par],
+                          (int)c->run.filter_rho);
 }
 
 template <int ORDER, int NV, int DEP>
@@ -403,6 +454,14 @@ void dispatch_dep(pic_ctx *c, int what, int par, int64_t step, const double *X, 
     case D_ESEC1:
         if (kind == 0) launch_esec1<ORDER, 1, DEP>(c, step, X, V);
         else launch_esec1<ORDER, 3, DEP>(c, step, X, V);
+        break;
+    case D_STD_PASS:
+        if (kind == 0) launch_std_pass<ORDER, 1, DEP>(c, step, X, V);
+        else launch_std_pass<ORDER, 3, DEP>(c, step, X, V);
+        break;
+    case D_STD_PRIME:
+        hipLaunchKernelGGL((k_std_prime<ORDER>), dim3(c->run.nblocks), dim3(c->threads),
+                           lds_deposit(&c->p), c->stream, c->run, c->wk, X, V, c->wk.J2[0]);
         break;
     case D_PASS_A:
         if (kind == 0) launch_a<ORDER, 1, false, DEP>(c, par, step, X, V);
@@ -459,6 +518,8 @@ void dispatch(pic_ctx *c, int what, int par = 0, int64_t step = 0, const double 
     case D_PASS_A: reduce_partials(c, c->wk.J2[par], ncur); break;
     case D_PASS_B: reduce_partials(c, c->wk.J1[par ^ 1], ncur); break;
     case D_ESEC1: reduce_partials(c, esec1_current(c, step + 1), 1); break;
+    case D_STD_PASS: reduce_partials(c, c->wk.J2[(par ^ 1) & 1], 1); break;
+    case D_STD_PRIME: reduce_partials(c, c->wk.J2[0], 1); break;
     case D_PREDEPOSIT: reduce_partials(c, c->wk.J1[0], ncur); break;
     case D_RHO: reduce_partials(c, c->wk.J2[0], 1); break;
     }
@@ -507,7 +568,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.nrep = nrep_of(p);
     r.interleave = 0;
     r.det = is_det(p) ? 1 : 0;
-    r.pad0 = 0;
+    r.filter_rho = (p->flags & PIC_F_FILTER_RHO) ? 1 : 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -749,6 +810,10 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
     if (p->scheme == PIC_ESEC1)
         dispatch(c, D_PASS_A, 0, 0);    // j^{1/2}, read by the first one-pass step
+    if (is_std(p)) {
+        hipLaunchKernelGGL(k_std_green, dim3(1), dim3(gt), 0, c->stream, r, w);
+        dispatch(c, D_STD_PRIME);       // the density at x*_0 for the first field launch
+    }
     int rc = check(c, "pic_init launches");
     if (rc != PIC_OK)
         g_last_error = c->err;
@@ -773,6 +838,15 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
         if (c->p.scheme == PIC_ESEC1) {
             Timer t(c, PIC_K_PASS_B, true);
             dispatch(c, D_ESEC1, par, n, X, V);
+        } else if (is_std(&c->p)) {
+            {
+                Timer t(c, PIC_K_PASS_A, true);
+                launch_std_field(c, n);
+            }
+            {
+                Timer t(c, PIC_K_PASS_B, true);
+                dispatch(c, D_STD_PASS, par, n, X, V);
+            }
         } else {
             {
                 Timer t(c, PIC_K_PASS_A, true);
@@ -795,7 +869,7 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
         Work wk = c->wk;
         wk.spart = spart_of(c, c->steps_done);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(grid_threads(c)), 0, c->stream, c->run, wk,
-                           (int)(c->steps_done & 1), c->steps_done);
+                           field_parity(c, c->steps_done), c->steps_done);
     }
     return check(c, "pic_step launches");
 }
@@ -940,6 +1014,8 @@ StateParts state_parts(const pic_ctx *c)
 // (ESEC2, EMEC(LI)) or, for the one-pass ESEC1, j^{n+1/2}.
 double *carried_current(pic_ctx *c, int64_t n)
 {
+    if (c->p.scheme == PIC_STANDARD)
+        return c->wk.J2[n & 1];     // the density at x*_n
     return c->p.scheme == PIC_ESEC1 ? esec1_current(c, n) : c->wk.J1[n & 1];
 }
 
@@ -991,7 +1067,7 @@ int pic_save_state(pic_ctx *c, void *dst, size_t bytes)
         h.b_ext[i] = c->p.b_ext[i];
     h.step = c->steps_done;
     h.payload_bytes = sp.total - sizeof h;
-    const int par = (int)(c->steps_done & 1);
+    const int par = field_parity(c, c->steps_done);
     const size_t np = (size_t)c->p.n_particles, ng = (size_t)c->p.n_cells;
     int rc = copy_in(c, &h.st, c->wk.st, sizeof h.st, "pic_save_state copy");
     if (rc == PIC_OK)
@@ -1043,7 +1119,7 @@ int pic_load_state(pic_ctx *c, const void *src, size_t bytes)
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return check(c, "pic_load_state sync");
     const char *in = (const char *)src;
-    const int par = (int)(h.step & 1);
+    const int par = field_parity(c, h.step);
     int rc = PIC_OK;
     // all current buffers start from zero; j^{n,*} is then restored
     fill(c, c->wk.J1[0], (int64_t)c->run.nrep * 3 * ng, 0.0);
@@ -1310,6 +1386,8 @@ int batch_validate(const pic_batch_params *p)
         return fail(nullptr, PIC_EINVAL, "n_runs >= 1 and the per-run arrays are required");
     if (p->flags & ~(uint32_t)PIC_BF_INIT_GAUSS)
         return fail(nullptr, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (p->scheme == PIC_STANDARD)
+        return fail(nullptr, PIC_EUNSUPPORTED, "the batched form runs the energy-conserving schemes");
     if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > kBatchMaxThreads))
         return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, %d]", kBatchMaxThreads);
     if (p->chunk < 0 || p->chunk % batch_threads(p))

@@ -86,7 +86,10 @@ def run_pair(wl, steps, scheme=None, every=1, tol=TOL, **knobs):
     if knobs.get("rebin_every", 0) > 0:
         knobs.setdefault("track_ids", True)
     gpu = Pic.from_workload(wl, scheme=scheme, **knobs)
-    ost = oracle.State(wl, scheme=scheme)
+    if (scheme or wl.scheme) == "standard":
+        ost = oracle.StdState(wl, filter_rho=knobs.get("filter_rho", False))
+    else:
+        ost = oracle.State(wl, scheme=scheme)
     vscale = max(1.0, float(np.abs(wl.v).max()))
     grecs = [gpu.diagnostics()]
     orecs = [ost.run(0)]

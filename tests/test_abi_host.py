@@ -59,7 +59,10 @@ def test_validation_accepts_and_sizes():
                dict(rebin_every=10), dict(rebin_every=1, deposit_mode="lds_atomic"),
                dict(deposit_mode="window"), dict(rebin_every=8, deposit_mode="wave"),
                dict(deterministic=True), dict(deterministic=True, deposit_mode="lds_atomic"),
-               dict(nv=3, scheme="emec_li", n_cells=256, deterministic=True)]:
+               dict(nv=3, scheme="emec_li", n_cells=256, deterministic=True),
+               dict(scheme="standard", init_gauss=True),
+               dict(scheme="standard", init_gauss=True, filter_rho=True, nv=3),
+               dict(scheme="standard", init_gauss=True, deterministic=True)]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
@@ -90,6 +93,9 @@ def test_validation_lds_limits():
     (dict(deterministic=True, rebin_every=5), -1),
     (dict(deterministic=True, deposit_mode="window"), -1),
     (dict(deterministic=True, deposit_mode="lds_f64"), -1),
+    (dict(scheme="standard"), -1),                        # needs PIC_F_INIT_GAUSS
+    (dict(filter_rho=True, init_gauss=True), -1),         # filter: standard scheme only
+    (dict(scheme=4, init_gauss=True), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P
@@ -151,7 +157,7 @@ def test_batch_validation_accepts_and_sizes():
     dict(n_particles=[], n_cells=[], length=[]), dict(n_cells=[64, 2, 512]),
     dict(n_particles=[1000, 0, 5]), dict(length=[10.0, -1.0, 1.0]), dict(chunk=100),
     dict(block_threads=96), dict(graph_steps=-1), dict(nv=1, scheme="emec_li"),
-    dict(n_cells=[64, 3, 100000]), dict(dt=float("inf")),
+    dict(n_cells=[64, 3, 100000]), dict(dt=float("inf")), dict(scheme="standard"),
 ])
 def test_batch_validation_rejects(kw):
     import paper_2411_09605_amd.binding as B
