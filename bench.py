@@ -191,6 +191,63 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_dt_sweep(args):
+    """Section 5.1 (Fig. maxerrs_vs_dt): maximum energy error and Gamma fallbacks against
+    dt for ESEC2, ESEC1 and the standard scheme on the Landau workload (1e5 particles, 64
+    cells, tent, alpha 0.01) over t = 20, in 1D-1V and with the paper's two velocity
+    components (v_y thermal, run as 1D-3V).  One JSON line; the headline value is ESEC2's
+    largest energy error with two velocity components up to dt = 1."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2411_09605_amd import Pic
+
+    T = 20.0
+    rows = []
+    for variant, builder in (("1v", workloads.landau), ("2v", workloads.landau_2v)):
+        for dt in (0.05, 0.1, 0.2, 0.4, 0.7, 1.0):
+            steps = int(round(T / dt))
+            for scheme in ("esec2", "esec1", "standard"):
+                wl = builder(n_particles=100_000, n_cells=64, dt=dt, steps=steps)
+                g = Pic.from_workload(wl, scheme=scheme, device="cuda:0",
+                                      record_capacity=steps + 8)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(g.stream)
+                g.step(steps)
+                e1.record(g.stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                recs = g.diagnostics()
+                g.destroy()
+                en = energy_report(recs)
+                ab = sum(alg_bytes(wl.nv, scheme).values()) * wl.n_particles
+                gbs = ab / (ms / steps * 1e-3) / 1e9
+                rows.append({"velocity_space": variant, "dt": dt, "scheme": scheme,
+                             "steps": steps, "max_rel_err": en["max_rel_err"],
+                             "max_delta_n": en["max_delta_n"], "fallbacks": en["fallbacks"],
+                             "max_fallbacks_per_step": int(recs["fallbacks"].max()),
+                             "ms_per_step": ms / steps, "step_GBps": round(gbs, 1),
+                             "step_frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)})
+                print(f"[bench] dt sweep {variant} dt {dt} {scheme}: err {en['max_rel_err']:.2e}"
+                      f" fallbacks {en['fallbacks']}", file=sys.stderr, flush=True)
+    head = max(r["max_rel_err"] for r in rows if r["velocity_space"] == "2v"
+               and r["scheme"] == "esec2")
+    total_steps = sum(r["steps"] for r in rows)
+    total_ms = sum(r["ms_per_step"] * r["steps"] for r in rows)
+    out = {"metric": "max fractional energy error vs dt, Landau 1e5 x 64 (FP64); ESEC2 with "
+                     "two velocity components, dt <= 1",
+           "value": head, "unit": "fractional energy error", "n_gpus": 1,
+           "steps": total_steps, "warmup": 0, "ms_per_step": total_ms / total_steps,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "landau_1d1v_64c_100k and landau_2v_64c_100k", "t_end": T,
+                      "schemes": ["esec2", "esec1", "standard"]},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args):
     """Adjoint form: (forward + backward) time against the forward-only plain step."""
     import numpy as np
@@ -298,7 +355,7 @@ def main():
                     help="also time --late-steps steps from this step on, after the "
                          "instability has saturated (0: skip)")
     ap.add_argument("--late-steps", type=int, default=20)
-    ap.add_argument("--form", choices=("plain", "batched", "adjoint"), default="plain")
+    ap.add_argument("--form", choices=("plain", "batched", "adjoint", "dt_sweep"), default="plain")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batched form: steps per captured hipGraph")
     ap.add_argument("--seq-steps", type=int, default=20,
@@ -320,6 +377,8 @@ def main():
         return bench_batched(args)
     if args.form == "adjoint":
         return bench_adjoint(args)
+    if args.form == "dt_sweep":
+        return bench_dt_sweep(args)
 
     import numpy as np
     import torch

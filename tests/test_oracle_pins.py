@@ -259,3 +259,24 @@ def test_weibel_growth_rate_quiet_positions():
     res = np.log(amp[sel]) - np.polyval(np.polyfit(t[sel], np.log(amp[sel]), 1), t[sel])
     assert np.abs(res).max() < 0.1
     assert _rel_energy_drift(np.array(st.records)) < 1e-12
+
+
+def test_dt_sweep_fallbacks_and_energy_section_5_1():
+    """Section 5.1 (Fig. maxerrs_vs_dt): with the paper's two velocity components, ESEC2
+    keeps energy to rounding up to dt = 0.7 with no fallback, while ESEC1's fallbacks and
+    energy error grow with dt; in 1D-1V (where |v-dagger| near zero is far more likely)
+    ESEC2 still has fewer fallbacks and a smaller error than ESEC1 at every dt."""
+    e1, f1 = [], []
+    for dt in (0.1, 0.4, 0.7):
+        steps = int(round(10.0 / dt))
+        for wlf in (workloads.landau_2v, workloads.landau):
+            r2 = oracle.State(wlf(n_particles=10_000, dt=dt, alpha=0.05), "esec2").run(steps)
+            r1 = oracle.State(wlf(n_particles=10_000, dt=dt, alpha=0.05), "esec1").run(steps)
+            assert r2["fallbacks"].sum() <= r1["fallbacks"].sum()
+            # (below 1e-13 both are rounding)
+            assert max(_rel_energy_drift(r2), 1e-13) <= max(_rel_energy_drift(r1), 1e-13)
+            if wlf is workloads.landau_2v:
+                assert r2["fallbacks"].sum() == 0 and _rel_energy_drift(r2) < 1e-13, dt
+                e1.append(_rel_energy_drift(r1))
+                f1.append(r1["fallbacks"].sum())
+    assert e1[0] < e1[1] < e1[2] and f1[0] <= f1[1] <= f1[2] and f1[2] > f1[0]

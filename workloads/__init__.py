@@ -5,6 +5,6 @@ initial density, the workload catalogue).  It contains none of the particle-in-c
 step's arithmetic, and it imports neither the oracle nor the GPU package.
 """
 from .generators import (  # noqa: F401
-    uniforms, normals, sample_density, Workload, landau, two_stream, weibel,
+    uniforms, normals, sample_density, Workload, landau, landau_2v, two_stream, weibel,
     batched_landau, adjoint_two_stream, catalogue, by_name,
 )

@@ -206,6 +206,20 @@ def weibel(n_particles: int = 20_000_000, n_cells: int = 256, k0: float = 0.5,
                               seed=seed))
 
 
+def landau_2v(n_particles: int = 100_000, n_cells: int = 64, dt: float = 0.1,
+              steps: int = 200, order: int = 1, alpha: float = 0.01, seed: int = 1,
+              scheme: str = "esec2") -> Workload:
+    """Landau damping with two velocity components (the paper's tests have a 2D velocity
+    space, section 5): the 1D-1V Landau workload plus a thermal v_y ~ N(0, 1), v_z = 0, no
+    magnetic field, run as 1D-3V."""
+    wl = landau(n_particles=n_particles, n_cells=n_cells, dt=dt, steps=steps, order=order,
+                alpha=alpha, seed=seed, scheme=scheme)
+    wl.v = np.stack([wl.v[0], normals(seed, S_VY, n_particles), np.zeros(n_particles)])
+    wl.nv = 3
+    wl.name = "landau_2v"
+    return wl
+
+
 def _run_seed(seed: int, r: int) -> int:
     with np.errstate(over="ignore"):
         z = _mix64(np.array([np.uint64(seed) * GAMMA + np.uint64(r + 1) * _STREAM],
