@@ -186,6 +186,16 @@ size_t pic_workspace_size(const pic_params *p);
  * PIC_EUNSUPPORTED; pic_last_error(NULL) then describes the problem. */
 int pic_validate_params(const pic_params *p);
 
+/* Host-only check of a run's inputs before they are copied to the device (no GPU needed):
+ * the parameters as pic_validate_params, then every value of the HOST arrays x [N_p],
+ * v [nv][N_p], w [N_p] (may be NULL), E [3][N_g] and B [2][N_g] (PIC_EMEC_LI; may be NULL
+ * otherwise) must be finite.  PIC_ENONFINITE names the first non-finite value (array and
+ * index) in pic_last_error(NULL) and stores its index within that array in *bad_index (may
+ * be NULL; -1 when nothing is wrong); PIC_EINVAL for NULL x, v, E (or B in EM).  Nothing is
+ * modified.  The device-side counterpart is the non-finite flag of the records. */
+int pic_check_inputs(const pic_params *p, const double *x, const double *v, const double *w,
+                     const double *E, const double *B, int64_t *bad_index);
+
 /* Bind a context to the caller's buffers and HIP stream (hipStream_t, may be NULL for
  * the null stream) and enqueue the initial work: wrap x into [0, L); optionally the
  * Gauss solve for E_x^0; the energy record of step 0; for ESEC2/EMEC(LI) the predictor

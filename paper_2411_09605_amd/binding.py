@@ -50,7 +50,8 @@ DIAG_DTYPE = np.dtype([("step", "i8"), ("time", "f8"), ("kinetic", "f8"), ("fiel
 EXPORTS = ("pic_workspace_size", "pic_validate_params", "pic_init", "pic_step",
            "pic_diagnostics", "pic_sync_state", "pic_profile_enable", "pic_profile_read",
            "pic_launch_shape", "pic_destroy", "pic_strerror", "pic_last_error",
-           "pic_run_static", "pic_state_size", "pic_save_state", "pic_load_state")
+           "pic_run_static", "pic_state_size", "pic_save_state", "pic_load_state",
+           "pic_check_inputs")
 STATIC_SCRATCH_BYTES = 16 << 20
 KERNEL_CLASSES = ("pass_a", "pass_b", "rebin")
 
@@ -97,6 +98,9 @@ def _load():
     lib.pic_last_error.restype = ctypes.c_char_p
     lib.pic_run_static.argtypes = [P, ctypes.POINTER(PicBuffers), vp, ctypes.c_int64, vp]
     lib.pic_run_static.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.pic_check_inputs.argtypes = [P, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_check_inputs.restype = ctypes.c_int
     lib.pic_state_size.argtypes = [vp]
     lib.pic_state_size.restype = ctypes.c_size_t
     lib.pic_save_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -133,6 +137,21 @@ def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: in
 
 def validate(p: PicParams) -> int:
     return lib.pic_validate_params(ctypes.byref(p))
+
+
+def check_inputs(p: PicParams, x, v, E, B=None, w=None):
+    """pic_check_inputs on host arrays: (status, index of the first non-finite value or -1)."""
+    def ptr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep = []
+    bad = ctypes.c_int64()
+    rc = lib.pic_check_inputs(ctypes.byref(p), ptr(x), ptr(v), ptr(w), ptr(E), ptr(B),
+                              ctypes.byref(bad))
+    return rc, bad.value
 
 
 def workspace_size(p: PicParams) -> int:
@@ -278,6 +297,8 @@ class Pic:
         ``ids`` numbers the particles 0 .. N_p - 1."""
         import torch
         n = int(np.asarray(x).shape[0])
+        cls.check_host_inputs(nv, scheme, order, n_cells, length, dt, x, v, E0=E0, B0=B0, w=w,
+                              c=c, b_ext=b_ext, init_gauss=init_gauss, **knobs)
         if track_ids and ids is None:
             ids = np.arange(n, dtype=np.int64)
         f64 = dict(dtype=torch.float64, device=device)
@@ -298,6 +319,19 @@ class Pic:
         p = make_params(nv, scheme, order, n, n_cells, length, dt, c=c, b_ext=b_ext,
                         init_gauss=init_gauss, track_ids=ids is not None, **knobs)
         return cls(p, xt, vt, Et, Bt, wt, it)
+
+    @staticmethod
+    def check_host_inputs(nv, scheme, order, n_cells, length, dt, x, v, E0=None, B0=None,
+                          w=None, c=1.0, b_ext=(0.0, 0.0, 0.0), init_gauss=False, **knobs):
+        """pic_check_inputs on the host arrays ``from_arrays`` would upload; raises
+        PicError (PIC_ENONFINITE names the array and index)."""
+        n = int(np.asarray(x).shape[0])
+        p = make_params(nv, scheme, order, n, n_cells, length, dt, c=c, b_ext=b_ext,
+                        init_gauss=init_gauss, **knobs)
+        E = np.zeros((3, n_cells)) if E0 is None else E0
+        B = (np.zeros((2, n_cells)) if B0 is None else B0) if scheme in ("emec_li", 2) else B0
+        rc, _ = check_inputs(p, x, v, E, B, w)
+        _check(rc)
 
     @classmethod
     def from_workload(cls, wl, scheme: Optional[str] = None, device="cuda", **knobs) -> "Pic":

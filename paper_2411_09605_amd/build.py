@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "pic_lib.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "pic_device.hpp"),
         os.path.join(HERE, "csrc", "pic_adjoint.hpp"),
+        os.path.join(HERE, "csrc", "pic_types.hpp"), os.path.join(HERE, "csrc", "pic_host.cpp"),
         os.path.join(os.path.dirname(HERE), "include", "pic.h")]
 LIB = os.path.join(HERE, "libpic.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

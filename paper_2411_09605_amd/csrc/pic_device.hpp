@@ -30,14 +30,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace pic {
+#include "pic_types.hpp"
 
-constexpr int kMaxGrid = 8192;   // upper bound on particle-pass workgroups
-// Per-workgroup scalars: KE, fallbacks, max|G-1|, nonfinite (every pass B), and at
-// initialisation also sum w, max w and max w |v| (slots 4-6, for the fixed-point scales).
-constexpr int kNS = 8;
-constexpr int kGhost = 4;        // ghost nodes on each side of an LDS field or current tile
-constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
+namespace pic {
 
 // Particles whose loads each thread issues together before computing on them, per pass
 // (more loads in flight against fewer waves per SIMD from the extra registers).
@@ -188,77 +183,6 @@ template <int U> struct WaveBatches {
     }
 };
 
-// Per-step record, laid out exactly like pic_diag.
-struct DevRecord {
-    int64_t step;
-    double time, kinetic, field_e, field_b, total, rel_energy_err, max_gamma_dev;
-    int64_t fallbacks, fallbacks_total;
-    int32_t nonfinite, pad;
-};
-
-struct DevState {
-    int64_t recorded;      // newest step whose record is written
-    double te0;            // total energy of step 0
-    int64_t fb_total;
-    double we, wb;         // field energies of the newest fields (written by pass B)
-    int32_t nonfinite_sticky;
-    int32_t flag_a;        // set by a pass A whose deposit met a value it cannot hold
-                           // (deterministic mode); taken into the next record
-    // Fixed-point scales 2^S and 2^-S of the LDS deposit tiles (Depo<., ., 0>), chosen at
-    // initialisation from the particles (k_fx_setup): [0] currents, [1] charge density.
-    double fx_scale[2], fx_inv[2];
-};
-
-// Scalars of a run, passed by value to every kernel.
-struct Run {
-    int64_t np;
-    int64_t vstride;       // distance between velocity components in V (N_p, or the
-                           // packed total in the batched form)
-    int32_t ng, nv;
-    int32_t nblocks;       // workgroups of the particle passes
-    int32_t rec_cap;
-    int64_t chunk;         // particles per workgroup
-    int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI)
-    int32_t tw;            // LDS tile width: ng + 2 kGhost
-    int32_t nrep;          // replicas of the current accumulators (see Work::J1)
-    int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
-    int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
-    int32_t filter_rho;    // standard scheme: binomial filter on the charge density
-    double L, h, inv_h, dt, hdt, c2;
-    double qs;             // 1/h: deposit factor (times w_p)
-    double wu;             // uniform weight L / N_p
-    double fx_lim;         // contributions with |c| 2^S >= fx_lim leave the fixed-point tile
-                           // (each tile entry then stays below 2^62: fx_lim <= 2^62 / chunk)
-    double bext[3];
-    const double *w;       // [N_p] weights or nullptr (uniform)
-};
-
-// Workspace arrays (device pointers).  Index [k] below is the step parity.
-struct Work {
-    double *E, *B;         // caller fields: E[3][ng], B[2][ng] (B null for ES)
-    double *Ef[2];         // [3][ng] E^n (Ef[n & 1])
-    double *Bf[2];         // [2][ng] B^n
-    // Currents are accumulated with device-scope atomics from every workgroup.  To keep
-    // the chain of atomics on each address short, they go to nrep replicas [nrep][3][ng]
-    // (workgroup b adds into replica b mod nrep); readers sum the replicas in order.
-    double *J1[2];         // [nrep][3][ng] predictor current j^{n,*} (J1[n & 1])
-    double *J2[2];         // [nrep][3][ng] centred current j^{*,n+1/2} (J2[n & 1])
-    double *cninv;         // [ng] first row of the Crank-Nicolson inverse
-    double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
-                           // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
-    double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
-    double *part;          // deterministic mode: [nblocks][3][ng] per-workgroup deposits,
-                           // summed in workgroup order by k_reduce_partials
-    DevState *st;
-    DevRecord *rec;        // [rec_cap] ring
-    // counting-sort rebin (only when enabled)
-    double *x2, *v2;       // [N_p], [nv][N_p] sorted copy of the state
-    int64_t *id2;          // [N_p] (ids tracked)
-    double *wcur, *w2;     // [N_p] permuted weights (non-uniform weights)
-    int64_t *hist;         // [nbins][nblocks] counts, then offsets
-    int64_t *segsum;       // [nseg] per-segment sums of hist
-};
-
 // ------------------------------------------------------------------ shape functions
 // Cardinal B-spline weights of degree ORDER for a particle at xi = x / h - shift
 // (section 2.2).  first = index of the leftmost node of the ORDER + 1 node stencil.
@@ -405,9 +329,6 @@ __device__ __forceinline__ void coef_fill(double *ct, const double *t, int ng, i
     }
 }
 
-// Offset (in doubles) of the coefficient tiles in the LDS of the passes, kept even so that
-// tent coefficients can be read as pairs.
-__host__ __device__ constexpr int coef_offset(int doubles) { return (doubles + 1) & ~1; }
 
 // Add a workgroup's ghost-padded LDS current tile (ncomp components) into the global
 // current (hardware FP64 atomics); ghost slots go to their periodic nodes, zero entries
@@ -881,9 +802,6 @@ __device__ __forceinline__ double block_mean(const double *a, int n, double *red
     return block_sum(s, red) / n;
 }
 
-// Upper bound on the replicas of the currents: a default launch (256 workgroups) uses 8,
-// and a prologue keeps the replicas of two currents in flight at once.
-constexpr int kMaxRep = 8;
 
 // Component value J[i] summed over nrep <= kMaxRep replicas of stride rs, in replica
 // order; the loads are issued together.
@@ -1205,7 +1123,6 @@ __device__ __forceinline__ void field_energies(const Run &r, const double *E, co
 // The standard scheme (Run::scheme == kStandard) has its fields at half steps: its record
 // of step n >= 1 is TE at (n - 1/2) dt, the mean of the kinetic energies of steps n - 1
 // (slot 4, written by the same pass) and n plus the field energy of E^{n-1/2}.
-constexpr int kStandard = 3;
 
 __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64_t step, double *red)
 {

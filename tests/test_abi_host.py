@@ -236,3 +236,29 @@ def test_deterministic_workspace_holds_partials():
     a = _good(n_particles=1_000_000, n_cells=512)
     b = _good(n_particles=1_000_000, n_cells=512, deterministic=True)
     assert P.workspace_size(b) > P.workspace_size(a) + 200 * 3 * 512 * 8
+
+
+def test_host_input_check_names_the_first_non_finite_value():
+    """pic_check_inputs on host arrays (no GPU): finite inputs pass; a NaN or Inf anywhere in
+    x, v, w, E or B is PIC_ENONFINITE with its array and index; missing arrays are
+    PIC_EINVAL.  Pic.from_arrays runs it before copying anything to the device."""
+    import numpy as np
+    import paper_2411_09605_amd as P
+    import paper_2411_09605_amd.binding as B
+    n, ng = 1000, 32
+    p = P.make_params(3, "emec_li", 2, n, ng, 10.0, 0.1)
+    x, v, w = np.full(n, 0.5), np.zeros((3, n)), np.ones(n)
+    E, Bf = np.zeros((3, ng)), np.zeros((2, ng))
+    assert B.check_inputs(p, x, v, E, Bf, w) == (0, -1)
+    for arr, idx in ((x, 17), (v.reshape(-1), 2 * n + 5), (w, 999), (E.reshape(-1), 64),
+                     (Bf.reshape(-1), 33)):
+        keep = arr[idx]
+        arr[idx] = np.nan if idx % 2 else -np.inf
+        rc, bad = B.check_inputs(p, x, v, E, Bf, w)
+        assert rc == -5 and bad == idx
+        assert "not finite" in P.last_error()
+        arr[idx] = keep
+    assert B.check_inputs(p, x, v, E, None, w)[0] == -1          # EM needs B
+    with pytest.raises(P.PicError) as e:
+        P.Pic.check_host_inputs(1, "esec2", 2, ng, 10.0, 0.1, x, np.array([[np.inf] * n]))
+    assert e.value.status == -5
