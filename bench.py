@@ -52,7 +52,8 @@ def source_digest():
     import hashlib
     h = hashlib.sha256()
     for rel in ("paper_2411_09605_amd/csrc/pic_device.hpp", "paper_2411_09605_amd/csrc/pic_adjoint.hpp",
-                "paper_2411_09605_amd/csrc/pic_lib.hip", "include/pic.h"):
+                "paper_2411_09605_amd/csrc/pic_lib.hip", "paper_2411_09605_amd/csrc/pic_types.hpp",
+                "paper_2411_09605_amd/csrc/pic_host.cpp", "include/pic.h"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
