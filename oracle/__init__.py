@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2}
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "emec_psatd": 4}
 
 
 class OCfg(ctypes.Structure):
@@ -78,6 +78,8 @@ def lib():
                                    ctypes.c_double, dp]
         L.oracle_cn_solve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         L.oracle_energy.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, ctypes.c_void_p]
+        L.oracle_psatd.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -168,6 +170,16 @@ def cn_solve(ng, h, s, r):
     y = np.zeros(ng)
     lib().oracle_cn_solve(ng, h, s, _p(r), _p(y))
     return y
+
+
+def psatd(ng, L, c, tau, E, B, J, average=True):
+    """One PSATD field update over tau with the current held fixed: (E', B', <E> or None)."""
+    E = np.ascontiguousarray(E, dtype=np.float64).reshape(3, ng)
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(2, ng)
+    J = np.ascontiguousarray(J, dtype=np.float64).reshape(3, ng)
+    Eo, Bo, Ea = np.zeros((3, ng)), np.zeros((2, ng)), np.zeros((3, ng))
+    lib().oracle_psatd(ng, L, c, tau, _p(E), _p(B), _p(J), _p(Eo), _p(Bo), _p(Ea) if average else None)
+    return Eo, Bo, (Ea if average else None)
 
 
 def energy(state: State) -> np.void:

@@ -17,6 +17,8 @@
  *   - ESEC1: the first scheme, eq. (naivetranslation) + eq. (PICmodification) with the
  *     closed-form root eq. (opt_solution);
  *   - EMEC(LI): eq. (EMbasic), Crank-Nicolson Maxwell on a staggered 1D grid;
+ *   - EMEC(PSATD): eq. (EM_PSATD), the field update solved exactly in time per Fourier mode
+ *     (eq. (PSATDformula) and its time average) with spectral staggered curls;
  *   - the fallback Gamma := 1 when the root is imaginary (section 3.2), counted;
  *   - total energy of section 5.1.
  * The electrostatic Ampere update is E <- E - dt (j - mean j): in 1D, E = -d(phi)/dx
@@ -24,6 +26,7 @@
  * Sums over particles run in particle index order; energy sums are compensated.
  * No loop is blocked, fused or reordered beyond what the equations say.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -31,7 +34,7 @@
 
 typedef struct {
     int32_t nv;          /* 1 (1D-1V) or 3 (1D-3V)                                  */
-    int32_t scheme;      /* 0 = ESEC2, 1 = ESEC1, 2 = EMEC(LI)                       */
+    int32_t scheme;      /* 0 = ESEC2, 1 = ESEC1, 2 = EMEC(LI), 4 = EMEC(PSATD)      */
     int32_t order;       /* B-spline degree: 1 or 2                                  */
     int32_t n_cells;     /* N_g                                                      */
     int64_t n_particles; /* N_p                                                      */
@@ -239,6 +242,99 @@ void oracle_cn_solve(int ng, double h, double s, const double *r, double *y)
     free(im);
 }
 
+/* ---------------------------------------------- PSATD field solve (EMEC(PSATD) only) */
+
+/* Exact solution over a time tau of the semi-discrete Maxwell system with the current j held
+ * fixed (eq. (PSATDconstruction)), by Fourier mode (eq. (PSATDformula)), and its time
+ * average over [0, tau] (the formula at the end of section 4.2).  In 1D along x the
+ * transverse pairs (E_y, B_z) and (E_z, -B_y) both obey dE/dt = -c^2 D- B - j, dB/dt = -D+ E,
+ * with E, j on the nodes x_i and B on the half nodes x_{i+1/2}; the curls are spectral on the
+ * staggered grid: D+ (nodes -> half nodes) multiplies mode m by a = i k e^{i k h/2}, D- (half
+ * nodes -> nodes) by b = i k e^{-i k h/2}, k = 2 pi m / L with m signed (|m| <= N/2), so that
+ * a b = -k^2.  With w = c |k|, C = cos(w tau), S = sin(w tau):
+ *   E(tau) = C E - c^2 b S/w B - S/w j,
+ *   B(tau) = C B - a S/w E + a (1 - C)/w^2 j,
+ *   <E>    = S/(w tau) E - c^2 b (1 - C)/(w^2 tau) B - (1 - C)/(w^2 tau) j,
+ * and for k = 0: E - tau j, B, E - tau/2 j.  E_x (no curl): E_x - tau j_x, average
+ * E_x - tau/2 j_x.  E, J: [3][ng]; B: [2][ng] (B_y, B_z).  Outputs Eo [3][ng], Bo [2][ng]
+ * and Ea [3][ng] (may be NULL).  Direct O(N^2) transforms. */
+static void dft(int ng, const double *f, double complex *F)
+{
+    for (int m = 0; m < ng; ++m) {
+        double complex acc = 0.0;
+        for (int i = 0; i < ng; ++i) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * i) % ng) / ng;
+            acc += f[i] * cexp(-I * th);
+        }
+        F[m] = acc;
+    }
+}
+
+static void idft(int ng, const double complex *F, double *f)
+{
+    for (int i = 0; i < ng; ++i) {
+        double complex acc = 0.0;
+        for (int m = 0; m < ng; ++m) {
+            double th = 2.0 * M_PI * (double)(((int64_t)m * i) % ng) / ng;
+            acc += F[m] * cexp(I * th);
+        }
+        f[i] = creal(acc) / ng;
+    }
+}
+
+void oracle_psatd(int ng, double L, double c, double tau, const double *E, const double *B,
+                  const double *J, double *Eo, double *Bo, double *Ea)
+{
+    const double h = L / ng, c2 = c * c;
+    double complex *Ef = malloc(sizeof(double complex) * (size_t)ng);
+    double complex *Bf = malloc(sizeof(double complex) * (size_t)ng);
+    double complex *Jf = malloc(sizeof(double complex) * (size_t)ng);
+    double complex *E1 = malloc(sizeof(double complex) * (size_t)ng);
+    double complex *B1 = malloc(sizeof(double complex) * (size_t)ng);
+    double complex *A1 = malloc(sizeof(double complex) * (size_t)ng);
+    double *bneg = malloc(sizeof(double) * (size_t)ng), *tmp = malloc(sizeof(double) * (size_t)ng);
+    for (int i = 0; i < ng; ++i) {
+        Eo[i] = E[i] - tau * J[i];                              /* E_x */
+        if (Ea)
+            Ea[i] = E[i] - 0.5 * tau * J[i];
+    }
+    for (int pair = 0; pair < 2; ++pair) {
+        /* pair 0: (E_y, B_z, j_y); pair 1: (E_z, -B_y, j_z) */
+        const double *e = E + (1 + pair) * ng, *j = J + (1 + pair) * ng;
+        const double *bb = pair == 0 ? B + ng : B;
+        const double sg = pair == 0 ? 1.0 : -1.0;
+        for (int i = 0; i < ng; ++i)
+            bneg[i] = sg * bb[i];
+        dft(ng, e, Ef);
+        dft(ng, bneg, Bf);
+        dft(ng, j, Jf);
+        for (int m = 0; m < ng; ++m) {
+            const int ms = 2 * m <= ng ? m : m - ng;             /* signed mode number */
+            if (ms == 0) {
+                E1[m] = Ef[m] - tau * Jf[m];
+                B1[m] = Bf[m];
+                A1[m] = Ef[m] - 0.5 * tau * Jf[m];
+                continue;
+            }
+            const double k = 2.0 * M_PI * ms / L, w = c * fabs(k);
+            const double complex a = I * k * cexp(I * 0.5 * k * h);
+            const double complex b = I * k * cexp(-I * 0.5 * k * h);
+            const double C = cos(w * tau), S = sin(w * tau);
+            E1[m] = C * Ef[m] - c2 * b * S / w * Bf[m] - S / w * Jf[m];
+            B1[m] = C * Bf[m] - a * S / w * Ef[m] + a * (1.0 - C) / (w * w) * Jf[m];
+            A1[m] = S / (w * tau) * Ef[m] - c2 * b * (1.0 - C) / (w * w * tau) * Bf[m]
+                    - (1.0 - C) / (w * w * tau) * Jf[m];
+        }
+        idft(ng, E1, Eo + (1 + pair) * ng);
+        idft(ng, B1, tmp);
+        for (int i = 0; i < ng; ++i)
+            (pair == 0 ? Bo + ng : Bo)[i] = sg * tmp[i];
+        if (Ea)
+            idft(ng, A1, Ea + (1 + pair) * ng);
+    }
+    free(Ef); free(Bf); free(Jf); free(E1); free(B1); free(A1); free(bneg); free(tmp);
+}
+
 /* Staggered differences: node arrays f[i] at i h, half-node arrays g[i] at (i + 1/2) h.
  * D+ f at half node i: (f[i+1] - f[i]) / h;  D- g at node i: (g[i] - g[i-1]) / h. */
 static double dplus(const double *f, int i, int ng, double h)
@@ -266,11 +362,12 @@ void oracle_energy(const ocfg *cfg, const double *v, const double *w, const doub
             v2 += v[c * np + p] * v[c * np + p];
         nadd(&ke, 0.5 * (w ? w[p] : wu) * v2);
     }
-    int ne = cfg->scheme == 2 ? 3 : 1;
+    const int emf = cfg->scheme == 2 || cfg->scheme == 4;
+    int ne = emf ? 3 : 1;
     for (int c = 0; c < ne; ++c)
         for (int i = 0; i < ng; ++i)
             nadd(&we, 0.5 * h * E[c * ng + i] * E[c * ng + i]);
-    if (cfg->scheme == 2 && B)
+    if (emf && B)
         for (int c = 0; c < 2; ++c)
             for (int i = 0; i < ng; ++i)
                 nadd(&wb, 0.5 * cfg->c * cfg->c * h * B[c * ng + i] * B[c * ng + i]);
@@ -313,7 +410,8 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
     const int ng = cfg->n_cells, nv = cfg->nv, ord = cfg->order, sch = cfg->scheme;
     const double L = cfg->length, h = L / ng, dt = cfg->dt, c2 = cfg->c * cfg->c;
     const double wu = L / (double)np;
-    const int em = sch == 2;
+    const int psatd = sch == 4;
+    const int em = sch == 2 || psatd;
     const int ncur = em ? 3 : 1;                 /* current components that matter */
     double *vx = v;
 
@@ -334,6 +432,9 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
             double m = mean(o->J1, ng);
             for (int i = 0; i < ng; ++i)
                 o->Es[i] = E[i] - 0.5 * dt * (o->J1[i] - m);
+        } else if (psatd) {
+            /* (E*, B*) = PSATD(E^n, B^n, j^{n,*}, dt/2) */
+            oracle_psatd(ng, L, cfg->c, 0.5 * dt, E, B, o->J1, o->Es, o->Bs, NULL);
         } else {
             const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
             const double *By = B, *Bz = B + ng;
@@ -395,7 +496,13 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         oracle_deposit(ord, np, o->xh, o->wv, o->vs + c * np, ng, h, 0.0, o->J2 + c * ng);
 
     /* S8: field update */
-    if (!em) {
+    if (psatd) {
+        /* (E^{n+1}, B^{n+1}) = PSATD(E^n, B^n, j^{*,n+1/2}, dt); the gather for v-dagger takes
+         * the time average <E> over the step; B at n + 1/2 is the mean of B^n and B^{n+1} */
+        oracle_psatd(ng, L, cfg->c, dt, E, B, o->J2, o->En, o->Bn, o->Eb);
+        for (int i = 0; i < 2 * ng; ++i)
+            o->Bb[i] = 0.5 * (B[i] + o->Bn[i]);
+    } else if (!em) {
         double m = mean(o->J2, ng);
         for (int i = 0; i < ng; ++i)
             o->En[i] = E[i] - dt * (o->J2[i] - m);
@@ -513,13 +620,15 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
 /* Validate the configuration: 0 if usable, -1 otherwise. */
 int oracle_check(const ocfg *cfg)
 {
-    if (!cfg || (cfg->nv != 1 && cfg->nv != 3) || cfg->scheme < 0 || cfg->scheme > 2)
+    if (!cfg || (cfg->nv != 1 && cfg->nv != 3) || cfg->scheme < 0 || cfg->scheme > 4)
         return -1;
     if (cfg->order < 1 || cfg->order > 2 || cfg->n_particles < 1)
         return -1;
     if (cfg->n_cells < 2 * cfg->order + 1 || !(cfg->length > 0.0) || !(cfg->dt > 0.0))
         return -1;
-    if (cfg->scheme == 2 && (cfg->nv != 3 || !(cfg->c > 0.0)))
+    if (cfg->scheme == 3 || cfg->scheme > 4)
+        return -1;
+    if ((cfg->scheme == 2 || cfg->scheme == 4) && (cfg->nv != 3 || !(cfg->c > 0.0)))
         return -1;
     return 0;
 }
@@ -640,7 +749,7 @@ static double field_energy(const ocfg *cfg, const double *E)
 int oracle_std_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
                    int64_t nsteps, int filter, int first, odiag *rec)
 {
-    if (oracle_check(cfg) || cfg->scheme == 2)
+    if (oracle_check(cfg) || cfg->scheme == 2 || cfg->scheme == 4)
         return -1;
     const int64_t np = cfg->n_particles;
     const int ng = cfg->n_cells, nv = cfg->nv;

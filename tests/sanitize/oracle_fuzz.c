@@ -44,12 +44,13 @@ int main(void)
     for (int ip = 0; ip < 5; ++ip)
         for (int ig = 0; ig < 5; ++ig)
             for (int order = 1; order <= 2; ++order)
-                for (int scheme = 0; scheme <= 3; ++scheme) {
+                for (int scheme = 0; scheme <= 4; ++scheme) {
                     const int64_t np = nps[ip];
                     const int ng = ngs[ig];
                     if (ng < 2 * order + 1)
                         continue;
-                    const int nv = (scheme == 2 || (ip + ig) % 2) ? 3 : 1;
+                    const int em = scheme == 2 || scheme == 4;
+                    const int nv = (em || (ip + ig) % 2) ? 3 : 1;
                     ocfg c = {nv, scheme == 3 ? 0 : scheme, order, ng, np, 5.0, 0.3, 1.0,
                               {0.0, 0.0, 0.0}};
                     if (nv == 3) {
@@ -73,7 +74,7 @@ int main(void)
                         rc = oracle_std_run(&c, x, v, w, E, 6, ip % 2, 1, rec);
                     else
                         rc = oracle_run_gamma(&c, x, v, (ip % 2) ? w : NULL, E, B, 6,
-                                              scheme != 2, rec, np <= 301 ? g : NULL);
+                                              !em, rec, np <= 301 ? g : NULL);
                     if (rc != 0) {
                         printf("FAILED: oracle rejected scheme %d np %lld ng %d\n", scheme,
                                (long long)np, ng);
