@@ -341,7 +341,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream_1d1v_512c_10M")
-    ap.add_argument("--scheme", default=None, choices=("esec2", "esec1", "emec_li", "standard"),
+    ap.add_argument("--scheme", default=None,
+                    choices=("esec2", "esec1", "emec_li", "emec_psatd", "standard"),
                     help="scheme to run the workload with (default: the workload's own)")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)

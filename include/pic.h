@@ -26,6 +26,16 @@
  *               so the state is read and written once per step.
  *   PIC_EMEC_LI eq. (EMbasic): ESEC2's particle update with the Crank-Nicolson
  *               (linearly implicit) Maxwell update; requires nv == 3.
+ *   PIC_EMEC_PSATD eq. (EM_PSATD), section 4.2: as PIC_EMEC_LI with the Maxwell update
+ *               integrated exactly in time for each Fourier mode with the current held
+ *               fixed over the step (eq. (PSATDformula)): (E*, B*) = PSATD(E^n, B^n,
+ *               j^{n,*}, dt/2) for v*, (E^{n+1}, B^{n+1}) = PSATD(E^n, B^n, j^{*,n+1/2},
+ *               dt), and v-dagger gathers the exact time average of E over the step and
+ *               B^{n+1/2} = (B^n + B^{n+1})/2.  The curls are spectral on the same
+ *               staggered grid (d/dx from nodes to half nodes multiplies mode k by
+ *               i k e^{i k h/2}, back by i k e^{-i k h/2}); E_x has no curl term.  Each
+ *               field update is a fixed-order real-space convolution with rows computed
+ *               once at initialisation.  Requires nv == 3.
  *   PIC_STANDARD the comparison scheme of section 5 (not energy-conserving): Vlasov-Poisson
  *               with the leapfrog/Boris push in its symmetric form, eq. (symm_Boris):
  *               x* = x^n + dt/2 v^n, E^{n+1/2} the Gauss field (spectral, as the initial
@@ -73,7 +83,8 @@ enum pic_status {
     PIC_EUNSUPPORTED = -6    /* valid but outside what this library handles            */
 };
 
-enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2, PIC_STANDARD = 3 };
+enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2, PIC_STANDARD = 3,
+                  PIC_EMEC_PSATD = 4 };
 
 enum pic_flag {
     PIC_F_INIT_GAUSS = 1u,   /* set E_x^0 from the particles: dE/dx = rho - 1 solved
@@ -118,7 +129,7 @@ enum pic_deposit_mode {
 typedef struct {
     int32_t abi_version;   /* must equal PIC_ABI_VERSION                                 */
     int32_t nv;            /* velocity components per particle: 1 or 3                   */
-    int32_t scheme;        /* enum pic_scheme; PIC_EMEC_LI requires nv == 3              */
+    int32_t scheme;        /* enum pic_scheme; the EM schemes require nv == 3            */
     int32_t shape_order;   /* B-spline degree: 1 (tent) or 2 (quadratic)                 */
     int64_t n_particles;   /* N_p >= 1                                                   */
     int32_t n_cells;       /* N_g >= 2 * shape_order + 1                                 */
@@ -127,7 +138,7 @@ typedef struct {
                               unspecified: track identities with PIC_F_TRACK_IDS          */
     double  length;        /* L > 0                                                      */
     double  dt;            /* time step > 0                                              */
-    double  c;             /* speed of light (PIC_EMEC_LI), > 0                          */
+    double  c;             /* speed of light (EM schemes), > 0                           */
     double  b_ext[3];      /* uniform imposed magnetic field added to every gathered B
                               (section 3.2 starts from an externally imposed B); used
                               only when nv == 3                                           */
@@ -154,8 +165,8 @@ typedef struct {
                               PIC_F_TRACK_IDS), may be NULL otherwise                     */
     double  *E;            /* [3][N_g] node field (E_x, E_y, E_z), in/out; the
                               electrostatic schemes use and update E_x only               */
-    double  *B;            /* [2][N_g] half-node field (B_y, B_z), in/out; PIC_EMEC_LI
-                              only, NULL otherwise                                        */
+    double  *B;            /* [2][N_g] half-node field (B_y, B_z), in/out; EM schemes
+                              (PIC_EMEC_LI, PIC_EMEC_PSATD) only, NULL otherwise           */
     void    *workspace;    /* >= pic_workspace_size(params) bytes, 256-byte aligned,
                               caller-owned scratch the library carves up                  */
     size_t   workspace_bytes;
@@ -188,7 +199,7 @@ int pic_validate_params(const pic_params *p);
 
 /* Host-only check of a run's inputs before they are copied to the device (no GPU needed):
  * the parameters as pic_validate_params, then every value of the HOST arrays x [N_p],
- * v [nv][N_p], w [N_p] (may be NULL), E [3][N_g] and B [2][N_g] (PIC_EMEC_LI; may be NULL
+ * v [nv][N_p], w [N_p] (may be NULL), E [3][N_g] and B [2][N_g] (EM schemes; may be NULL
  * otherwise) must be finite.  PIC_ENONFINITE names the first non-finite value (array and
  * index) in pic_last_error(NULL) and stores its index within that array in *bad_index (may
  * be NULL; -1 when nothing is wrong); PIC_EINVAL for NULL x, v, E (or B in EM).  Nothing is
@@ -198,15 +209,16 @@ int pic_check_inputs(const pic_params *p, const double *x, const double *v, cons
 
 /* Bind a context to the caller's buffers and HIP stream (hipStream_t, may be NULL for
  * the null stream) and enqueue the initial work: wrap x into [0, L); optionally the
- * Gauss solve for E_x^0; the energy record of step 0; for ESEC2/EMEC(LI) the predictor
- * deposit j^{0,*} and the predictor fields (eq. (good_translation), (EMbasic)).
+ * Gauss solve for E_x^0; the energy record of step 0; for ESEC2 and the EM schemes the
+ * predictor deposit j^{0,*} (eq. (good_translation), (EMbasic), (EM_PSATD)); for
+ * PIC_EMEC_PSATD also the rows of its field-update convolutions.
  * On success *out receives the context.  The first init on a device (of any form) also
  * checks, with two one-workgroup launches and a wait on the stream, that the runtime
  * passes the workgroup size where the kernels read it; PIC_EUNSUPPORTED if not. */
 int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out);
 
 /* Enqueue n_steps steps (eq. (good_translation) / (naivetranslation)+(PICmodification) /
- * (EMbasic)), each recording a pic_diag.  Asynchronous: returns after enqueueing. */
+ * (EMbasic) / (EM_PSATD) / (symm_Boris)), each recording a pic_diag.  Asynchronous: returns after enqueueing. */
 int pic_step(pic_ctx *ctx, int64_t n_steps);
 
 /* Synchronise the stream and copy out the records written since the previous call (the
@@ -222,7 +234,7 @@ int pic_sync_state(pic_ctx *ctx);
 /* ----------------------------------------------------------- checkpoint / resume
  * The complete state of a run between two steps: positions, velocities, ids (with
  * PIC_F_TRACK_IDS), the library's permuted weights (rebins with non-uniform weights),
- * E^n and B^n, the predictor current j^{n,*} that ESEC2 and EMEC(LI) carry from one step
+ * E^n and B^n, the predictor current j^{n,*} that ESEC2 and the EM schemes carry from one step
  * to the next (eq. (good_translation) with (doublestardef); for ESEC1 the centred current
  * j^{n+1/2} its previous launch deposited), the step number n, the
  * initial total energy, the fallback total, the deposit's fixed-point scales and the
@@ -307,6 +319,7 @@ int pic_run_static(const pic_params *p, const pic_buffers *b, void *hip_stream,
 /* ------------------------------------------------------------ batched ensemble form
  * Many independent runs of one scheme advanced together: each run has its own particle
  * count, cell count and length; all share the scheme, shape order, nv, dt, c and b_ext.
+ * Schemes: ESEC2, ESEC1 and EMEC(LI).
  * Every pass of every step is one persistent launch over a table of work items (chunks of
  * one run's particles), and steps can be replayed from a captured hipGraph.  Each run
  * computes exactly what pic_step computes for it alone (same records, same parity). */

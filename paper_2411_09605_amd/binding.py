@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "standard": 3}
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "standard": 3, "emec_psatd": 4}
+EM_SCHEMES = ("emec_li", 2, "emec_psatd", 4)
 F_INIT_GAUSS, F_TRACK_IDS, F_INTERLEAVE, F_DETERMINISTIC, F_FILTER_RHO = 1, 2, 4, 8, 16
 DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3, "lds_f64": 4}
 ABI_VERSION = 1
@@ -308,7 +309,7 @@ class Pic:
         if E0 is not None:
             Et.copy_(torch.as_tensor(np.asarray(E0, dtype=np.float64).reshape(3, n_cells)))
         Bt = None
-        if scheme in ("emec_li", 2):
+        if scheme in EM_SCHEMES:
             Bt = torch.zeros((2, n_cells), **f64)
             if B0 is not None:
                 Bt.copy_(torch.as_tensor(np.asarray(B0, dtype=np.float64).reshape(2, n_cells)))
@@ -329,7 +330,7 @@ class Pic:
         p = make_params(nv, scheme, order, n, n_cells, length, dt, c=c, b_ext=b_ext,
                         init_gauss=init_gauss, **knobs)
         E = np.zeros((3, n_cells)) if E0 is None else E0
-        B = (np.zeros((2, n_cells)) if B0 is None else B0) if scheme in ("emec_li", 2) else B0
+        B = (np.zeros((2, n_cells)) if B0 is None else B0) if scheme in EM_SCHEMES else B0
         rc, _ = check_inputs(p, x, v, E, B, w)
         _check(rc)
 
@@ -486,7 +487,7 @@ def pack_runs(runs, device="cuda") -> dict:
             [np.asarray(r.w, dtype=np.float64) if r.w is not None
              else np.full(r.n_particles, r.length / r.n_particles) for r in runs])).to(**f64)
     return dict(x=x, v=v, w=w, E=torch.as_tensor(Eh).to(**f64),
-                B=torch.as_tensor(Bh).to(**f64) if r0.scheme == "emec_li" else None,
+                B=torch.as_tensor(Bh).to(**f64) if r0.scheme in EM_SCHEMES else None,
                 np=np_, ng=ng_, len=len_, poff=poff, goff=goff, nv=nv, r0=r0,
                 init_gauss=all(r.init_gauss for r in runs))
 

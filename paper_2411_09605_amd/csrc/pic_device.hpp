@@ -44,6 +44,9 @@ template <int NV> constexpr int kWavesPerEU = NV == 1 ? 6 : 1;
 // Largest workgroup of the particle passes.
 template <int NV> constexpr int kMaxThreads = 1024;
 
+// Run::scheme of the electromagnetic schemes, EMEC(LI) and EMEC(PSATD).
+__host__ __device__ constexpr bool em_scheme(int s) { return s == 2 || s == kPsatd; }
+
 // Threads of the (1-D) workgroup: the group-size field of the implicit kernel arguments
 // (a 16-bit field at byte 12), read with a scalar load of the dword that holds it.
 // blockDim.x also allows for a partial last workgroup, which these launches never have,
@@ -898,6 +901,18 @@ __device__ __forceinline__ void tile_load_ghost(double *tile, const double *src,
     }
 }
 
+// Interiors of the ghost-padded E [3][tw] and B [2][tw] tiles from a field block
+// E [3][ng] | B [2][ng] (EMEC(PSATD)'s ps or pf); the caller fills the ghosts.
+__device__ __forceinline__ void psatd_tiles(const Run &r, const double *src, double *et, double *bt)
+{
+    const int ng = r.ng, tw = r.tw;
+    for (int idx = threadIdx.x; idx < 5 * ng; idx += nthreads()) {
+        const int c = idx / ng, i = idx - c * ng;
+        double *dst = c < 3 ? et + c * tw : bt + (c - 3) * tw;
+        dst[kGhost + i] = src[idx];
+    }
+}
+
 // ------------------------------------------------------------------ grid operations
 // Staggered differences: nodes f[i] at i h, half nodes g[i] at (i + 1/2) h.
 __device__ __forceinline__ double dplus(const double *f, int i, int ng, double inv_h)
@@ -1106,7 +1121,7 @@ __device__ __forceinline__ void esec2_fields_finish(const Run &r, double *es, do
 __device__ __forceinline__ void field_energies(const Run &r, const double *E, const double *B, double *we,
                                double *wb, double *red)
 {
-    const bool em = r.scheme == 2;
+    const bool em = em_scheme(r.scheme);
     const int ng = r.ng, ne = em ? 3 : 1;
     double se = 0.0, sb = 0.0;
     for (int i = threadIdx.x; i < ne * ng; i += nthreads())
@@ -1128,8 +1143,15 @@ __device__ __forceinline__ void write_record(const Run &r, const Work &wk, int64
 {
     const bool half = r.scheme == kStandard && step > 0;
     double ke = 0.0, fb = 0.0, gd = 0.0, nf = 0.0;
+    // The kinetic energy is summed by the first wavefront alone (lane l takes workgroups
+    // l, l + 64, ... in turn, then the fixed wavefront and workgroup reductions, where the
+    // other wavefronts add exact zeros), so the sum does not depend on the size of the
+    // workgroup writing the record: a pass and the end-of-call launch write the same
+    // record.  The other values are exact (integer sums below 2^53, maxima).
+    if (threadIdx.x < 64)
+        for (int b = threadIdx.x; b < r.nblocks; b += 64)
+            ke += half ? 0.5 * (wk.spart[b * kNS + 0] + wk.spart[b * kNS + 4]) : wk.spart[b * kNS + 0];
     for (int b = threadIdx.x; b < r.nblocks; b += nthreads()) {
-        ke += half ? 0.5 * (wk.spart[b * kNS + 0] + wk.spart[b * kNS + 4]) : wk.spart[b * kNS + 0];
         fb += wk.spart[b * kNS + 1];
         gd = fmax(gd, wk.spart[b * kNS + 2]);
         nf = fmax(nf, wk.spart[b * kNS + 3]);
@@ -1283,6 +1305,10 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
         const double part = esec2_predictor_load(r, wk.Ef[par], wk.J1[par], es, ct, r.nrep);
         load_batch(cur, X, V, r.vstride, bcur, p1);
         esec2_predictor_finish(r, es, ct, red, part);
+    } else if (EM && r.scheme == kPsatd) {
+        // E*, B* come from the field launch before this pass
+        psatd_tiles(r, wk.ps, es, bs);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
     } else {
         predictor_fields(r, wk.Ef[par], EM ? wk.Bf[par] : nullptr, wk.J1[par], es, bs, red, r.nrep);
         load_batch(cur, X, V, r.vstride, bcur, p1);
@@ -1400,6 +1426,16 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                                              lead ? wk.grid_save : nullptr);
         load_batch(cur, X, V, r.vstride, bcur, p1);
         esec2_fields_finish(r, es, e1, eb, red, part);
+    } else if (EM && r.scheme == kPsatd) {
+        // E*, B* and <E>, B^{n+1/2} come from the field launches of this step, which have
+        // also published E^{n+1}, B^{n+1}; the lead reads those back for their energies
+        psatd_tiles(r, wk.ps, es, bs);
+        psatd_tiles(r, wk.pf, eb, bb);
+        if (lead) {
+            tile_load(e1, wk.Ef[par ^ 1], 3 * ng);
+            tile_load(b1, wk.Bf[par ^ 1], 2 * ng);
+        }
+        load_batch(cur, X, V, r.vstride, bcur, p1);
     } else {
         predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
         load_batch(cur, X, V, r.vstride, bcur, p1);
@@ -1422,11 +1458,13 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     const double *eg = EM ? es : cts;    // what half_step gathers E* from
     if (lead) {
         // publish E^{n+1} (B^{n+1}) and their energies (pass A clears the next currents)
-        for (int i = threadIdx.x; i < T::ne * ng; i += nthreads())
-            wk.Ef[par ^ 1][i] = e1[i];
-        if constexpr (EM)
-            for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
-                wk.Bf[par ^ 1][i] = b1[i];
+        if (r.scheme != kPsatd) {
+            for (int i = threadIdx.x; i < T::ne * ng; i += nthreads())
+                wk.Ef[par ^ 1][i] = e1[i];
+            if constexpr (EM)
+                for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
+                    wk.Bf[par ^ 1][i] = b1[i];
+        }
         double we, wb;
         field_energies(r, e1, b1, &we, &wb, red);
         if (threadIdx.x == 0) {
@@ -1981,7 +2019,7 @@ __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step,
         write_record(r, wk, step, red);
     for (int i = threadIdx.x; i < 3 * r.ng; i += nthreads())
         wk.E[i] = wk.Ef[par][i];
-    if (r.scheme == 2)
+    if (em_scheme(r.scheme))
         for (int i = threadIdx.x; i < 2 * r.ng; i += nthreads())
             wk.B[i] = wk.Bf[par][i];
 }
@@ -2402,13 +2440,156 @@ __device__ void cn_init_body(const Run &r, const Work &wk)
 
 __global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk) { cn_init_body(r, wk); }
 
+// ------------------------------------------------------------------- EMEC(PSATD)
+// Field update of EMEC(PSATD) (section 4.2): the semi-discrete Maxwell system with the
+// current held fixed, dE/dt = c^2 curl B - j, dB/dt = -curl E, integrated exactly over a
+// time tau for each Fourier mode (eq. (PSATDformula)), and the time average of E over the
+// step (its time integral).  In 1D the transverse pairs (E_y, B_z) and (E_z, -B_y) both
+// obey dE/dt = -c^2 D- B - j, dB/dt = -D+ E with E, j on the nodes and B on the half
+// nodes; the curls are spectral on this staggered grid: D+ (nodes to half nodes)
+// multiplies mode k by a = i k e^{i k h/2}, D- (half nodes to nodes) by
+// b = i k e^{-i k h/2}, so that a b = -k^2.  With w = c |k|, C = cos(w tau),
+// S = sin(w tau) and 1 - C = 2 sin^2(w tau / 2):
+//   E(tau) = C E - c^2 b S/w B - S/w j,   B(tau) = C B - a S/w E + a (1 - C)/w^2 j,
+//   <E>    = S/(w tau) E - c^2 b (1 - C)/(w^2 tau) B - (1 - C)/(w^2 tau) j,
+// and mode 0: E - tau j, B, E - tau/2 j.  Each map is a circulant convolution in real
+// space, out_i = sum_j K[(i - j) mod N] in_j, whose row K[d] = (1/N) Re sum_m K(m)
+// e^{2 pi i m d / N} (m signed, |m| <= N/2; every symbol is real at the Nyquist mode)
+// is computed once here: grid (ceil(N / blockDim), kPsatdRows).
+__device__ __forceinline__ void psatd_symbol(const Run &r, int row, int ms, double &sr, double &si)
+{
+    const bool full = row >= kRowC2;
+    const double tau = full ? r.dt : r.hdt;
+    if (ms == 0) {
+        sr = (row == kRowC1 || row == kRowC2 || row == kRowAE) ? 1.0
+             : (row == kRowEJ1 || row == kRowEJ2) ? -tau
+             : row == kRowAJ ? -0.5 * tau : 0.0;
+        si = 0.0;
+        return;
+    }
+    const double k = 2.0 * M_PI * (double)ms / r.L;
+    const double w = sqrt(r.c2) * fabs(k);
+    double sh, ch;                       // e^{i k h/2} = ch + i sh, k h/2 = pi ms / N
+    sincospi((double)ms / r.ng, &sh, &ch);
+    double S, C;
+    sincos(w * tau, &S, &C);
+    const double sh2 = sin(0.5 * w * tau);
+    const double omc = 2.0 * sh2 * sh2;  // 1 - C
+    // a = i k e^{i k h/2} = k (-sh + i ch),  b = i k e^{-i k h/2} = k (sh + i ch)
+    switch (row) {
+    case kRowC1: case kRowC2: sr = C; si = 0.0; break;
+    case kRowEB1: case kRowEB2: sr = -r.c2 * S / w * k * sh; si = -r.c2 * S / w * k * ch; break;
+    case kRowEJ1: case kRowEJ2: sr = -S / w; si = 0.0; break;
+    case kRowBE1: case kRowBE2: sr = S / w * k * sh; si = -S / w * k * ch; break;
+    case kRowBJ1: case kRowBJ2: sr = -omc / (w * w) * k * sh; si = omc / (w * w) * k * ch; break;
+    case kRowAE: sr = S / (w * tau); si = 0.0; break;
+    case kRowAB: sr = -r.c2 * omc / (w * w * tau) * k * sh; si = -r.c2 * omc / (w * w * tau) * k * ch; break;
+    default: sr = -omc / (w * w * tau); si = 0.0; break;   // kRowAJ
+    }
+}
+
+__global__ __launch_bounds__(256) void k_psatd_rows(Run r, Work wk)
+{
+    extern __shared__ double sym[];      // [2][ng]: the row's symbol, real and imaginary
+    const int ng = r.ng, row = blockIdx.y;
+    for (int m = threadIdx.x; m < ng; m += nthreads()) {
+        const int ms = 2 * m <= ng ? m : m - ng;
+        psatd_symbol(r, row, ms, sym[m], sym[ng + m]);
+    }
+    __syncthreads();
+    const int d = blockIdx.x * nthreads() + threadIdx.x;
+    if (d >= ng)
+        return;
+    double acc = 0.0;
+    for (int m = 0; m < ng; ++m) {
+        double sn, cs;
+        const long long q = ((long long)m * d) % ng;
+        sincospi(2.0 * (double)q / ng, &sn, &cs);
+        acc += sym[m] * cs - sym[ng + m] * sn;
+    }
+    wk.prow[(size_t)row * ng + d] = acc / ng;
+}
+
+// One PSATD field update.  full = 0: the predictor (E*, B*) = PSATD(E^n, B^n, j^{n,*},
+// dt/2) into ps (eq. (EM_PSATD), second line); full = 1: (E^{n+1}, B^{n+1}) =
+// PSATD(E^n, B^n, j^{*,n+1/2}, dt) into Ef[par ^ 1], Bf[par ^ 1], and into pf the time
+// average <E> over the step and B^{n+1/2} = (B^n + B^{n+1})/2 that pass B gathers.
+// Grid (ceil(N / blockDim), nq): blockIdx.y picks the pair p and the output o (predictor:
+// q = 2 p + o, o = E, B; full: q = 3 p + o, o = E, B, <E>); each thread one node.  The
+// sums run over j in increasing order (no atomics), so the update is reproducible.
+// E_x has no curl term: E_x - tau j_x (average E_x - tau/2 j_x), written by q = 0.
+// LDS: e | B (signed) | j | the three rows [6][N].
+__global__ __launch_bounds__(256) void k_psatd_fields(Run r, Work wk, int par, int full)
+{
+    extern __shared__ double sm[];
+    const int ng = r.ng, rs = 3 * ng, q = blockIdx.y;
+    const int p = full ? q / 3 : q >> 1, o = full ? q % 3 : q & 1;
+    const double *E = wk.Ef[par], *B = wk.Bf[par], *J = full ? wk.J2[par] : wk.J1[par];
+    const int bc = p == 0 ? 1 : 0;       // pair 0: B_z, pair 1: B_y (taken as -B_y)
+    const double sg = p == 0 ? 1.0 : -1.0;
+    double *e = sm, *b = sm + ng, *jj = sm + 2 * ng, *k0 = sm + 3 * ng, *k1 = sm + 4 * ng,
+           *k2 = sm + 5 * ng;
+    int r0, r1, r2;
+    if (o == 0) {
+        r0 = full ? kRowC2 : kRowC1; r1 = full ? kRowEB2 : kRowEB1; r2 = full ? kRowEJ2 : kRowEJ1;
+    } else if (o == 1) {
+        r0 = full ? kRowBE2 : kRowBE1; r1 = full ? kRowC2 : kRowC1; r2 = full ? kRowBJ2 : kRowBJ1;
+    } else {
+        r0 = kRowAE; r1 = kRowAB; r2 = kRowAJ;
+    }
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
+        e[i] = E[(1 + p) * ng + i];
+        b[i] = sg * B[bc * ng + i];
+        jj[i] = rep_sum(J, (1 + p) * ng + i, r.nrep, rs);
+        k0[i] = wk.prow[(size_t)r0 * ng + i];
+        k1[i] = wk.prow[(size_t)r1 * ng + i];
+        k2[i] = wk.prow[(size_t)r2 * ng + i];
+    }
+    __syncthreads();
+    const int i = blockIdx.x * nthreads() + threadIdx.x;
+    if (i >= ng)
+        return;
+    double acc = 0.0;
+    for (int j = 0; j < ng; ++j) {
+        int k = i - j;
+        k += k < 0 ? ng : 0;
+        acc = fma(k0[k], e[j], acc);
+        acc = fma(k1[k], b[j], acc);
+        acc = fma(k2[k], jj[j], acc);
+    }
+    if (!full) {
+        if (o == 0)
+            wk.ps[(1 + p) * ng + i] = acc;
+        else
+            wk.ps[(3 + bc) * ng + i] = sg * acc;
+    } else if (o == 0) {
+        wk.Ef[par ^ 1][(1 + p) * ng + i] = acc;
+    } else if (o == 1) {
+        const double bn = sg * acc;
+        wk.Bf[par ^ 1][bc * ng + i] = bn;
+        wk.pf[(3 + bc) * ng + i] = 0.5 * (B[bc * ng + i] + bn);
+    } else {
+        wk.pf[(1 + p) * ng + i] = acc;
+    }
+    if (q == 0) {
+        const double ex = E[i], jx = rep_sum(J, i, r.nrep, rs);
+        if (full) {
+            wk.Ef[par ^ 1][i] = ex - r.dt * jx;
+            wk.pf[i] = ex - r.hdt * jx;
+        } else {
+            wk.ps[i] = ex - r.hdt * jx;
+        }
+    }
+}
+
+
 // Initial fields into the parity-0 buffers and the record of step 0 (one workgroup).
 __device__ void init_finish_body(const Run &r, const Work &wk, double *red)
 {
     const int ng = r.ng;
     for (int i = threadIdx.x; i < 3 * ng; i += nthreads())
         wk.Ef[0][i] = wk.E[i];
-    if (r.scheme == 2)
+    if (em_scheme(r.scheme))
         for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
             wk.Bf[0][i] = wk.B[i];
     double we, wb;

@@ -52,6 +52,7 @@ bool is_std(const pic_params *p) { return p->scheme == PIC_STANDARD; }
 
 struct Layout {
     size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, part, st, rec;
+    size_t prow, ps, pf;                            // EMEC(PSATD) (0 when unused)
     size_t x2, v2, id2, wcur, w2, hist, segsum;     // rebin (0 when unused)
     size_t total;
 };
@@ -87,7 +88,9 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
     return (int)nb;
 }
 
-bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI; }
+bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI || p->scheme == PIC_EMEC_PSATD; }
+
+bool is_psatd(const pic_params *p) { return p->scheme == PIC_EMEC_PSATD; }
 
 // LDS bytes of the largest kernel of this configuration.
 size_t tile_width(const pic_params *p) { return (size_t)p->n_cells + 2 * kGhost; }
@@ -128,6 +131,9 @@ size_t lds_std_pass_of(int order, size_t ng)
 
 size_t lds_std_field_of(size_t ng) { return 4 * ng * 8; }
 
+// EMEC(PSATD)'s field launch (k_psatd_fields): one pair's E, B and j and three rows
+size_t lds_psatd_of(size_t ng) { return 6 * ng * 8; }
+
 size_t lds_pass_a(const pic_params *p) { return lds_pass_a_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
 
 size_t lds_deposit(const pic_params *p) { return 2 * (is_em(p) ? 3 : 1) * tile_width(p) * 8; }
@@ -143,6 +149,8 @@ size_t lds_need(const pic_params *p)
                                       lds_std_field_of((size_t)p->n_cells))
                            : std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
+    if (is_psatd(p))
+        m = std::max(m, lds_psatd_of((size_t)p->n_cells));
     m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
         m = std::max(m, lds_rebin(p));
@@ -204,6 +212,9 @@ Layout layout_of(const pic_params *p)
         L.J2[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
     }
     L.cninv = take(ng * 8);
+    L.prow = is_psatd(p) ? take((size_t)kPsatdRows * ng * 8) : 0;
+    L.ps = is_psatd(p) ? take(5 * ng * 8) : 0;
+    L.pf = is_psatd(p) ? take(5 * ng * 8) : 0;
     // two arrays of per-workgroup scalars (the one-pass ESEC1 alternates between them)
     L.spart = take(2 * (size_t)blocks_of(p, nullptr) * kNS * 8);
     L.part = is_det(p) ? take((size_t)blocks_of(p, nullptr) * 3 * ng * 8) : 0;
@@ -254,14 +265,14 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "abi_version %d != %d", p->abi_version, PIC_ABI_VERSION);
     if (p->nv != 1 && p->nv != 3)
         return fail(err, PIC_EINVAL, "nv must be 1 or 3 (got %d)", p->nv);
-    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_STANDARD)
+    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_EMEC_PSATD)
         return fail(err, PIC_EINVAL, "unknown scheme %d", p->scheme);
     if (p->scheme == PIC_STANDARD && !(p->flags & PIC_F_INIT_GAUSS))
         return fail(err, PIC_EINVAL, "PIC_STANDARD needs PIC_F_INIT_GAUSS (its field comes from the density)");
     if ((p->flags & PIC_F_FILTER_RHO) && p->scheme != PIC_STANDARD)
         return fail(err, PIC_EINVAL, "PIC_F_FILTER_RHO is for PIC_STANDARD only");
-    if (p->scheme == PIC_EMEC_LI && p->nv != 3)
-        return fail(err, PIC_EINVAL, "PIC_EMEC_LI needs nv == 3");
+    if (is_em(p) && p->nv != 3)
+        return fail(err, PIC_EINVAL, "the electromagnetic schemes need nv == 3");
     if (p->shape_order != 1 && p->shape_order != 2)
         return fail(err, PIC_EINVAL, "shape_order must be 1 or 2 (got %d)", p->shape_order);
     if (p->n_particles < 1)
@@ -274,8 +285,8 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "length must be finite and > 0");
     if (!(p->dt > 0.0) || !std::isfinite(p->dt))
         return fail(err, PIC_EINVAL, "dt must be finite and > 0");
-    if (p->scheme == PIC_EMEC_LI && (!(p->c > 0.0) || !std::isfinite(p->c)))
-        return fail(err, PIC_EINVAL, "c must be finite and > 0 for PIC_EMEC_LI");
+    if (is_em(p) && (!(p->c > 0.0) || !std::isfinite(p->c)))
+        return fail(err, PIC_EINVAL, "c must be finite and > 0 for the electromagnetic schemes");
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(p->b_ext[i]))
             return fail(err, PIC_EINVAL, "b_ext must be finite");
@@ -331,7 +342,7 @@ int pic_check_inputs(const pic_params *p, const double *x, const double *v, cons
     if (!x || !v || !E)
         return fail(nullptr, PIC_EINVAL, "x, v and E must be non-NULL");
     if (is_em(p) && !B)
-        return fail(nullptr, PIC_EINVAL, "B must be non-NULL for PIC_EMEC_LI");
+        return fail(nullptr, PIC_EINVAL, "B must be non-NULL for the electromagnetic schemes");
     struct Array {
         const char *name;
         const double *a;

@@ -144,6 +144,15 @@ void launch_std_field(pic_ctx *c, int64_t n)
                           (int)c->run.filter_rho);
 }
 
+// EMEC(PSATD)'s field launch of step n (par = n & 1): full = 0 the predictor fields
+// (before pass A), full = 1 the new fields and the averages pass B gathers (before pass B).
+void launch_psatd(pic_ctx *c, int par, int full)
+{
+    const int ng = c->p.n_cells;
+    hipLaunchKernelGGL(k_psatd_fields, dim3((unsigned)((ng + 255) / 256), full ? 6u : 4u), dim3(256),
+                       (uint32_t)lds_psatd_of((size_t)ng), c->stream, c->run, c->wk, par, full);
+}
+
 template <int ORDER, int NV, int DEP>
 void launch_esec1(pic_ctx *c, int64_t n, const double *X, const double *V)
 {
@@ -301,6 +310,9 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
         w.J2[k] = (double *)(ws + L.J2[k]);
     }
     w.cninv = (double *)(ws + L.cninv);
+    w.prow = L.prow ? (double *)(ws + L.prow) : nullptr;
+    w.ps = L.ps ? (double *)(ws + L.ps) : nullptr;
+    w.pf = L.pf ? (double *)(ws + L.pf) : nullptr;
     w.grid_save = nullptr;
     w.spart = (double *)(ws + L.spart);
     w.part = L.part ? (double *)(ws + L.part) : nullptr;
@@ -456,7 +468,7 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
     if (!b->x || !b->v || !b->E)
         return fail(nullptr, PIC_EINVAL, "x, v and E must be non-NULL");
     if (is_em(p) && !b->B)
-        return fail(nullptr, PIC_EINVAL, "B must be non-NULL for PIC_EMEC_LI");
+        return fail(nullptr, PIC_EINVAL, "B must be non-NULL for the electromagnetic schemes");
     if ((p->flags & PIC_F_TRACK_IDS) && !b->id)
         return fail(nullptr, PIC_EINVAL, "PIC_F_TRACK_IDS needs an id array");
     if ((uintptr_t)b->workspace % kAlign)
@@ -512,7 +524,10 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
     }
-    if (is_em(p))
+    if (is_psatd(p))
+        hipLaunchKernelGGL(k_psatd_rows, dim3((unsigned)((p->n_cells + 255) / 256), kPsatdRows), dim3(256),
+                           2 * p->n_cells * 8, c->stream, r, w);
+    else if (is_em(p))
         hipLaunchKernelGGL(k_cn_init, dim3(1), dim3(gt), 0, c->stream, r, w);
     if (p->scheme != PIC_ESEC1)
         dispatch(c, D_PREDEPOSIT);
@@ -557,10 +572,15 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
                 dispatch(c, D_STD_PASS, par, n, X, V);
             }
         } else {
+            const bool psatd = is_psatd(&c->p);
+            if (psatd)
+                launch_psatd(c, par, 0);
             {
                 Timer t(c, PIC_K_PASS_A, true);
                 dispatch(c, D_PASS_A, par, n, X, V);
             }
+            if (psatd)
+                launch_psatd(c, par, 1);
             {
                 Timer t(c, PIC_K_PASS_B, true);
                 dispatch(c, D_PASS_B, par, n, X, V);
@@ -1073,8 +1093,8 @@ int batch_validate(const pic_batch_params *p)
         return fail(nullptr, PIC_EINVAL, "n_runs >= 1 and the per-run arrays are required");
     if (p->flags & ~(uint32_t)PIC_BF_INIT_GAUSS)
         return fail(nullptr, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
-    if (p->scheme == PIC_STANDARD)
-        return fail(nullptr, PIC_EUNSUPPORTED, "the batched form runs the energy-conserving schemes");
+    if (p->scheme == PIC_STANDARD || p->scheme == PIC_EMEC_PSATD)
+        return fail(nullptr, PIC_EUNSUPPORTED, "the batched form runs ESEC2, ESEC1 and EMEC(LI)");
     if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > kBatchMaxThreads))
         return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, %d]", kBatchMaxThreads);
     if (p->chunk < 0 || p->chunk % batch_threads(p))

@@ -19,8 +19,21 @@ constexpr int kVBins = 2;        // rebin key: cell x sign of v_x
 // and a prologue keeps the replicas of two currents in flight at once.
 constexpr int kMaxRep = 8;
 
-// Run::scheme of the standard explicit scheme (section 5's comparison scheme).
+// Run::scheme of the standard explicit scheme (section 5's comparison scheme) and of
+// EMEC(PSATD) (section 4.2).
 constexpr int kStandard = 3;
+constexpr int kPsatd = 4;
+
+// EMEC(PSATD)'s convolution rows (Work::prow), [kPsatdRows][ng]: for the predictor update
+// over dt/2 (tau1) and the full update over dt (tau2), the rows that map E (node), -B or
+// B (half node) and j (node) of one transverse pair to the new E and B, then the rows of
+// the time average of E over the full step.
+enum PsatdRow {
+    kRowC1 = 0, kRowEB1, kRowEJ1, kRowBE1, kRowBJ1,     // tau1 = dt/2
+    kRowC2, kRowEB2, kRowEJ2, kRowBE2, kRowBJ2,         // tau2 = dt
+    kRowAE, kRowAB, kRowAJ,                             // time average over dt
+    kPsatdRows
+};
 
 // Offset (in doubles) of the coefficient tiles in the LDS of the passes, kept even so that
 // tent coefficients can be read as pairs.
@@ -56,7 +69,8 @@ struct Run {
     int32_t nblocks;       // workgroups of the particle passes
     int32_t rec_cap;
     int64_t chunk;         // particles per workgroup
-    int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI), 3 standard (kStandard)
+    int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI), 3 standard (kStandard),
+                           // 4 EMEC(PSATD) (kPsatd)
     int32_t tw;            // LDS tile width: ng + 2 kGhost
     int32_t nrep;          // replicas of the current accumulators (see Work::J1)
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
@@ -82,6 +96,10 @@ struct Work {
     double *J1[2];         // [nrep][3][ng] predictor current j^{n,*} (J1[n & 1])
     double *J2[2];         // [nrep][3][ng] centred current j^{*,n+1/2} (J2[n & 1])
     double *cninv;         // [ng] first row of the Crank-Nicolson inverse
+    // EMEC(PSATD) only (else null): the convolution rows, the predictor fields
+    // E*[3][ng] | B*[2][ng] of the current step, and the time-averaged E [3][ng] |
+    // B^{n+1/2} [2][ng] that pass B gathers
+    double *prow, *ps, *pf;
     double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
                            // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state

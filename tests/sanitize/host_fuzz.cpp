@@ -47,7 +47,7 @@ int main()
         p.abi_version = (k % 50 == 0) ? 7 : PIC_ABI_VERSION;
         const int32_t nvs[] = {1, 3, 1, 3, 2, 0};
         p.nv = pick(nvs);
-        const int32_t schemes[] = {0, 1, 2, 3, 0, 1, 4, -1};
+        const int32_t schemes[] = {0, 1, 2, 3, 4, 1, 5, -1};
         p.scheme = pick(schemes);
         const int32_t orders[] = {1, 2, 1, 2, 0, 3};
         p.shape_order = pick(orders);
@@ -75,8 +75,8 @@ int main()
         if (k % 2 == 0) {
             // mostly valid: small runs of every scheme, whose inputs are then checked
             p.abi_version = PIC_ABI_VERSION;
-            p.scheme = (int32_t)(rng() % 4);
-            p.nv = (p.scheme == PIC_EMEC_LI || rng() % 2) ? 3 : 1;
+            p.scheme = (int32_t)(rng() % 5);
+            p.nv = (p.scheme == PIC_EMEC_LI || p.scheme == PIC_EMEC_PSATD || rng() % 2) ? 3 : 1;
             p.shape_order = 1 + (int32_t)(rng() % 2);
             p.n_particles = 1 + (int64_t)(rng() % 2000);
             p.n_cells = 2 * p.shape_order + 1 + (int32_t)(rng() % 300);
@@ -102,7 +102,7 @@ int main()
         // host input check on small finite arrays, then with one non-finite value
         std::vector<double> x(p.n_particles, 0.5), v((size_t)p.nv * p.n_particles, -0.25),
             w(p.n_particles, 1.0), E(3 * (size_t)p.n_cells, 0.0), B(2 * (size_t)p.n_cells, 0.0);
-        const bool em = p.scheme == PIC_EMEC_LI;
+        const bool em = p.scheme == PIC_EMEC_LI || p.scheme == PIC_EMEC_PSATD;
         int64_t bad = 7;
         expect(pic_check_inputs(&p, x.data(), v.data(), w.data(), E.data(), em ? B.data() : nullptr,
                                 &bad) == PIC_OK && bad == -1, "finite inputs pass", k);

@@ -62,7 +62,10 @@ def test_validation_accepts_and_sizes():
                dict(nv=3, scheme="emec_li", n_cells=256, deterministic=True),
                dict(scheme="standard", init_gauss=True),
                dict(scheme="standard", init_gauss=True, filter_rho=True, nv=3),
-               dict(scheme="standard", init_gauss=True, deterministic=True)]:
+               dict(scheme="standard", init_gauss=True, deterministic=True),
+               dict(nv=3, scheme="emec_psatd", n_cells=256),
+               dict(nv=3, scheme="emec_psatd", n_cells=3, shape_order=1),
+               dict(nv=3, scheme="emec_psatd", n_cells=256, deterministic=True)]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
@@ -73,7 +76,8 @@ def test_validation_lds_limits():
     for the kernels' static LDS)."""
     import paper_2411_09605_amd as P
     for kw in [dict(n_cells=1842), dict(shape_order=1, n_cells=2254),
-               dict(nv=3, scheme="emec_li", n_cells=697)]:
+               dict(nv=3, scheme="emec_li", n_cells=697),
+               dict(nv=3, scheme="emec_psatd", n_cells=697)]:
         assert P.validate(_good(**kw)) == 0, (kw, P.last_error())
 
 
@@ -95,7 +99,10 @@ def test_validation_lds_limits():
     (dict(deterministic=True, deposit_mode="lds_f64"), -1),
     (dict(scheme="standard"), -1),                        # needs PIC_F_INIT_GAUSS
     (dict(filter_rho=True, init_gauss=True), -1),         # filter: standard scheme only
-    (dict(scheme=4, init_gauss=True), -1),
+    (dict(scheme=5), -1), (dict(nv=1, scheme="emec_psatd"), -1),
+    (dict(nv=3, scheme="emec_psatd", c=0.0), -1), (dict(nv=3, scheme="emec_psatd", c=float("inf")), -1),
+    (dict(nv=3, scheme="emec_psatd", n_cells=698), -6),
+    (dict(nv=3, scheme="emec_psatd", filter_rho=True), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P
@@ -158,6 +165,7 @@ def test_batch_validation_accepts_and_sizes():
     dict(n_particles=[1000, 0, 5]), dict(length=[10.0, -1.0, 1.0]), dict(chunk=100),
     dict(block_threads=96), dict(graph_steps=-1), dict(nv=1, scheme="emec_li"),
     dict(n_cells=[64, 3, 100000]), dict(dt=float("inf")), dict(scheme="standard"),
+    dict(nv=3, scheme="emec_psatd"),
 ])
 def test_batch_validation_rejects(kw):
     import paper_2411_09605_amd.binding as B

@@ -47,10 +47,11 @@ def _cases():
     em.B0 *= 50.0
     return [("two-stream 3e5 x 256", ts, {}), ("weibel 1e5 x 128", em, {}),
             ("two-stream interleaved", ts, dict(interleave=True)),
-            ("two-stream esec1 (one pass)", ts, dict(scheme="esec1"))]
+            ("two-stream esec1 (one pass)", ts, dict(scheme="esec1")),
+            ("weibel 1e5 x 128 emec_psatd", em, dict(scheme="emec_psatd"))]
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_deterministic_runs_are_bit_identical(k):
     from paper_2411_09605_amd import Pic
     name, wl, kn = _cases()[k]
@@ -85,7 +86,7 @@ def test_deterministic_matches_default_and_oracle(k):
     gu.compare_state(gdet.state(), _O, wl.length, vscale, em, tol=1e-12, where="det vs default")
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_resume_is_bit_identical_in_deterministic_mode(k):
     from paper_2411_09605_amd import Pic
     name, wl, kn = _cases()[k]
