@@ -902,7 +902,7 @@ __device__ __forceinline__ void tile_load_ghost(double *tile, const double *src,
 }
 
 // Interiors of the ghost-padded E [3][tw] and B [2][tw] tiles from a field block
-// E [3][ng] | B [2][ng] (EMEC(PSATD)'s ps or pf); the caller fills the ghosts.
+// E [3][ng] | B [2][ng] (Work::ps or Work::pf); the caller fills the ghosts.
 __device__ __forceinline__ void psatd_tiles(const Run &r, const double *src, double *et, double *bt)
 {
     const int ng = r.ng, tw = r.tw;
@@ -962,7 +962,8 @@ __device__ __forceinline__ void predictor_fields(const Run &r, const double *E, 
 
 // Field update from the centred current J (global): new fields into e1 [ne][ng] and
 // b1 [2][ng] (LDS), averaged fields into the interiors of the tiles eb [ne][tw],
-// bb [2][tw] (the caller fills the ghosts).
+// bb [2][tw] (the caller fills the ghosts).  Electromagnetic single runs take these from
+// the field launch (k_em_fields) instead; the batched form solves them here.
 //   ES: E^{n+1} = E^n - dt (j - mean j)                    (eq. (ampere) in 1D)
 //   EM (a = dt/2, s = a^2 c^2, L_h = D-D+), eq. (EMbasic) with Crank-Nicolson:
 //     (I - s L_h) E_y' = (I + s L_h) E_y - dt c^2 D-B_z - dt j_y,  B_z' = B_z - a D+(E_y + E_y')
@@ -1426,10 +1427,15 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                                              lead ? wk.grid_save : nullptr);
         load_batch(cur, X, V, r.vstride, bcur, p1);
         esec2_fields_finish(r, es, e1, eb, red, part);
-    } else if (EM && r.scheme == kPsatd) {
-        // E*, B* and <E>, B^{n+1/2} come from the field launches of this step, which have
-        // also published E^{n+1}, B^{n+1}; the lead reads those back for their energies
-        psatd_tiles(r, wk.ps, es, bs);
+    } else if (EM && r.em_fields) {
+        // the fields v-dagger gathers come from the field launch before this pass, which
+        // has also published E^{n+1}, B^{n+1} (the lead reads those back for their
+        // energies); E*, B* from the predictor launch (PSATD) or, for the local LI
+        // predictor, as in pass A
+        if (r.scheme == kPsatd)
+            psatd_tiles(r, wk.ps, es, bs);
+        else
+            predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
         psatd_tiles(r, wk.pf, eb, bb);
         if (lead) {
             tile_load(e1, wk.Ef[par ^ 1], 3 * ng);
@@ -1458,7 +1464,7 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
     const double *eg = EM ? es : cts;    // what half_step gathers E* from
     if (lead) {
         // publish E^{n+1} (B^{n+1}) and their energies (pass A clears the next currents)
-        if (r.scheme != kPsatd) {
+        if (!(EM && r.em_fields)) {
             for (int i = threadIdx.x; i < T::ne * ng; i += nthreads())
                 wk.Ef[par ^ 1][i] = e1[i];
             if constexpr (EM)
@@ -2421,7 +2427,8 @@ __global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
 }
 
 // First row of (I - s L_h)^{-1} for the periodic 3-point Laplacian: circulant, so
-// g_k = (1/N) sum_m cos(2 pi m k / N) / (1 + s (4/h^2) sin^2(pi m / N)).
+// g_k = (1/N) sum_m cos(2 pi m k / N) / (1 + s (4/h^2) sin^2(pi m / N)).  Used by the
+// batched form, whose pass B solves Crank-Nicolson in its prologue (field_update).
 __device__ void cn_init_body(const Run &r, const Work &wk)
 {
     const int ng = r.ng;
@@ -2438,10 +2445,10 @@ __device__ void cn_init_body(const Run &r, const Work &wk)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_cn_init(Run r, Work wk) { cn_init_body(r, wk); }
 
 // ------------------------------------------------------------------- EMEC(PSATD)
-// Field update of EMEC(PSATD) (section 4.2): the semi-discrete Maxwell system with the
+// Field updates of the electromagnetic schemes as real-space convolutions.
+// EMEC(PSATD) (section 4.2): the semi-discrete Maxwell system with the
 // current held fixed, dE/dt = c^2 curl B - j, dB/dt = -curl E, integrated exactly over a
 // time tau for each Fourier mode (eq. (PSATDformula)), and the time average of E over the
 // step (its time integral).  In 1D the transverse pairs (E_y, B_z) and (E_z, -B_y) both
@@ -2488,13 +2495,53 @@ __device__ __forceinline__ void psatd_symbol(const Run &r, int row, int ms, doub
     }
 }
 
-__global__ __launch_bounds__(256) void k_psatd_rows(Run r, Work wk)
+// The same rows for EMEC(LI) (eq. (EMbasic) with Crank-Nicolson), from the symbols of the
+// staggered differences, D+ -> a = (e^{i k h} - 1)/h and D- -> b = (1 - e^{-i k h})/h, with
+// lambda = s a b = -4 s sin^2(k h/2)/h^2 (s = (dt/2)^2 c^2) and d = 1 - lambda:
+//   predictor (explicit half step): E* = E - dt/2 c^2 b B - dt/2 j, B* = B - dt/2 a E;
+//   full step: E' = (1 + lambda)/d E - dt c^2 b/d B - dt/d j,
+//              B' = B - dt/2 a (E + E') = (1 + lambda)/d B - dt a/d E + dt^2 a/(2 d) j;
+//   average (E + E')/2 = E/d - dt c^2 b/(2 d) B - dt/(2 d) j.
+__device__ __forceinline__ void cn_symbol(const Run &r, int row, int ms, double &sr, double &si)
+{
+    double st, ct, sh;                   // sin, cos of k h = 2 pi ms / N; sin(k h/2)
+    sincospi(2.0 * (double)ms / r.ng, &st, &ct);
+    sh = sinpi((double)ms / r.ng);
+    const double omc = 2.0 * sh * sh;    // 1 - cos(k h)
+    // a = (-omc + i st)/h,  b = (omc + i st)/h
+    const double ar = -omc * r.inv_h, ai = st * r.inv_h, br = omc * r.inv_h, bi = st * r.inv_h;
+    const double s = r.hdt * r.hdt * r.c2;
+    const double lam = -4.0 * s * sh * sh * r.inv_h * r.inv_h, d = 1.0 - lam;
+    const double dt = r.dt;
+    switch (row) {
+    case kRowC1: sr = 1.0; si = 0.0; break;
+    case kRowEB1: sr = -r.hdt * r.c2 * br; si = -r.hdt * r.c2 * bi; break;
+    case kRowEJ1: sr = -r.hdt; si = 0.0; break;
+    case kRowBE1: sr = -r.hdt * ar; si = -r.hdt * ai; break;
+    case kRowBJ1: sr = 0.0; si = 0.0; break;
+    case kRowC2: sr = (1.0 + lam) / d; si = 0.0; break;
+    case kRowEB2: sr = -dt * r.c2 * br / d; si = -dt * r.c2 * bi / d; break;
+    case kRowEJ2: sr = -dt / d; si = 0.0; break;
+    case kRowBE2: sr = -dt * ar / d; si = -dt * ai / d; break;
+    case kRowBJ2: sr = dt * dt * ar / (2.0 * d); si = dt * dt * ai / (2.0 * d); break;
+    case kRowAE: sr = 1.0 / d; si = 0.0; break;
+    case kRowAB: sr = -dt * r.c2 * br / (2.0 * d); si = -dt * r.c2 * bi / (2.0 * d); break;
+    default: sr = -dt / (2.0 * d); si = 0.0; break;   // kRowAJ
+    }
+}
+
+// Rows of the electromagnetic field updates (EMEC(PSATD) or EMEC(LI) by Run::scheme):
+// grid (ceil(N / blockDim), kPsatdRows).
+__global__ __launch_bounds__(256) void k_em_rows(Run r, Work wk)
 {
     extern __shared__ double sym[];      // [2][ng]: the row's symbol, real and imaginary
     const int ng = r.ng, row = blockIdx.y;
     for (int m = threadIdx.x; m < ng; m += nthreads()) {
         const int ms = 2 * m <= ng ? m : m - ng;
-        psatd_symbol(r, row, ms, sym[m], sym[ng + m]);
+        if (r.scheme == kPsatd)
+            psatd_symbol(r, row, ms, sym[m], sym[ng + m]);
+        else
+            cn_symbol(r, row, ms, sym[m], sym[ng + m]);
     }
     __syncthreads();
     const int d = blockIdx.x * nthreads() + threadIdx.x;
@@ -2510,16 +2557,20 @@ __global__ __launch_bounds__(256) void k_psatd_rows(Run r, Work wk)
     wk.prow[(size_t)row * ng + d] = acc / ng;
 }
 
-// One PSATD field update.  full = 0: the predictor (E*, B*) = PSATD(E^n, B^n, j^{n,*},
-// dt/2) into ps (eq. (EM_PSATD), second line); full = 1: (E^{n+1}, B^{n+1}) =
-// PSATD(E^n, B^n, j^{*,n+1/2}, dt) into Ef[par ^ 1], Bf[par ^ 1], and into pf the time
-// average <E> over the step and B^{n+1/2} = (B^n + B^{n+1})/2 that pass B gathers.
-// Grid (ceil(N / blockDim), nq): blockIdx.y picks the pair p and the output o (predictor:
-// q = 2 p + o, o = E, B; full: q = 3 p + o, o = E, B, <E>); each thread one node.  The
-// sums run over j in increasing order (no atomics), so the update is reproducible.
-// E_x has no curl term: E_x - tau j_x (average E_x - tau/2 j_x), written by q = 0.
-// LDS: e | B (signed) | j | the three rows [6][N].
-__global__ __launch_bounds__(256) void k_psatd_fields(Run r, Work wk, int par, int full)
+// One electromagnetic field update by the rows of k_em_rows.  full = 0: the predictor
+// fields (E*, B*) into ps (EMEC(PSATD): PSATD(E^n, B^n, j^{n,*}, dt/2), eq. (EM_PSATD)
+// second line); full = 1: (E^{n+1}, B^{n+1}) from E^n, B^n and j^{*,n+1/2} into
+// Ef[par ^ 1], Bf[par ^ 1], and into pf the E that v-dagger gathers (PSATD: the time
+// average <E> over the step; LI: (E^n + E^{n+1})/2) and B^{n+1/2} = (B^n + B^{n+1})/2.
+// Grid (ceil(N / kPsatdOut), nq), 256 threads: blockIdx.y picks the pair p and the output
+// o (predictor: q = 2 p + o, o = E, B; full: q = 3 p + o, o = E, B, <E>); a workgroup
+// computes kPsatdOut nodes, each as kPsatdSeg partial sums over consecutive ranges of j
+// (in increasing j) added in segment order, so the update is reproducible.  E_x has no
+// curl term: E_x - tau j_x (average E_x - tau/2 j_x), written by q = 0.
+// LDS: e | B (signed) | j | the three rows [6][N] | partial sums [kPsatdSeg][kPsatdOut].
+constexpr int kPsatdOut = 32, kPsatdSeg = 8;
+
+__global__ __launch_bounds__(256) void k_em_fields(Run r, Work wk, int par, int full)
 {
     extern __shared__ double sm[];
     const int ng = r.ng, rs = 3 * ng, q = blockIdx.y;
@@ -2528,7 +2579,7 @@ __global__ __launch_bounds__(256) void k_psatd_fields(Run r, Work wk, int par, i
     const int bc = p == 0 ? 1 : 0;       // pair 0: B_z, pair 1: B_y (taken as -B_y)
     const double sg = p == 0 ? 1.0 : -1.0;
     double *e = sm, *b = sm + ng, *jj = sm + 2 * ng, *k0 = sm + 3 * ng, *k1 = sm + 4 * ng,
-           *k2 = sm + 5 * ng;
+           *k2 = sm + 5 * ng, *part = sm + 6 * ng;
     int r0, r1, r2;
     if (o == 0) {
         r0 = full ? kRowC2 : kRowC1; r1 = full ? kRowEB2 : kRowEB1; r2 = full ? kRowEJ2 : kRowEJ1;
@@ -2546,17 +2597,28 @@ __global__ __launch_bounds__(256) void k_psatd_fields(Run r, Work wk, int par, i
         k2[i] = wk.prow[(size_t)r2 * ng + i];
     }
     __syncthreads();
-    const int i = blockIdx.x * nthreads() + threadIdx.x;
-    if (i >= ng)
-        return;
+    const int il = threadIdx.x % kPsatdOut, seg = threadIdx.x / kPsatdOut;
+    const int i = blockIdx.x * kPsatdOut + il;
+    const int len = (ng + kPsatdSeg - 1) / kPsatdSeg;
+    const int j0 = seg * len, j1 = min(ng, j0 + len);
     double acc = 0.0;
-    for (int j = 0; j < ng; ++j) {
-        int k = i - j;
+    if (i < ng) {
+        int k = i - j0;
         k += k < 0 ? ng : 0;
-        acc = fma(k0[k], e[j], acc);
-        acc = fma(k1[k], b[j], acc);
-        acc = fma(k2[k], jj[j], acc);
+        for (int j = j0; j < j1; ++j) {
+            acc = fma(k0[k], e[j], acc);
+            acc = fma(k1[k], b[j], acc);
+            acc = fma(k2[k], jj[j], acc);
+            k = k == 0 ? ng - 1 : k - 1;
+        }
     }
+    part[seg * kPsatdOut + il] = acc;
+    __syncthreads();
+    if (seg != 0 || i >= ng)
+        return;
+    acc = part[il];
+    for (int t = 1; t < kPsatdSeg; ++t)
+        acc += part[t * kPsatdOut + il];
     if (!full) {
         if (o == 0)
             wk.ps[(1 + p) * ng + i] = acc;

@@ -52,7 +52,7 @@ bool is_std(const pic_params *p) { return p->scheme == PIC_STANDARD; }
 
 struct Layout {
     size_t Ef[2], Bf[2], J1[2], J2[2], cninv, spart, part, st, rec;
-    size_t prow, ps, pf;                            // EMEC(PSATD) (0 when unused)
+    size_t prow, ps, pf;                            // EM field launches (0 when unused)
     size_t x2, v2, id2, wcur, w2, hist, segsum;     // rebin (0 when unused)
     size_t total;
 };
@@ -131,8 +131,9 @@ size_t lds_std_pass_of(int order, size_t ng)
 
 size_t lds_std_field_of(size_t ng) { return 4 * ng * 8; }
 
-// EMEC(PSATD)'s field launch (k_psatd_fields): one pair's E, B and j and three rows
-size_t lds_psatd_of(size_t ng) { return 6 * ng * 8; }
+// the EM field launch (k_em_fields): one pair's E, B and j, three rows and the partial
+// sums of 256 threads
+size_t lds_psatd_of(size_t ng) { return (6 * ng + 256) * 8; }
 
 size_t lds_pass_a(const pic_params *p) { return lds_pass_a_of(is_em(p), p->shape_order, (size_t)p->n_cells); }
 
@@ -149,7 +150,7 @@ size_t lds_need(const pic_params *p)
                                       lds_std_field_of((size_t)p->n_cells))
                            : std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
-    if (is_psatd(p))
+    if (is_em(p))
         m = std::max(m, lds_psatd_of((size_t)p->n_cells));
     m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
@@ -212,9 +213,9 @@ Layout layout_of(const pic_params *p)
         L.J2[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
     }
     L.cninv = take(ng * 8);
-    L.prow = is_psatd(p) ? take((size_t)kPsatdRows * ng * 8) : 0;
+    L.prow = is_em(p) ? take((size_t)kPsatdRows * ng * 8) : 0;
     L.ps = is_psatd(p) ? take(5 * ng * 8) : 0;
-    L.pf = is_psatd(p) ? take(5 * ng * 8) : 0;
+    L.pf = is_em(p) ? take(5 * ng * 8) : 0;
     // two arrays of per-workgroup scalars (the one-pass ESEC1 alternates between them)
     L.spart = take(2 * (size_t)blocks_of(p, nullptr) * kNS * 8);
     L.part = is_det(p) ? take((size_t)blocks_of(p, nullptr) * 3 * ng * 8) : 0;

@@ -144,13 +144,14 @@ void launch_std_field(pic_ctx *c, int64_t n)
                           (int)c->run.filter_rho);
 }
 
-// EMEC(PSATD)'s field launch of step n (par = n & 1): full = 0 the predictor fields
-// (before pass A), full = 1 the new fields and the averages pass B gathers (before pass B).
-void launch_psatd(pic_ctx *c, int par, int full)
+// The EM field launch of step n (par = n & 1): full = 0 the predictor fields (EMEC(PSATD),
+// before pass A), full = 1 the new fields and the averages pass B gathers (before pass B).
+void launch_em_fields(pic_ctx *c, int par, int full)
 {
     const int ng = c->p.n_cells;
-    hipLaunchKernelGGL(k_psatd_fields, dim3((unsigned)((ng + 255) / 256), full ? 6u : 4u), dim3(256),
-                       (uint32_t)lds_psatd_of((size_t)ng), c->stream, c->run, c->wk, par, full);
+    hipLaunchKernelGGL(k_em_fields, dim3((unsigned)((ng + kPsatdOut - 1) / kPsatdOut), full ? 6u : 4u),
+                       dim3(kPsatdOut * kPsatdSeg), (uint32_t)lds_psatd_of((size_t)ng), c->stream,
+                       c->run, c->wk, par, full);
 }
 
 template <int ORDER, int NV, int DEP>
@@ -287,6 +288,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.interleave = 0;
     r.det = is_det(p) ? 1 : 0;
     r.filter_rho = (p->flags & PIC_F_FILTER_RHO) ? 1 : 0;
+    r.em_fields = is_em(p) ? 1 : 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -524,11 +526,9 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
     }
-    if (is_psatd(p))
-        hipLaunchKernelGGL(k_psatd_rows, dim3((unsigned)((p->n_cells + 255) / 256), kPsatdRows), dim3(256),
+    if (is_em(p))
+        hipLaunchKernelGGL(k_em_rows, dim3((unsigned)((p->n_cells + 255) / 256), kPsatdRows), dim3(256),
                            2 * p->n_cells * 8, c->stream, r, w);
-    else if (is_em(p))
-        hipLaunchKernelGGL(k_cn_init, dim3(1), dim3(gt), 0, c->stream, r, w);
     if (p->scheme != PIC_ESEC1)
         dispatch(c, D_PREDEPOSIT);
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
@@ -572,15 +572,14 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
                 dispatch(c, D_STD_PASS, par, n, X, V);
             }
         } else {
-            const bool psatd = is_psatd(&c->p);
-            if (psatd)
-                launch_psatd(c, par, 0);
+            if (is_psatd(&c->p))
+                launch_em_fields(c, par, 0);
             {
                 Timer t(c, PIC_K_PASS_A, true);
                 dispatch(c, D_PASS_A, par, n, X, V);
             }
-            if (psatd)
-                launch_psatd(c, par, 1);
+            if (is_em(&c->p))
+                launch_em_fields(c, par, 1);
             {
                 Timer t(c, PIC_K_PASS_B, true);
                 dispatch(c, D_PASS_B, par, n, X, V);

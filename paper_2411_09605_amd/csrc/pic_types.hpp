@@ -24,10 +24,11 @@ constexpr int kMaxRep = 8;
 constexpr int kStandard = 3;
 constexpr int kPsatd = 4;
 
-// EMEC(PSATD)'s convolution rows (Work::prow), [kPsatdRows][ng]: for the predictor update
-// over dt/2 (tau1) and the full update over dt (tau2), the rows that map E (node), -B or
-// B (half node) and j (node) of one transverse pair to the new E and B, then the rows of
-// the time average of E over the full step.
+// Convolution rows of the electromagnetic field updates (Work::prow), [kPsatdRows][ng]:
+// for the predictor update (over dt/2) and the full update (over dt), the rows that map
+// E (node), -B or B (half node) and j (node) of one transverse pair to the new E and B,
+// then the rows of the E that v-dagger gathers (EMEC(PSATD): the time average over the
+// step; EMEC(LI): the mean of E^n and E^{n+1}).
 enum PsatdRow {
     kRowC1 = 0, kRowEB1, kRowEJ1, kRowBE1, kRowBJ1,     // tau1 = dt/2
     kRowC2, kRowEB2, kRowEJ2, kRowBE2, kRowBJ2,         // tau2 = dt
@@ -76,6 +77,9 @@ struct Run {
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
     int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
     int32_t filter_rho;    // standard scheme: binomial filter on the charge density
+    int32_t em_fields;     // EM: a field launch before pass B computes E^{n+1}, B^{n+1}
+                           // and the gathered averages (Work::pf); 0: pass B's prologue
+                           // does (the batched form)
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
@@ -96,9 +100,9 @@ struct Work {
     double *J1[2];         // [nrep][3][ng] predictor current j^{n,*} (J1[n & 1])
     double *J2[2];         // [nrep][3][ng] centred current j^{*,n+1/2} (J2[n & 1])
     double *cninv;         // [ng] first row of the Crank-Nicolson inverse
-    // EMEC(PSATD) only (else null): the convolution rows, the predictor fields
-    // E*[3][ng] | B*[2][ng] of the current step, and the time-averaged E [3][ng] |
-    // B^{n+1/2} [2][ng] that pass B gathers
+    // EM schemes (else null): the field-update rows, the predictor fields E*[3][ng] |
+    // B*[2][ng] of the current step (EMEC(PSATD)), and the E [3][ng] | B^{n+1/2} [2][ng]
+    // that pass B gathers
     double *prow, *ps, *pf;
     double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
                            // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
