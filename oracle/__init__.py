@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "emec_psatd": 4}
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "emec_psatd": 4, "emec_lf": 5}
 
 
 class OCfg(ctypes.Structure):

@@ -19,6 +19,9 @@
  *   - EMEC(LI): eq. (EMbasic), Crank-Nicolson Maxwell on a staggered 1D grid;
  *   - EMEC(PSATD): eq. (EM_PSATD), the field update solved exactly in time per Fourier mode
  *     (eq. (PSATDformula) and its time average) with spectral staggered curls;
+ *   - EMEC(LF): eq. (EMleapfrog), the Yee leapfrog: B lives at half steps (the state holds
+ *     E^n and B^{n-1/2}) and the magnetic energy is the non-standard
+ *     W_B^n = c^2/2 h sum B^{n+1/2} . B^{n-1/2} of section 4.1;
  *   - the fallback Gamma := 1 when the root is imaginary (section 3.2), counted;
  *   - total energy of section 5.1.
  * The electrostatic Ampere update is E <- E - dt (j - mean j): in 1D, E = -d(phi)/dx
@@ -34,7 +37,7 @@
 
 typedef struct {
     int32_t nv;          /* 1 (1D-1V) or 3 (1D-3V)                                  */
-    int32_t scheme;      /* 0 = ESEC2, 1 = ESEC1, 2 = EMEC(LI), 4 = EMEC(PSATD)      */
+    int32_t scheme;      /* 0 ESEC2, 1 ESEC1, 2 EMEC(LI), 4 EMEC(PSATD), 5 EMEC(LF)  */
     int32_t order;       /* B-spline degree: 1 or 2                                  */
     int32_t n_cells;     /* N_g                                                      */
     int64_t n_particles; /* N_p                                                      */
@@ -347,6 +350,18 @@ static double dminus(const double *g, int i, int ng, double h)
     return (g[i] - g[(i + ng - 1) % ng]) / h;
 }
 
+/* Yee leapfrog magnetic half step (eq. (EMleapfrog), second line):
+ * B^{n+1/2} = B^{n-1/2} - dt curl E^n, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
+ * E [3][ng] on the nodes, B and Bo [2][ng] (B_y, B_z) on the half nodes. */
+static void leapfrog_b(int ng, double h, double dt, const double *E, const double *B, double *Bo)
+{
+    const double *Ey = E + ng, *Ez = E + 2 * ng;
+    for (int i = 0; i < ng; ++i) {
+        Bo[i] = B[i] + dt * dplus(Ez, i, ng, h);
+        Bo[ng + i] = B[ng + i] - dt * dplus(Ey, i, ng, h);
+    }
+}
+
 /* ------------------------------------------------------------------------ energy */
 
 void oracle_energy(const ocfg *cfg, const double *v, const double *w, const double *E,
@@ -362,15 +377,25 @@ void oracle_energy(const ocfg *cfg, const double *v, const double *w, const doub
             v2 += v[c * np + p] * v[c * np + p];
         nadd(&ke, 0.5 * (w ? w[p] : wu) * v2);
     }
-    const int emf = cfg->scheme == 2 || cfg->scheme == 4;
+    const int emf = cfg->scheme == 2 || cfg->scheme == 4 || cfg->scheme == 5;
     int ne = emf ? 3 : 1;
     for (int c = 0; c < ne; ++c)
         for (int i = 0; i < ng; ++i)
             nadd(&we, 0.5 * h * E[c * ng + i] * E[c * ng + i]);
-    if (emf && B)
+    if (emf && B && cfg->scheme == 5) {
+        /* leapfrog (section 4.1): the state holds E^n and B^{n-1/2};
+         * W_B^n = c^2/2 h sum B^{n+1/2} . B^{n-1/2} with B^{n+1/2} = B^{n-1/2} - dt curl E^n */
+        double *bh = malloc(sizeof(double) * 2 * (size_t)ng);
+        leapfrog_b(ng, h, cfg->dt, E, B, bh);
+        for (int c = 0; c < 2; ++c)
+            for (int i = 0; i < ng; ++i)
+                nadd(&wb, 0.5 * cfg->c * cfg->c * h * bh[c * ng + i] * B[c * ng + i]);
+        free(bh);
+    } else if (emf && B) {
         for (int c = 0; c < 2; ++c)
             for (int i = 0; i < ng; ++i)
                 nadd(&wb, 0.5 * cfg->c * cfg->c * h * B[c * ng + i] * B[c * ng + i]);
+    }
     d->kinetic = ke.s + ke.c;
     d->field_e = we.s + we.c;
     d->field_b = wb.s + wb.c;
@@ -410,8 +435,8 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
     const int ng = cfg->n_cells, nv = cfg->nv, ord = cfg->order, sch = cfg->scheme;
     const double L = cfg->length, h = L / ng, dt = cfg->dt, c2 = cfg->c * cfg->c;
     const double wu = L / (double)np;
-    const int psatd = sch == 4;
-    const int em = sch == 2 || psatd;
+    const int psatd = sch == 4, lf = sch == 5;
+    const int em = sch == 2 || psatd || lf;
     const int ncur = em ? 3 : 1;                 /* current components that matter */
     double *vx = v;
 
@@ -435,6 +460,16 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         } else if (psatd) {
             /* (E*, B*) = PSATD(E^n, B^n, j^{n,*}, dt/2) */
             oracle_psatd(ng, L, cfg->c, 0.5 * dt, E, B, o->J1, o->Es, o->Bs, NULL);
+        } else if (lf) {
+            /* B^{n+1/2} = B^{n-1/2} - dt curl E^n into Bs (gathered at x* for v* and at
+             * x^{n+1/2} for v-dagger);  E* = E^n + dt/2 (c^2 curl B^{n+1/2} - j^{n,*}) */
+            leapfrog_b(ng, h, dt, E, B, o->Bs);
+            const double *By = o->Bs, *Bz = o->Bs + ng;
+            for (int i = 0; i < ng; ++i) {
+                o->Es[i] = E[i] - 0.5 * dt * o->J1[i];
+                o->Es[ng + i] = E[ng + i] + 0.5 * dt * (-c2 * dminus(Bz, i, ng, h) - o->J1[ng + i]);
+                o->Es[2 * ng + i] = E[2 * ng + i] + 0.5 * dt * (c2 * dminus(By, i, ng, h) - o->J1[2 * ng + i]);
+            }
         } else {
             const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
             const double *By = B, *Bz = B + ng;
@@ -496,7 +531,20 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         oracle_deposit(ord, np, o->xh, o->wv, o->vs + c * np, ng, h, 0.0, o->J2 + c * ng);
 
     /* S8: field update */
-    if (psatd) {
+    if (lf) {
+        /* E^{n+1} = E^n + dt (c^2 curl B^{n+1/2} - j^{*,n+1/2}); v-dagger gathers
+         * E^{n+1/2} = (E^n + E^{n+1})/2 and B^{n+1/2}, which the state carries on */
+        const double *By = o->Bs, *Bz = o->Bs + ng;
+        for (int i = 0; i < ng; ++i) {
+            o->En[i] = E[i] - dt * o->J2[i];
+            o->En[ng + i] = E[ng + i] + dt * (-c2 * dminus(Bz, i, ng, h) - o->J2[ng + i]);
+            o->En[2 * ng + i] = E[2 * ng + i] + dt * (c2 * dminus(By, i, ng, h) - o->J2[2 * ng + i]);
+        }
+        for (int i = 0; i < 3 * ng; ++i)
+            o->Eb[i] = 0.5 * (E[i] + o->En[i]);
+        memcpy(o->Bb, o->Bs, sizeof(double) * 2 * (size_t)ng);
+        memcpy(o->Bn, o->Bs, sizeof(double) * 2 * (size_t)ng);
+    } else if (psatd) {
         /* (E^{n+1}, B^{n+1}) = PSATD(E^n, B^n, j^{*,n+1/2}, dt); the gather for v-dagger takes
          * the time average <E> over the step; B at n + 1/2 is the mean of B^n and B^{n+1} */
         oracle_psatd(ng, L, cfg->c, dt, E, B, o->J2, o->En, o->Bn, o->Eb);
@@ -620,15 +668,15 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
 /* Validate the configuration: 0 if usable, -1 otherwise. */
 int oracle_check(const ocfg *cfg)
 {
-    if (!cfg || (cfg->nv != 1 && cfg->nv != 3) || cfg->scheme < 0 || cfg->scheme > 4)
+    if (!cfg || (cfg->nv != 1 && cfg->nv != 3) || cfg->scheme < 0 || cfg->scheme > 5)
         return -1;
     if (cfg->order < 1 || cfg->order > 2 || cfg->n_particles < 1)
         return -1;
     if (cfg->n_cells < 2 * cfg->order + 1 || !(cfg->length > 0.0) || !(cfg->dt > 0.0))
         return -1;
-    if (cfg->scheme == 3 || cfg->scheme > 4)
+    if (cfg->scheme == 3 || cfg->scheme > 5)
         return -1;
-    if ((cfg->scheme == 2 || cfg->scheme == 4) && (cfg->nv != 3 || !(cfg->c > 0.0)))
+    if ((cfg->scheme == 2 || cfg->scheme >= 4) && (cfg->nv != 3 || !(cfg->c > 0.0)))
         return -1;
     return 0;
 }
@@ -749,7 +797,7 @@ static double field_energy(const ocfg *cfg, const double *E)
 int oracle_std_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
                    int64_t nsteps, int filter, int first, odiag *rec)
 {
-    if (oracle_check(cfg) || cfg->scheme == 2 || cfg->scheme == 4)
+    if (oracle_check(cfg) || cfg->scheme == 2 || cfg->scheme >= 4)
         return -1;
     const int64_t np = cfg->n_particles;
     const int ng = cfg->n_cells, nv = cfg->nv;

@@ -44,12 +44,12 @@ int main(void)
     for (int ip = 0; ip < 5; ++ip)
         for (int ig = 0; ig < 5; ++ig)
             for (int order = 1; order <= 2; ++order)
-                for (int scheme = 0; scheme <= 4; ++scheme) {
+                for (int scheme = 0; scheme <= 5; ++scheme) {
                     const int64_t np = nps[ip];
                     const int ng = ngs[ig];
                     if (ng < 2 * order + 1)
                         continue;
-                    const int em = scheme == 2 || scheme == 4;
+                    const int em = scheme == 2 || scheme >= 4;
                     const int nv = (em || (ip + ig) % 2) ? 3 : 1;
                     ocfg c = {nv, scheme == 3 ? 0 : scheme, order, ng, np, 5.0, 0.3, 1.0,
                               {0.0, 0.0, 0.0}};
