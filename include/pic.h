@@ -36,6 +36,15 @@
  *               i k e^{i k h/2}, back by i k e^{-i k h/2}); E_x has no curl term.  Each
  *               field update is a fixed-order real-space convolution with rows computed
  *               once at initialisation.  Requires nv == 3.
+ *   PIC_EMEC_LF eq. (EMleapfrog), section 4.1: the Yee leapfrog.  B lives at half steps:
+ *               the caller's B is B^{-1/2} at initialisation, and after m steps E holds
+ *               E^m and B holds B^{m-1/2}.  Each step: B^{n+1/2} = B^{n-1/2} - dt curl E^n,
+ *               E* = E^n + dt/2 (c^2 curl B^{n+1/2} - j^{n,*}), v* gathers E* and
+ *               B^{n+1/2} at x*, E^{n+1} = E^n + dt (c^2 curl B^{n+1/2} - j^{*,n+1/2}),
+ *               v-dagger gathers (E^n + E^{n+1})/2 and B^{n+1/2} at x^{n+1/2}.  The record
+ *               of step n reports the magnetic energy of that section,
+ *               W_B^n = c^2/2 h sum B^{n+1/2} . B^{n-1/2}.  Requires nv == 3 and
+ *               c dt <= h (the leapfrog's stability limit).
  *   PIC_STANDARD the comparison scheme of section 5 (not energy-conserving): Vlasov-Poisson
  *               with the leapfrog/Boris push in its symmetric form, eq. (symm_Boris):
  *               x* = x^n + dt/2 v^n, E^{n+1/2} the Gauss field (spectral, as the initial
@@ -84,7 +93,7 @@ enum pic_status {
 };
 
 enum pic_scheme { PIC_ESEC2 = 0, PIC_ESEC1 = 1, PIC_EMEC_LI = 2, PIC_STANDARD = 3,
-                  PIC_EMEC_PSATD = 4 };
+                  PIC_EMEC_PSATD = 4, PIC_EMEC_LF = 5 };
 
 enum pic_flag {
     PIC_F_INIT_GAUSS = 1u,   /* set E_x^0 from the particles: dE/dx = rho - 1 solved
@@ -166,7 +175,8 @@ typedef struct {
     double  *E;            /* [3][N_g] node field (E_x, E_y, E_z), in/out; the
                               electrostatic schemes use and update E_x only               */
     double  *B;            /* [2][N_g] half-node field (B_y, B_z), in/out; EM schemes
-                              (PIC_EMEC_LI, PIC_EMEC_PSATD) only, NULL otherwise           */
+                              (PIC_EMEC_LI, PIC_EMEC_PSATD, PIC_EMEC_LF) only, NULL
+                              otherwise                                                   */
     void    *workspace;    /* >= pic_workspace_size(params) bytes, 256-byte aligned,
                               caller-owned scratch the library carves up                  */
     size_t   workspace_bytes;
@@ -218,7 +228,7 @@ int pic_check_inputs(const pic_params *p, const double *x, const double *v, cons
 int pic_init(const pic_params *p, const pic_buffers *b, void *hip_stream, pic_ctx **out);
 
 /* Enqueue n_steps steps (eq. (good_translation) / (naivetranslation)+(PICmodification) /
- * (EMbasic) / (EM_PSATD) / (symm_Boris)), each recording a pic_diag.  Asynchronous: returns after enqueueing. */
+ * (EMbasic) / (EM_PSATD) / (EMleapfrog) / (symm_Boris)), each recording a pic_diag.  Asynchronous: returns after enqueueing. */
 int pic_step(pic_ctx *ctx, int64_t n_steps);
 
 /* Synchronise the stream and copy out the records written since the previous call (the

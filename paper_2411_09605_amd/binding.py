@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "standard": 3, "emec_psatd": 4}
-EM_SCHEMES = ("emec_li", 2, "emec_psatd", 4)
+SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "standard": 3, "emec_psatd": 4, "emec_lf": 5}
+EM_SCHEMES = ("emec_li", 2, "emec_psatd", 4, "emec_lf", 5)
 F_INIT_GAUSS, F_TRACK_IDS, F_INTERLEAVE, F_DETERMINISTIC, F_FILTER_RHO = 1, 2, 4, 8, 16
 DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3, "lds_f64": 4}
 ABI_VERSION = 1

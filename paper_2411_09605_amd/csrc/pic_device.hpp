@@ -44,8 +44,8 @@ template <int NV> constexpr int kWavesPerEU = NV == 1 ? 6 : 1;
 // Largest workgroup of the particle passes.
 template <int NV> constexpr int kMaxThreads = 1024;
 
-// Run::scheme of the electromagnetic schemes, EMEC(LI) and EMEC(PSATD).
-__host__ __device__ constexpr bool em_scheme(int s) { return s == 2 || s == kPsatd; }
+// Run::scheme of the electromagnetic schemes, EMEC(LI), EMEC(PSATD) and EMEC(LF).
+__host__ __device__ constexpr bool em_scheme(int s) { return s == 2 || s == kPsatd || s == kLeapfrog; }
 
 // Threads of the (1-D) workgroup: the group-size field of the implicit kernel arguments
 // (a 16-bit field at byte 12), read with a scalar load of the dword that holds it.
@@ -924,10 +924,42 @@ __device__ __forceinline__ double dminus(const double *g, int i, int ng, double 
     return (g[i] - g[i == 0 ? ng - 1 : i - 1]) * inv_h;
 }
 
+// EMEC(LF) magnetic half step at half node i, component c (0: B_y, 1: B_z):
+// B^{n+1/2} = B^{n-1/2} - dt curl E^n, (curl E)_y = -D+E_z, (curl E)_z = D+E_y
+// (eq. (EMleapfrog), second line).  E [3][ng], B [2][ng] in global memory.
+__device__ __forceinline__ double lf_bhalf(const Run &r, const double *E, const double *B, int c,
+                                           int i)
+{
+    const int ng = r.ng, ip = i + 1 == ng ? 0 : i + 1;
+    if (c == 0)
+        return B[i] + r.dt * ((E[2 * ng + ip] - E[2 * ng + i]) * r.inv_h);
+    return B[ng + i] - r.dt * ((E[ng + ip] - E[ng + i]) * r.inv_h);
+}
+
+// EMEC(LF)'s magnetic energy of the state (E^n, B^{n-1/2}) (section 4.1):
+// W_B^n = c^2/2 h sum B^{n+1/2} . B^{n-1/2}.  Summed by the first wavefront in an order
+// fixed by N_g alone (the other wavefronts add exact zeros), so that every writer of a
+// record (a pass's lead, the end-of-call launch, initialisation) gets the same bits.
+// Every thread gets the result.
+__device__ __forceinline__ double lf_magnetic_energy(const Run &r, const double *E, const double *B,
+                                                     double *red)
+{
+    const int ng = r.ng;
+    double s = 0.0;
+    if (threadIdx.x < 64)
+        for (int idx = threadIdx.x; idx < 2 * ng; idx += 64) {
+            const int c = idx >= ng ? 1 : 0, i = idx - c * ng;
+            s = fma(lf_bhalf(r, E, B, c, i), B[idx], s);
+        }
+    return 0.5 * r.c2 * r.h * block_sum(s, red);
+}
+
 // Predictor fields into the interiors of the LDS tiles es [ne][tw], bs [2][tw] from E^n,
 // B^n and j^{n,*} (the caller fills the ghosts):
 //   ESEC2: E* = E - dt/2 (j - mean j)                        (eq. (good_translation))
 //   EM   : E* = E + dt/2 (c^2 curl B - j), B* = B - dt/2 curl E   (eq. (EMbasic))
+//   EMEC(LF): B^{n+1/2} = B - dt curl E into bs, E* = E + dt/2 (c^2 curl B^{n+1/2} - j)
+//          (eq. (EMleapfrog); the workgroup synchronises between the two)
 //   ESEC1: E* = E  (v* uses E^n, eq. (naivetranslation))
 // In 1D: (curl B)_y = -D-B_z, (curl B)_z = D-B_y, (curl E)_y = -D+E_z, (curl E)_z = D+E_y.
 __device__ __forceinline__ void predictor_fields(const Run &r, const double *E, const double *B,
@@ -951,6 +983,23 @@ __device__ __forceinline__ void predictor_fields(const Run &r, const double *E, 
     }
     const double *Ex = E, *Ey = E + ng, *Ez = E + 2 * ng;
     const double *By = B, *Bz = B + ng;
+    if (r.scheme == kLeapfrog) {
+        // B^{n+1/2} into bs first (E* takes its curl), then E* (eq. (EMleapfrog))
+        for (int i = threadIdx.x; i < ng; i += nthreads()) {
+            b0[i] = lf_bhalf(r, E, B, 0, i);
+            b0[tw + i] = lf_bhalf(r, E, B, 1, i);
+        }
+        lds_barrier();
+        for (int i = threadIdx.x; i < ng; i += nthreads()) {
+            const int im = i == 0 ? ng - 1 : i - 1;
+            e0[i] = Ex[i] - r.hdt * rep_sum(J, i, nrep, rs);
+            e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * ((b0[tw + i] - b0[tw + im]) * r.inv_h)
+                                          - rep_sum(J, ng + i, nrep, rs));
+            e0[2 * tw + i] = Ez[i] + r.hdt * (r.c2 * ((b0[i] - b0[im]) * r.inv_h)
+                                              - rep_sum(J, 2 * ng + i, nrep, rs));
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < ng; i += nthreads()) {
         e0[i] = Ex[i] - r.hdt * rep_sum(J, i, nrep, rs);
         e0[tw + i] = Ey[i] + r.hdt * (-r.c2 * dminus(Bz, i, ng, r.inv_h) - rep_sum(J, ng + i, nrep, rs));
@@ -1030,6 +1079,35 @@ __device__ __forceinline__ void field_update(const Run &r, const Work &wk, const
         eb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (E0[i] + e1[i]);
     for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
         bb[(i / ng) * tw + kGhost + i % ng] = 0.5 * (B0[i] + b1[i]);
+}
+
+// EMEC(LF)'s full step in pass B (eq. (EMleapfrog)), after predictor_fields has put
+// B^{n+1/2} into the interior of bs: E^{n+1} = E^n + dt (c^2 curl B^{n+1/2} - j^{*,n+1/2})
+// into e1 [3][ng], B^{n+1/2} (the next state's B) into b1 [2][ng], and what v-dagger
+// gathers into the interiors of eb ((E^n + E^{n+1})/2) and bb (B^{n+1/2}).
+__device__ __forceinline__ void lf_full_fields(const Run &r, const double *E, const double *J,
+                                               const double *bs, double *e1, double *b1,
+                                               double *eb, double *bb, int nrep)
+{
+    const int ng = r.ng, tw = r.tw, rs = 3 * ng;
+    const double *by = bs + kGhost, *bz = bs + tw + kGhost;
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
+        const int im = i == 0 ? ng - 1 : i - 1;
+        const double ex = E[i], ey = E[ng + i], ez = E[2 * ng + i];
+        const double nx = ex - r.dt * rep_sum(J, i, nrep, rs);
+        const double ny = ey + r.dt * (-r.c2 * ((bz[i] - bz[im]) * r.inv_h) - rep_sum(J, ng + i, nrep, rs));
+        const double nz = ez + r.dt * (r.c2 * ((by[i] - by[im]) * r.inv_h) - rep_sum(J, 2 * ng + i, nrep, rs));
+        e1[i] = nx;
+        e1[ng + i] = ny;
+        e1[2 * ng + i] = nz;
+        eb[kGhost + i] = 0.5 * (ex + nx);
+        eb[tw + kGhost + i] = 0.5 * (ey + ny);
+        eb[2 * tw + kGhost + i] = 0.5 * (ez + nz);
+        b1[i] = by[i];
+        b1[ng + i] = bz[i];
+        bb[kGhost + i] = by[i];
+        bb[tw + kGhost + i] = bz[i];
+    }
 }
 
 // ESEC2 electrostatic predictor field E* of pass A into the interior of es, exactly as
@@ -1325,8 +1403,14 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
         rep_zero_part(wk.J2[par ^ 1], T::ncur * ng, r.nrep, 3 * ng, part, nparts);
     }
     // the record of the state this step starts from, if not written yet
-    if (lead && step > wk.st->recorded)
+    if (lead && step > wk.st->recorded) {
+        if (EM && r.scheme == kLeapfrog) {
+            const double wbl = lf_magnetic_energy(r, wk.Ef[par], wk.Bf[par], red);
+            if (threadIdx.x == 0)
+                wk.st->wb = wbl;
+        }
         write_record(r, wk, step, red);
+    }
     lds_barrier();
     if constexpr (EM) {
         ghost_fill(es, T::ne, ng, tw);
@@ -1442,6 +1526,10 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
             tile_load(b1, wk.Bf[par ^ 1], 2 * ng);
         }
         load_batch(cur, X, V, r.vstride, bcur, p1);
+    } else if (EM && r.scheme == kLeapfrog) {
+        predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
+        load_batch(cur, X, V, r.vstride, bcur, p1);
+        lf_full_fields(r, En, wk.J2[par], bs, e1, b1, eb, bb, r.nrep);
     } else {
         predictor_fields(r, En, Bn, wk.J1[par], es, bs, red, r.nrep);
         load_batch(cur, X, V, r.vstride, bcur, p1);
@@ -1475,7 +1563,9 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
         field_energies(r, e1, b1, &we, &wb, red);
         if (threadIdx.x == 0) {
             wk.st->we = we;
-            wk.st->wb = wb;
+            // EMEC(LF)'s W_B needs B^{n+3/2}: the writer of the next record computes it
+            if (r.scheme != kLeapfrog)
+                wk.st->wb = wb;
         }
     }
     lds_barrier();
@@ -2021,8 +2111,14 @@ void k_std_pass(Run r, Work wk, int par, int64_t step, const double *X, const do
 // the newest fields into the caller's arrays.
 __device__ void finish_body(const Run &r, const Work &wk, int par, int64_t step, double *red)
 {
-    if (step > wk.st->recorded)
+    if (step > wk.st->recorded) {
+        if (r.scheme == kLeapfrog) {
+            const double wbl = lf_magnetic_energy(r, wk.Ef[par], wk.Bf[par], red);
+            if (threadIdx.x == 0)
+                wk.st->wb = wbl;
+        }
         write_record(r, wk, step, red);
+    }
     for (int i = threadIdx.x; i < 3 * r.ng; i += nthreads())
         wk.E[i] = wk.Ef[par][i];
     if (em_scheme(r.scheme))
@@ -2656,6 +2752,8 @@ __device__ void init_finish_body(const Run &r, const Work &wk, double *red)
             wk.Bf[0][i] = wk.B[i];
     double we, wb;
     field_energies(r, wk.E, wk.B, &we, &wb, red);
+    if (r.scheme == kLeapfrog)
+        wb = lf_magnetic_energy(r, wk.E, wk.B, red);
     if (threadIdx.x == 0) {
         wk.st->we = we;
         wk.st->wb = wb;

@@ -88,7 +88,13 @@ int blocks_of(const pic_params *p, int64_t *chunk_out)
     return (int)nb;
 }
 
-bool is_em(const pic_params *p) { return p->scheme == PIC_EMEC_LI || p->scheme == PIC_EMEC_PSATD; }
+bool is_em(const pic_params *p)
+{
+    return p->scheme == PIC_EMEC_LI || p->scheme == PIC_EMEC_PSATD || p->scheme == PIC_EMEC_LF;
+}
+
+// EM schemes whose full-step field update is the field launch (k_em_fields)
+bool has_em_fields(const pic_params *p) { return p->scheme == PIC_EMEC_LI || p->scheme == PIC_EMEC_PSATD; }
 
 bool is_psatd(const pic_params *p) { return p->scheme == PIC_EMEC_PSATD; }
 
@@ -150,7 +156,7 @@ size_t lds_need(const pic_params *p)
                                       lds_std_field_of((size_t)p->n_cells))
                            : std::max(lds_pass_a(p), lds_pass_b(p));
     m = std::max(m, (size_t)3 * p->n_cells * 8);
-    if (is_em(p))
+    if (has_em_fields(p))
         m = std::max(m, lds_psatd_of((size_t)p->n_cells));
     m = std::max(m, lds_deposit(p));
     if (p->rebin_every > 0)
@@ -213,9 +219,9 @@ Layout layout_of(const pic_params *p)
         L.J2[k] = take((size_t)nrep_of(p) * 3 * ng * 8);
     }
     L.cninv = take(ng * 8);
-    L.prow = is_em(p) ? take((size_t)kPsatdRows * ng * 8) : 0;
+    L.prow = has_em_fields(p) ? take((size_t)kPsatdRows * ng * 8) : 0;
     L.ps = is_psatd(p) ? take(5 * ng * 8) : 0;
-    L.pf = is_em(p) ? take(5 * ng * 8) : 0;
+    L.pf = has_em_fields(p) ? take(5 * ng * 8) : 0;
     // two arrays of per-workgroup scalars (the one-pass ESEC1 alternates between them)
     L.spart = take(2 * (size_t)blocks_of(p, nullptr) * kNS * 8);
     L.part = is_det(p) ? take((size_t)blocks_of(p, nullptr) * 3 * ng * 8) : 0;
@@ -266,7 +272,7 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "abi_version %d != %d", p->abi_version, PIC_ABI_VERSION);
     if (p->nv != 1 && p->nv != 3)
         return fail(err, PIC_EINVAL, "nv must be 1 or 3 (got %d)", p->nv);
-    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_EMEC_PSATD)
+    if (p->scheme < PIC_ESEC2 || p->scheme > PIC_EMEC_LF)
         return fail(err, PIC_EINVAL, "unknown scheme %d", p->scheme);
     if (p->scheme == PIC_STANDARD && !(p->flags & PIC_F_INIT_GAUSS))
         return fail(err, PIC_EINVAL, "PIC_STANDARD needs PIC_F_INIT_GAUSS (its field comes from the density)");
@@ -288,6 +294,9 @@ int validate(const pic_params *p, std::string *err)
         return fail(err, PIC_EINVAL, "dt must be finite and > 0");
     if (is_em(p) && (!(p->c > 0.0) || !std::isfinite(p->c)))
         return fail(err, PIC_EINVAL, "c must be finite and > 0 for the electromagnetic schemes");
+    if (p->scheme == PIC_EMEC_LF && p->c * p->dt > p->length / p->n_cells * (1.0 + 1e-12))
+        return fail(err, PIC_EINVAL, "PIC_EMEC_LF needs c dt <= h (leapfrog stability): c dt = %g, h = %g",
+                    p->c * p->dt, p->length / p->n_cells);
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(p->b_ext[i]))
             return fail(err, PIC_EINVAL, "b_ext must be finite");

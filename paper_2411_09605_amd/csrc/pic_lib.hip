@@ -288,7 +288,7 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.interleave = 0;
     r.det = is_det(p) ? 1 : 0;
     r.filter_rho = (p->flags & PIC_F_FILTER_RHO) ? 1 : 0;
-    r.em_fields = is_em(p) ? 1 : 0;
+    r.em_fields = has_em_fields(p) ? 1 : 0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -526,7 +526,7 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
     }
-    if (is_em(p))
+    if (has_em_fields(p))
         hipLaunchKernelGGL(k_em_rows, dim3((unsigned)((p->n_cells + 255) / 256), kPsatdRows), dim3(256),
                            2 * p->n_cells * 8, c->stream, r, w);
     if (p->scheme != PIC_ESEC1)
@@ -578,7 +578,7 @@ int enqueue_steps(pic_ctx *c, int64_t n_steps)
                 Timer t(c, PIC_K_PASS_A, true);
                 dispatch(c, D_PASS_A, par, n, X, V);
             }
-            if (is_em(&c->p))
+            if (has_em_fields(&c->p))
                 launch_em_fields(c, par, 1);
             {
                 Timer t(c, PIC_K_PASS_B, true);
@@ -1092,7 +1092,7 @@ int batch_validate(const pic_batch_params *p)
         return fail(nullptr, PIC_EINVAL, "n_runs >= 1 and the per-run arrays are required");
     if (p->flags & ~(uint32_t)PIC_BF_INIT_GAUSS)
         return fail(nullptr, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
-    if (p->scheme == PIC_STANDARD || p->scheme == PIC_EMEC_PSATD)
+    if (p->scheme == PIC_STANDARD || p->scheme == PIC_EMEC_PSATD || p->scheme == PIC_EMEC_LF)
         return fail(nullptr, PIC_EUNSUPPORTED, "the batched form runs ESEC2, ESEC1 and EMEC(LI)");
     if (p->block_threads && (p->block_threads % 64 || p->block_threads < 64 || p->block_threads > kBatchMaxThreads))
         return fail(nullptr, PIC_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, %d]", kBatchMaxThreads);

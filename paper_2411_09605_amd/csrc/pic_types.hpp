@@ -23,6 +23,7 @@ constexpr int kMaxRep = 8;
 // EMEC(PSATD) (section 4.2).
 constexpr int kStandard = 3;
 constexpr int kPsatd = 4;
+constexpr int kLeapfrog = 5;     // EMEC(LF) (section 4.1)
 
 // Convolution rows of the electromagnetic field updates (Work::prow), [kPsatdRows][ng]:
 // for the predictor update (over dt/2) and the full update (over dt), the rows that map
@@ -71,15 +72,15 @@ struct Run {
     int32_t rec_cap;
     int64_t chunk;         // particles per workgroup
     int32_t scheme;        // 0 ESEC2, 1 ESEC1, 2 EMEC(LI), 3 standard (kStandard),
-                           // 4 EMEC(PSATD) (kPsatd)
+                           // 4 EMEC(PSATD) (kPsatd), 5 EMEC(LF) (kLeapfrog)
     int32_t tw;            // LDS tile width: ng + 2 kGhost
     int32_t nrep;          // replicas of the current accumulators (see Work::J1)
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
     int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
     int32_t filter_rho;    // standard scheme: binomial filter on the charge density
-    int32_t em_fields;     // EM: a field launch before pass B computes E^{n+1}, B^{n+1}
-                           // and the gathered averages (Work::pf); 0: pass B's prologue
-                           // does (the batched form)
+    int32_t em_fields;     // EMEC(LI), EMEC(PSATD): a field launch before pass B computes
+                           // E^{n+1}, B^{n+1} and the gathered averages (Work::pf); 0:
+                           // pass B's prologue does (EMEC(LF), the batched form)
     double L, h, inv_h, dt, hdt, c2;
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p

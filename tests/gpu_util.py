@@ -82,7 +82,7 @@ def run_pair(wl, steps, scheme=None, every=1, tol=TOL, **knobs):
     """Run ``steps`` steps on the GPU and in the oracle, comparing every ``every`` steps.
     Returns (gpu records, oracle records, gpu Pic, oracle State)."""
     from paper_2411_09605_amd import Pic
-    em = (scheme or wl.scheme) in ("emec_li", "emec_psatd")
+    em = (scheme or wl.scheme) in ("emec_li", "emec_psatd", "emec_lf")
     if knobs.get("rebin_every", 0) > 0:
         knobs.setdefault("track_ids", True)
     gpu = Pic.from_workload(wl, scheme=scheme, **knobs)

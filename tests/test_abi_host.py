@@ -65,7 +65,9 @@ def test_validation_accepts_and_sizes():
                dict(scheme="standard", init_gauss=True, deterministic=True),
                dict(nv=3, scheme="emec_psatd", n_cells=256),
                dict(nv=3, scheme="emec_psatd", n_cells=3, shape_order=1),
-               dict(nv=3, scheme="emec_psatd", n_cells=256, deterministic=True)]:
+               dict(nv=3, scheme="emec_psatd", n_cells=256, deterministic=True),
+               dict(nv=3, scheme="emec_lf", n_cells=256, dt=0.039),
+               dict(nv=3, scheme="emec_lf", n_cells=100, length=10.0, dt=0.1, c=1.0)]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
@@ -103,6 +105,9 @@ def test_validation_lds_limits():
     (dict(nv=3, scheme="emec_psatd", c=0.0), -1), (dict(nv=3, scheme="emec_psatd", c=float("inf")), -1),
     (dict(nv=3, scheme="emec_psatd", n_cells=698), -6),
     (dict(nv=3, scheme="emec_psatd", filter_rho=True), -1),
+    (dict(nv=1, scheme="emec_lf"), -1), (dict(nv=3, scheme="emec_lf", c=0.0), -1),
+    (dict(nv=3, scheme="emec_lf", n_cells=256, dt=0.05), -1),    # c dt > h: unstable leapfrog
+    (dict(scheme=6), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P
@@ -165,7 +170,7 @@ def test_batch_validation_accepts_and_sizes():
     dict(n_particles=[1000, 0, 5]), dict(length=[10.0, -1.0, 1.0]), dict(chunk=100),
     dict(block_threads=96), dict(graph_steps=-1), dict(nv=1, scheme="emec_li"),
     dict(n_cells=[64, 3, 100000]), dict(dt=float("inf")), dict(scheme="standard"),
-    dict(nv=3, scheme="emec_psatd"),
+    dict(nv=3, scheme="emec_psatd"), dict(nv=3, scheme="emec_lf"),
 ])
 def test_batch_validation_rejects(kw):
     import paper_2411_09605_amd.binding as B

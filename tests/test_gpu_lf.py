@@ -1,0 +1,172 @@
+"""GPU parity of EMEC(LF) (section 4.1, eq. (EMleapfrog)): the HIP path through the C ABI
+against the oracle's leapfrog on the same seeded inputs (1e-10, the metric of
+tests/gpu_util.py), the vacuum wave on the leapfrog's dispersion relation, the Boris limit,
+energy (with the non-standard W_B) over long runs, the Weibel growth rate, and the edge
+cases (odd and minimum grids, weights, launch shapes and deposit modes, deterministic
+reruns and checkpoint/resume).  Runs keep c dt <= h.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import gpu_util as gu
+from tests import theory
+
+pytestmark = pytest.mark.gpu
+S = "emec_lf"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_09605_amd  # noqa: F401  (raises if the library is missing)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _weibel(n, ng, order=2, steps=10, dt=None):
+    wl = workloads.weibel(n_particles=n, n_cells=ng, order=order, steps=steps)
+    h = wl.length / ng
+    wl.dt = dt if dt is not None else min(0.05, 0.8 * h / wl.c)
+    return wl
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_lf_mini_10_steps(order):
+    _say(f"case: LF weibel 1e5 x 256 order {order}")
+    wl = _weibel(100_000, 256, order=order)
+    wl.B0 *= 50.0
+    gu.run_pair(wl, 10, scheme=S)
+
+
+@pytest.mark.parametrize("n,ng,order", [(1, 3, 1), (1, 5, 2), (7, 6, 2), (1000, 37, 1),
+                                        (5000, 64, 2), (20_001, 255, 2)])
+def test_lf_small_odd_and_minimum_grids(n, ng, order):
+    _say(f"case: LF n {n} ng {ng} order {order}")
+    wl = _weibel(n, ng, order=order, steps=6)
+    wl.B0 = 0.05 * np.stack([np.cos(2 * np.pi * np.arange(ng) / ng),
+                             np.sin(4 * np.pi * np.arange(ng) / ng)])
+    wl.E0 = np.zeros((3, ng))
+    wl.E0[1] = 0.02 * np.sin(2 * np.pi * 3 * np.arange(ng) / ng)
+    wl.w = wl.length / n * (1.0 + 0.5 * workloads.uniforms(11, 5, n))
+    wl.b_ext = (0.2, -0.1, 0.3)
+    gu.run_pair(wl, 6, scheme=S)
+
+
+def test_lf_vacuum_wave_on_the_leapfrog_dispersion():
+    """Zero weights: a wave of each polarisation follows sin(w dt/2) = (c dt/h) sin(k h/2)
+    with B = E/c (B^{-1/2} seeded half a step back); after 200 steps the GPU fields equal the
+    travelling wave to 1e-11 and W_E + W_B holds to rounding."""
+    from paper_2411_09605_amd import Pic
+    _say("case: LF vacuum wave, 200 steps")
+    ng, L, c, dt, steps, m = 64, 4 * math.pi, 1.0, 0.15, 200, 5
+    h = L / ng
+    xn, xh = np.arange(ng) * h, (np.arange(ng) + 0.5) * h
+    k = 2 * math.pi * m / L
+    w = 2.0 / dt * math.asin(c * dt / h * math.sin(0.5 * k * h))
+    E0 = np.zeros((3, ng))
+    B0 = np.zeros((2, ng))
+    E0[1], B0[1] = np.cos(k * xn), np.cos(k * xh + 0.5 * w * dt) / c
+    E0[2], B0[0] = 0.5 * np.sin(k * xn), -0.5 * np.sin(k * xh + 0.5 * w * dt) / c
+    n = 64
+    rng = np.random.default_rng(1)
+    gpu = Pic.from_arrays(3, S, 2, ng, L, dt, rng.uniform(0, L, n), rng.normal(size=(3, n)),
+                          E0=E0, B0=B0, w=np.zeros(n), c=c)
+    gpu.step(steps)
+    t = steps * dt
+    E = gpu.E.cpu().numpy()
+    B = gpu.B.cpu().numpy()
+    assert np.abs(E[1] - np.cos(k * xn - w * t)).max() < 1e-11
+    assert np.abs(E[2] - 0.5 * np.sin(k * xn - w * t)).max() < 1e-11
+    assert np.abs(B[1] - np.cos(k * xh - w * (t - 0.5 * dt)) / c).max() < 1e-11
+    assert np.abs(B[0] + 0.5 * np.sin(k * xh - w * (t - 0.5 * dt)) / c).max() < 1e-11
+    rec = gpu.diagnostics()
+    assert np.abs(rec["total"] / rec["total"][0] - 1).max() < 2e-15 * steps
+
+
+def test_lf_boris_limit():
+    from paper_2411_09605_amd import Pic
+    from tests.test_oracle_pins import _boris_reference
+    _say("case: LF Boris limit")
+    n, steps, dt, L = 1000, 20, 0.3, 5.0
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, L, n)
+    v = rng.normal(size=(3, n))
+    b = (0.4, -1.3, 2.0)
+    gpu = Pic.from_arrays(3, S, 2, 16, L, dt, x, v, w=np.zeros(n), b_ext=b, c=1.0)
+    gpu.step(steps)
+    st = gpu.state()
+    xr, vr = _boris_reference(x, v, b, dt, L, steps)
+    assert gu.periodic_err(st["x"], xr, L).max() < 1e-12
+    assert np.abs(st["v"] - vr).max() < 1e-12
+    rec = gpu.diagnostics()
+    assert rec["fallbacks"].sum() == 0 and rec["max_gamma_dev"].max() < 1e-14
+
+
+@pytest.mark.parametrize("case", ["small_grid_blocks", "interleave", "lds_f64", "window",
+                                  "wave", "rebin_window", "deterministic"])
+def test_lf_launch_shapes_and_deposits(case):
+    knobs = {"small_grid_blocks": dict(grid_blocks=37, block_threads=256),
+             "interleave": dict(interleave=True),
+             "lds_f64": dict(deposit_mode="lds_f64"),
+             "window": dict(deposit_mode="window"),
+             "wave": dict(deposit_mode="wave"),
+             "rebin_window": dict(rebin_every=3, deposit_mode="window"),
+             "deterministic": dict(deterministic=True)}[case]
+    _say(f"case: LF weibel 1e5 x 128, {case}")
+    wl = _weibel(100_000, 128, steps=8)
+    wl.B0 *= 50.0
+    gu.run_pair(wl, 8, scheme=S, **knobs)
+
+
+def test_lf_full_size_parity_and_energy():
+    """The 2e7-particle Weibel workload with the leapfrog (dt = 0.04 so that c dt < h):
+    10 steps element by element against the oracle (at steps 5 and 10), then 290 more steps
+    with the energy bar."""
+    _say("case: LF weibel FULL 2e7 x 256, 10 steps vs oracle")
+    wl = workloads.weibel(dt=0.04)
+    grec, orec, gpu, _ = gu.run_pair(wl, 10, scheme=S, every=5)
+    _say("  290 more steps on the GPU")
+    gpu.step(290)
+    rec = np.concatenate([grec, gpu.diagnostics()])
+    clean = rec["fallbacks_total"] == 0
+    _say(f"  fallbacks {int(rec['fallbacks_total'][-1])}, max energy error "
+         f"{rec['rel_energy_err'].max():.3e}")
+    assert rec["rel_energy_err"][clean].max() < 1e-11
+    assert rec["nonfinite"].max() == 0
+
+
+@pytest.mark.timeout(600)
+def test_lf_weibel_growth_rate_matches_oracle():
+    """Weibel growth (section 5.3) with EMEC(LF): the rate of the seeded B_z mode over the
+    linear phase, GPU against the oracle on the same inputs (2e5 particles, 64 cells,
+    dt 0.1), within 2 %, and near the kinetic rate; energy within 1e-11."""
+    from paper_2411_09605_amd import Pic
+    _say("case: LF weibel growth 2e5 x 64, 450 steps")
+    wl = workloads.weibel(n_particles=200_000, n_cells=64, dt=0.1, steps=450)
+    gpu = Pic.from_workload(wl, scheme=S, record_capacity=wl.steps + 8)
+    ost = oracle.State(wl, S)
+    ga, oa = [], []
+    for _ in range(wl.steps):
+        gpu.step(1)
+        ost.run(1)
+        ga.append(theory.mode_amplitude(gpu.B[1].cpu().numpy(), 1))
+        oa.append(theory.mode_amplitude(ost.B[1], 1))
+    t = (np.arange(wl.steps) + 1) * wl.dt
+    sel = (t > 15) & (t < 40)
+    gr = np.polyfit(t[sel], np.log(np.array(ga)[sel]), 1)[0]
+    orate = np.polyfit(t[sel], np.log(np.array(oa)[sel]), 1)[0]
+    ref = theory.weibel_growth(0.5, 0.15, 0.3)
+    _say(f"  rate gpu {gr:.5f} oracle {orate:.5f} theory {ref:.5f}")
+    assert abs(gr - orate) < 0.02 * orate
+    assert abs(orate - ref) < 0.06 * orate
+    rec = gpu.diagnostics()
+    assert rec["rel_energy_err"].max() < 1e-11
+    np.testing.assert_array_equal(rec["fallbacks"], np.array(ost.records)["fallbacks"])

@@ -45,13 +45,16 @@ def _cases():
     ts = workloads.two_stream(n_particles=300_001, n_cells=256, steps=20)
     em = workloads.weibel(n_particles=100_000, n_cells=128, steps=20)
     em.B0 *= 50.0
+    lf = workloads.weibel(n_particles=100_000, n_cells=128, steps=20, dt=0.08)
+    lf.B0 *= 50.0
     return [("two-stream 3e5 x 256", ts, {}), ("weibel 1e5 x 128", em, {}),
             ("two-stream interleaved", ts, dict(interleave=True)),
             ("two-stream esec1 (one pass)", ts, dict(scheme="esec1")),
-            ("weibel 1e5 x 128 emec_psatd", em, dict(scheme="emec_psatd"))]
+            ("weibel 1e5 x 128 emec_psatd", em, dict(scheme="emec_psatd")),
+            ("weibel 1e5 x 128 emec_lf", lf, dict(scheme="emec_lf"))]
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5])
 def test_deterministic_runs_are_bit_identical(k):
     from paper_2411_09605_amd import Pic
     name, wl, kn = _cases()[k]
@@ -86,7 +89,7 @@ def test_deterministic_matches_default_and_oracle(k):
     gu.compare_state(gdet.state(), _O, wl.length, vscale, em, tol=1e-12, where="det vs default")
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5])
 def test_resume_is_bit_identical_in_deterministic_mode(k):
     from paper_2411_09605_amd import Pic
     name, wl, kn = _cases()[k]
