@@ -26,7 +26,7 @@ class OCfg(ctypes.Structure):
                 ("order", ctypes.c_int32), ("n_cells", ctypes.c_int32),
                 ("n_particles", ctypes.c_int64), ("length", ctypes.c_double),
                 ("dt", ctypes.c_double), ("c", ctypes.c_double),
-                ("b_ext", ctypes.c_double * 3)]
+                ("b_ext", ctypes.c_double * 3), ("cc", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class ODiag(ctypes.Structure):
@@ -77,6 +77,9 @@ def lib():
         L.oracle_gauss.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_int,
                                    ctypes.c_double, dp]
         L.oracle_cn_solve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_rho_cc.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_deposit_cc.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int,
+                                        ctypes.c_double, dp]
         L.oracle_energy.argtypes = [ctypes.POINTER(OCfg), dp, dp, dp, dp, ctypes.c_void_p]
         L.oracle_psatd.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    dp, dp, dp, dp, dp, dp]
@@ -91,8 +94,10 @@ def _p(a: Optional[np.ndarray]):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_cfg(nv, scheme, order, n_cells, n_particles, length, dt, c=1.0, b_ext=(0, 0, 0)):
+def make_cfg(nv, scheme, order, n_cells, n_particles, length, dt, c=1.0, b_ext=(0, 0, 0),
+             charge_conserving=False):
     cfg = OCfg()
+    cfg.cc = 1 if charge_conserving else 0
     cfg.nv, cfg.scheme, cfg.order, cfg.n_cells = nv, SCHEMES.get(scheme, scheme), order, n_cells
     cfg.n_particles, cfg.length, cfg.dt, cfg.c = n_particles, length, dt, c
     for i in range(3):
@@ -103,9 +108,10 @@ def make_cfg(nv, scheme, order, n_cells, n_particles, length, dt, c=1.0, b_ext=(
 class State:
     """Host arrays of one run, in the layout the oracle uses (SoA FP64)."""
 
-    def __init__(self, wl, scheme: Optional[str] = None):
+    def __init__(self, wl, scheme: Optional[str] = None, charge_conserving: bool = False):
         self.cfg = make_cfg(wl.nv, scheme or wl.scheme, wl.order, wl.n_cells,
-                            wl.n_particles, wl.length, wl.dt, wl.c, wl.b_ext)
+                            wl.n_particles, wl.length, wl.dt, wl.c, wl.b_ext,
+                            charge_conserving=charge_conserving)
         self.x = np.ascontiguousarray(wl.x, dtype=np.float64).copy()
         self.v = np.ascontiguousarray(wl.v, dtype=np.float64).reshape(wl.nv, -1).copy()
         self.w = None if wl.w is None else np.ascontiguousarray(wl.w, dtype=np.float64).copy()
@@ -163,6 +169,23 @@ def gauss(order, x, w, ng, length):
     E = np.zeros(ng)
     lib().oracle_gauss(order, x.size, _p(x), _p(w), ng, length, _p(E))
     return E
+
+
+def rho_cc(x, w, ng, h):
+    """Charge density on the nodes with the quadratic B-spline (section 3.5's S')."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    rho = np.zeros(ng)
+    lib().oracle_rho_cc(x.size, _p(x), _p(w), ng, h, _p(rho))
+    return rho
+
+
+def deposit_cc(x0, x1, w, u, ng, h):
+    """Charge-conserving current on the half nodes from the paths x0 -> x1 (section 3.5)."""
+    x0, x1, w, u = (np.ascontiguousarray(a, dtype=np.float64) for a in (x0, x1, w, u))
+    out = np.zeros(ng)
+    lib().oracle_deposit_cc(x0.size, _p(x0), _p(x1), _p(w), _p(u), ng, h, _p(out))
+    return out
 
 
 def cn_solve(ng, h, s, r):

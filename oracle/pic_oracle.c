@@ -22,6 +22,9 @@
  *   - EMEC(LF): eq. (EMleapfrog), the Yee leapfrog: B lives at half steps (the state holds
  *     E^n and B^{n-1/2}) and the magnetic energy is the non-standard
  *     W_B^n = c^2/2 h sum B^{n+1/2} . B^{n-1/2} of section 4.1;
+ *   - exact charge conservation (section 3.5, ocfg.cc = 1; ESEC2/ESEC1, electrostatic,
+ *     tent shapes): E_x and the current on the half nodes, the charge density on the nodes
+ *     with the quadratic B-spline, and each particle's path split at the tent's kinks;
  *   - the fallback Gamma := 1 when the root is imaginary (section 3.2), counted;
  *   - total energy of section 5.1.
  * The electrostatic Ampere update is E <- E - dt (j - mean j): in 1D, E = -d(phi)/dx
@@ -45,6 +48,8 @@ typedef struct {
     double dt;
     double c;            /* speed of light in thermal-speed units (EM only)          */
     double b_ext[3];     /* uniform imposed magnetic field                           */
+    int32_t cc;          /* 1: exact charge conservation (section 3.5), see below    */
+    int32_t pad;
 } ocfg;
 
 typedef struct {
@@ -209,6 +214,129 @@ void oracle_gauss(int order, int64_t np, const double *x, const double *w, int n
     oracle_deposit(order, np, x, w, ones, ng, h, 0.0, rho);
     oracle_gauss_rho(ng, L, rho, E);
     free(ones);
+    free(rho);
+}
+
+/* ------------------------------------------ exact charge conservation (section 3.5) */
+
+/* Section 3.5 asks for a shape pair (S, S') with
+ *   S'(x_i - x^{n+1}) - S'(x_i - x^n) = -(x^{n+1} - x^n) . grad_h S(x_i - x^{n+1/2})
+ * (eq. (detbal)), so that rho^n_i = (1/h) sum_p w_p S'(x_i - x_p^n) and the centred current
+ * satisfy the discrete continuity equation (eq. (discCont)).  In 1D with second-order
+ * differences the pair is S = the tent (degree 1) and S' = the quadratic B-spline (degree 2):
+ * the derivative of the quadratic B-spline centred at a node is the difference of the two
+ * tents centred at the neighbouring half nodes, divided by h.  So here the current (and E_x,
+ * which Ampere's law updates from it) lives on the half nodes x_{i+1/2} = (i + 1/2) h with
+ * the tent S, and the divergence of a half-node field at node i is (f_{i+1/2} - f_{i-1/2})/h.
+ * Eq. (detbal) needs S' quadratic along the particle's path, i.e. S linear there: the
+ * path [x^n, x^{n+1}] is cut where S has its kinks (at the half nodes), and on each piece
+ * [a, b] the tent's time average is its value at the piece's midpoint.  The piece carries
+ * the fraction (b - a)/(x^{n+1} - x^n) of the particle's current w v*.  Coordinates below
+ * are u = x / h - 1/2, in which the half nodes are the integers and the tent centred at
+ * half node i is max(0, 1 - |u - i|). */
+
+/* Tent weights at the half nodes around u: (i0, 1 - d) and (i0 + 1, d), d = u - floor(u). */
+static void tent_u(double u, int ng, int64_t *idx, double *wt)
+{
+    double f = floor(u);
+    double d = u - f;
+    idx[0] = pmod((int64_t)f, ng);
+    idx[1] = pmod((int64_t)f + 1, ng);
+    wt[0] = 1.0 - d;
+    wt[1] = d;
+}
+
+/* The pieces of the path from x0 to x1 (unwrapped): for each, call visit(mid_u, frac). */
+typedef void (*piece_fn)(double mid_u, double frac, void *ctx);
+
+static void cc_pieces(double x0, double x1, double h, piece_fn visit, void *ctx)
+{
+    double ua = x0 / h - 0.5, ub = x1 / h - 0.5;
+    double lo = ua < ub ? ua : ub, hi = ua < ub ? ub : ua, len = hi - lo;
+    if (!(len > 0.0) || !isfinite(len)) {          /* no motion (or no finite path) */
+        visit(0.5 * (ua + ub), 1.0, ctx);
+        return;
+    }
+    double s = lo;
+    for (;;) {
+        double e = floor(s) + 1.0;                  /* next kink after s */
+        if (e > hi)
+            e = hi;
+        visit(0.5 * (s + e), (e - s) / len, ctx);
+        if (e >= hi)
+            break;
+        s = e;
+    }
+}
+
+typedef struct {
+    int ng;
+    double q, scale;      /* deposit: q = w u / h */
+    double *out;          /* deposit target or NULL */
+    const double *field;  /* gather source or NULL */
+    double acc;
+} piece_ctx;
+
+static void piece_visit(double mid_u, double frac, void *vctx)
+{
+    piece_ctx *c = (piece_ctx *)vctx;
+    int64_t idx[2];
+    double wt[2];
+    tent_u(mid_u, c->ng, idx, wt);
+    for (int k = 0; k < 2; ++k) {
+        if (c->out)
+            c->out[idx[k]] += c->q * frac * wt[k];
+        if (c->field)
+            c->acc += frac * wt[k] * c->field[idx[k]];
+    }
+}
+
+/* j_{i+1/2} = (1/h) sum_p w_p u_p sum_pieces frac S(x_{i+1/2} - mid), paths x0 -> x1. */
+void oracle_deposit_cc(int64_t np, const double *x0, const double *x1, const double *w,
+                       const double *u, int ng, double h, double *out)
+{
+    memset(out, 0, sizeof(double) * (size_t)ng);
+    for (int64_t p = 0; p < np; ++p) {
+        piece_ctx c = {ng, w[p] * u[p] / h, 1.0, out, NULL, 0.0};
+        cc_pieces(x0[p], x1[p], h, piece_visit, &c);
+    }
+}
+
+/* E_p = sum_pieces frac sum_i E_{i+1/2} S(x_{i+1/2} - mid), paths x0 -> x1. */
+void oracle_gather_cc(int64_t np, const double *x0, const double *x1, const double *field,
+                      int ng, double h, double *out)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        piece_ctx c = {ng, 0.0, 1.0, NULL, field, 0.0};
+        cc_pieces(x0[p], x1[p], h, piece_visit, &c);
+        out[p] = c.acc;
+    }
+}
+
+/* Charge density on the nodes with the quadratic B-spline (the S' of the pair above). */
+void oracle_rho_cc(int64_t np, const double *x, const double *w, int ng, double h, double *rho)
+{
+    double *ones = (double *)malloc(sizeof(double) * (size_t)np);
+    for (int64_t p = 0; p < np; ++p)
+        ones[p] = 1.0;
+    oracle_deposit(2, np, x, w, ones, ng, h, 0.0, rho);
+    free(ones);
+}
+
+/* Gauss' law on the half-node E: (E_{i+1/2} - E_{i-1/2}) / h = rho_i - mean(rho), E with
+ * zero mean (E = -d(phi)/dx); E[i] holds E_{i+1/2}. */
+void oracle_gauss_cc(int64_t np, const double *x, const double *w, int ng, double L, double *E)
+{
+    double h = L / ng;
+    double *rho = (double *)malloc(sizeof(double) * (size_t)ng);
+    oracle_rho_cc(np, x, w, ng, h, rho);
+    double m = mean(rho, ng);
+    E[0] = 0.0;
+    for (int i = 1; i < ng; ++i)
+        E[i] = E[i - 1] + h * (rho[i] - m);
+    double me = mean(E, ng);
+    for (int i = 0; i < ng; ++i)
+        E[i] -= me;
     free(rho);
 }
 
@@ -437,6 +565,7 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
     const double wu = L / (double)np;
     const int psatd = sch == 4, lf = sch == 5;
     const int em = sch == 2 || psatd || lf;
+    const double gs = cfg->cc ? 0.5 : 0.0;       /* E_x, j on the half nodes (cc) */
     const int ncur = em ? 3 : 1;                 /* current components that matter */
     double *vx = v;
 
@@ -452,7 +581,7 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         memcpy(o->Es, E, sizeof(double) * (size_t)ng);
     } else {
         for (int c = 0; c < ncur; ++c)
-            oracle_deposit(ord, np, o->xs, o->wv, v + c * np, ng, h, 0.0, o->J1 + c * ng);
+            oracle_deposit(ord, np, o->xs, o->wv, v + c * np, ng, h, gs, o->J1 + c * ng);
         if (!em) {
             double m = mean(o->J1, ng);
             for (int i = 0; i < ng; ++i)
@@ -487,7 +616,7 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
 
     /* S4-S5: gather at x* and the half-step velocity v* */
     if (nv == 1) {
-        oracle_gather(ord, np, o->xs, o->Es, ng, h, 0.0, o->gE);
+        oracle_gather(ord, np, o->xs, o->Es, ng, h, gs, o->gE);
         for (int64_t p = 0; p < np; ++p)
             o->vs[p] = v[p] + 0.5 * dt * o->gE[p];
     } else {
@@ -495,7 +624,7 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         double *gE = o->gE;                        /* [3][np] */
         for (int c = 0; c < 3; ++c) {
             if (c < ne)
-                oracle_gather(ord, np, o->xs, o->Es + c * ng, ng, h, 0.0, gE + c * np);
+                oracle_gather(ord, np, o->xs, o->Es + c * ng, ng, h, gs, gE + c * np);
             else
                 memset(gE + c * np, 0, sizeof(double) * (size_t)np);
         }
@@ -526,9 +655,14 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
         o->xh[p] = 0.5 * (x[p] + o->x1[p]);
     }
 
-    /* S7: centred deposit j^{*,n+1/2} (velocity v* at x^{n+1/2}) */
-    for (int c = 0; c < ncur; ++c)
-        oracle_deposit(ord, np, o->xh, o->wv, o->vs + c * np, ng, h, 0.0, o->J2 + c * ng);
+    /* S7: centred deposit j^{*,n+1/2} (velocity v* at x^{n+1/2}); with exact charge
+     * conservation, through the pieces of the path x^n -> x^{n+1} (their midpoints replace
+     * x^{n+1/2}) */
+    if (cfg->cc)
+        oracle_deposit_cc(np, x, o->x1, o->wv, o->vs, ng, h, o->J2);
+    else
+        for (int c = 0; c < ncur; ++c)
+            oracle_deposit(ord, np, o->xh, o->wv, o->vs + c * np, ng, h, 0.0, o->J2 + c * ng);
 
     /* S8: field update */
     if (lf) {
@@ -598,7 +732,9 @@ static int step(const ocfg *cfg, double *x, double *v, const double *w, double *
     int ne = em ? 3 : 1;
     double *gE = o->gE, *gBy = o->gB, *gBz = o->gB + np;
     for (int c = 0; c < nv; ++c) {
-        if (c < ne)
+        if (c < ne && cfg->cc)
+            oracle_gather_cc(np, x, o->x1, o->Eb, ng, h, gE);   /* E_x through the pieces */
+        else if (c < ne)
             oracle_gather(ord, np, o->xh, o->Eb + c * ng, ng, h, 0.0, gE + c * np);
         else
             memset(gE + c * np, 0, sizeof(double) * (size_t)np);
@@ -678,6 +814,8 @@ int oracle_check(const ocfg *cfg)
         return -1;
     if ((cfg->scheme == 2 || cfg->scheme >= 4) && (cfg->nv != 3 || !(cfg->c > 0.0)))
         return -1;
+    if (cfg->cc && (cfg->scheme > 1 || cfg->order != 1))
+        return -1;                      /* charge conservation: ESEC2/ESEC1, tent shapes */
     return 0;
 }
 
@@ -699,7 +837,10 @@ int oracle_run_gamma(const ocfg *cfg, double *x, double *v, const double *w, dou
         double *wv = (double *)malloc(sizeof(double) * (size_t)np);
         for (int64_t p = 0; p < np; ++p)
             wv[p] = w ? w[p] : wu;
-        oracle_gauss(cfg->order, np, x, wv, ng, cfg->length, E);
+        if (cfg->cc)
+            oracle_gauss_cc(np, x, wv, ng, cfg->length, E);
+        else
+            oracle_gauss(cfg->order, np, x, wv, ng, cfg->length, E);
         free(wv);
     }
     owork o;
@@ -797,7 +938,7 @@ static double field_energy(const ocfg *cfg, const double *E)
 int oracle_std_run(const ocfg *cfg, double *x, double *v, const double *w, double *E,
                    int64_t nsteps, int filter, int first, odiag *rec)
 {
-    if (oracle_check(cfg) || cfg->scheme == 2 || cfg->scheme >= 4)
+    if (oracle_check(cfg) || cfg->scheme == 2 || cfg->scheme >= 4 || cfg->cc)
         return -1;
     const int64_t np = cfg->n_particles;
     const int ng = cfg->n_cells, nv = cfg->nv;
@@ -950,7 +1091,7 @@ int oracle_tlm_run(const ocfg *cfg, double *x, double *v, const double *w, doubl
                    int64_t nsteps, int init_gauss, double lw, int K, double *dx, double *dv,
                    double *dE, double *loss, double *dloss, odiag *rec)
 {
-    if (oracle_check(cfg) || cfg->nv != 1 || cfg->scheme != 0 || K < 0)
+    if (oracle_check(cfg) || cfg->nv != 1 || cfg->scheme != 0 || K < 0 || cfg->cc)
         return -1;
     const int64_t np = cfg->n_particles;
     const int ng = cfg->n_cells, ord = cfg->order;

@@ -57,6 +57,8 @@ int main(void)
                         c.b_ext[0] = 0.3;
                         c.b_ext[2] = -0.7;
                     }
+                    /* exact charge conservation on the electrostatic tent runs */
+                    c.cc = (scheme <= 1 && order == 1 && (ip + ig) % 3 == 0) ? 1 : 0;
                     double *x = malloc(sizeof(double) * np), *v = malloc(sizeof(double) * 3 * np);
                     double *w = malloc(sizeof(double) * np);
                     double E[3 * 17] = {0}, B[2 * 17] = {0}, g[301];
