@@ -12,6 +12,7 @@ typedef struct {
     int32_t nv, scheme, order, n_cells;
     int64_t n_particles;
     double length, dt, c, b_ext[3];
+    int32_t cc, pad;
 } ocfg;
 
 typedef struct {
