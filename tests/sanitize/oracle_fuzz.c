@@ -83,7 +83,7 @@ int main(void)
                                (long long)np, ng);
                         return 1;
                     }
-                    if (scheme == 0 && nv == 1) {
+                    if (scheme == 0 && nv == 1 && !c.cc) {
                         double dx[2 * 301], dv[2 * 301], dE[2 * 17], J, dJ[2];
                         for (int64_t p = 0; p < 2 * np; ++p) {
                             dx[p] = urand(&seed);
