@@ -350,6 +350,9 @@ def main():
     ap.add_argument("--rebin-every", type=int, default=0)
     ap.add_argument("--deterministic", action="store_true",
                     help="PIC_F_DETERMINISTIC (bit-reproducible current sums)")
+    ap.add_argument("--charge-conserving", action="store_true",
+                    help="PIC_F_CHARGE_CONSERVING (exact charge conservation; ESEC2 with "
+                         "tent shapes: the workload is run with shape order 1)")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps of the same workload for the CPU baseline (0: skip)")
@@ -389,11 +392,13 @@ def main():
     wl = workload_for(args.workload)
     if args.scheme:
         wl.scheme = args.scheme
+    if args.charge_conserving:
+        wl.order = 1
     print(f"[bench] workload {args.workload}: {wl.n_particles} particles, {wl.n_cells} cells, "
           f"order {wl.order}, dt {wl.dt}", file=sys.stderr, flush=True)
     knobs = dict(block_threads=args.block_threads, grid_blocks=args.grid_blocks,
                  deposit_mode=args.deposit_mode, rebin_every=args.rebin_every,
-                 deterministic=args.deterministic,
+                 deterministic=args.deterministic, charge_conserving=args.charge_conserving,
                  record_capacity=max(4096, args.steps + args.warmup + args.profile_steps
                                      + args.late_start + args.late_steps + 8))
     gpu = Pic.from_workload(wl, device="cuda:0", **knobs)
@@ -472,7 +477,7 @@ def main():
     cpu = None
     if args.cpu_steps > 0:
         import oracle
-        ost = oracle.State(wl)
+        ost = oracle.State(wl, charge_conserving=args.charge_conserving)
         ost.run(0)                       # initial Gauss solve outside the timing
         c0 = time.perf_counter()
         ost.run(args.cpu_steps)
@@ -514,7 +519,8 @@ def main():
                    "shape_order": wl.order, "scheme": wl.scheme, "dt": wl.dt,
                    "nv": wl.nv, "block_threads": gpu.block_threads,
                    "grid_blocks": gpu.grid_blocks, "deposit_mode": args.deposit_mode,
-                   "rebin_every": args.rebin_every, "deterministic": args.deterministic},
+                   "rebin_every": args.rebin_every, "deterministic": args.deterministic,
+                   "charge_conserving": args.charge_conserving},
         "energy": energy,
         "roofline": roofline,
         "step_roofline": step_roof,

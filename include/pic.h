@@ -107,6 +107,19 @@ enum pic_flag {
     PIC_F_FILTER_RHO = 16u,  /* PIC_STANDARD: one pass of the binomial filter (1/4, 1/2,
                                 1/4) on the charge density before each field solve
                                 (section 5 filters the standard scheme's density)       */
+    PIC_F_CHARGE_CONSERVING = 32u, /* exact charge conservation (section 3.5, eq. (discCont),
+                                eq. (detbal)) for PIC_ESEC2 with tent shapes
+                                (shape_order 1), electrostatic: E_x and the current live on
+                                the half nodes (i + 1/2) h; the centred current is
+                                deposited, and v-dagger's field gathered, through the pieces
+                                of each particle's path x^n -> x^{n+1} between the half
+                                nodes, each piece carrying its fraction of the path at its
+                                midpoint.  Then D-(E) = rho - mean(rho) holds at every step
+                                (if it holds at the start), with rho_i = (1/h) sum_p w_p
+                                S2(x_i - x_p) on the nodes, S2 the quadratic B-spline, and
+                                D-(E)_i = (E_{i+1/2} - E_{i-1/2}) / h.  PIC_F_INIT_GAUSS
+                                then solves that law (running sum, mean of E zero).  Needs
+                                rebin_every == 0 and the LDS_ATOMIC or LDS_F64 deposit    */
     PIC_F_DETERMINISTIC = 8u /* bit-for-bit reproducible runs (and continuations through
                                 pic_save_state / pic_load_state with the same launch
                                 shape): each workgroup's deposit is summed exactly in

@@ -20,6 +20,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ENONFINITE, PIC_EUN
 SCHEMES = {"esec2": 0, "esec1": 1, "emec_li": 2, "standard": 3, "emec_psatd": 4, "emec_lf": 5}
 EM_SCHEMES = ("emec_li", 2, "emec_psatd", 4, "emec_lf", 5)
 F_INIT_GAUSS, F_TRACK_IDS, F_INTERLEAVE, F_DETERMINISTIC, F_FILTER_RHO = 1, 2, 4, 8, 16
+F_CHARGE_CONSERVING = 32
 DEPOSIT_MODES = {"auto": 0, "lds_atomic": 1, "window": 2, "wave": 3, "lds_f64": 4}
 ABI_VERSION = 1
 
@@ -119,7 +120,8 @@ def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: in
                 init_gauss: bool = False, track_ids: bool = False, rebin_every: int = 0,
                 block_threads: int = 0, grid_blocks: int = 0, deposit_mode="auto",
                 record_capacity: int = 0, interleave: bool = False,
-                deterministic: bool = False, filter_rho: bool = False) -> PicParams:
+                deterministic: bool = False, filter_rho: bool = False,
+                charge_conserving: bool = False) -> PicParams:
     p = PicParams()
     p.abi_version = ABI_VERSION
     p.nv, p.scheme, p.shape_order = nv, SCHEMES.get(scheme, scheme), shape_order
@@ -129,7 +131,8 @@ def make_params(nv: int, scheme, shape_order: int, n_particles: int, n_cells: in
         p.b_ext[i] = b_ext[i]
     p.flags = ((F_INIT_GAUSS if init_gauss else 0) | (F_TRACK_IDS if track_ids else 0)
                | (F_INTERLEAVE if interleave else 0) | (F_DETERMINISTIC if deterministic else 0)
-               | (F_FILTER_RHO if filter_rho else 0))
+               | (F_FILTER_RHO if filter_rho else 0)
+               | (F_CHARGE_CONSERVING if charge_conserving else 0))
     p.block_threads, p.grid_blocks = block_threads, grid_blocks
     p.deposit_mode = DEPOSIT_MODES.get(deposit_mode, deposit_mode)
     p.record_capacity, p.reserved = record_capacity, 0

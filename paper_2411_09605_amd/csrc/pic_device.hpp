@@ -698,6 +698,69 @@ __device__ __forceinline__ double wrap_pos(double x, double L)
     return x;
 }
 
+// Exact charge conservation (section 3.5; Run::cc; tent shapes): the centred current and
+// v-dagger's field go through the pieces of the particle's path x0 -> x1 (x0 wrapped, as
+// stored; x1 unwrapped) between the half nodes, where the tent has its kinks.  In
+// u = x / h - 1/2 the half nodes are the integers; a piece [s, e] is visited at its
+// midpoint with the fraction (e - s) / |u1 - u0| of the path (on a piece the tent is
+// linear, so its value at the midpoint is its time average there, and eq. (detbal) holds
+// piece by piece).  Coordinates are taken relative to the whole cell `base` = floor(u0),
+// and the end point as its wrapped image's u plus the whole periods in between: that is
+// the number the next step starts from, whereas x / h itself is not exactly periodic in
+// floating point (over many boundary crossings the difference would drift Gauss' law).
+// visit(base, t, frac) gets the midpoint t relative to base.  A path with no length, or
+// one longer than 2^30 cells (only a non-finite or absurd state), is one piece.
+template <typename F>
+__device__ __forceinline__ void cc_pieces(const Run &r, double x0, double x1, F &&visit)
+{
+    const double ua = x0 * r.inv_h - 0.5;
+    const double base = floor(ua);
+    const double xw = wrap_pos(x1, r.L);
+    const double m = rint((x1 - xw) / r.L);          // whole periods between x1 and xw
+    const double ta = ua - base;
+    const double tb = (xw * r.inv_h - 0.5) + (m * (double)r.ng - base);
+    const double lo = fmin(ta, tb), hi = fmax(ta, tb), len = hi - lo;
+    if (!(len > 0.0) || !(len < 1073741824.0)) {
+        visit(base, 0.5 * (ta + tb), 1.0);
+        return;
+    }
+    double t = lo;
+    for (;;) {
+        const double e = fmin(floor(t) + 1.0, hi);
+        visit(base, 0.5 * (t + e), (e - t) / len);
+        if (e >= hi)
+            break;
+        t = e;
+    }
+}
+
+// Tent stencil at u = base + t (base a whole number).
+__device__ __forceinline__ Stencil<1> cc_stencil(double base, double t)
+{
+    const double f = floor(t);
+    const double d = t - f;
+    Stencil<1> s;
+    s.first = (int)(base + f);
+    s.w[0] = 1.0 - d;
+    s.w[1] = d;
+    return s;
+}
+
+// v-dagger's field through the pieces of the path x0 -> x1 (tent coefficient tile ct).
+__device__ __forceinline__ double cc_gather(const Run &r, const double *ct, double x0, double x1)
+{
+    double acc = 0.0;
+    cc_pieces(r, x0, x1, [&](double base, double t, double f) {
+        const Stencil<1> st = cc_stencil(base, t);
+        Cell<1> c;
+        c.base = slots_of<1>(st, r.ng).n[0];
+        c.d = st.w[1];
+        acc = fma(f, gather_poly<1>(ct, c), acc);
+    });
+    return acc;
+}
+
+
 // --------------------------------------------------------------- block reductions
 // Workgroup barrier that orders LDS only.  __syncthreads also waits for every global load
 // and store the wavefront has in flight (particle writes, the last prefetch), which costs
@@ -1328,7 +1391,7 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
     Half<ORDER, NV, EM> o;
     const double xs = fma(r.hdt, v[0], x);
     if constexpr (NV == 1) {
-        o.vs[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h, r.ng)), v[0]);
+        o.vs[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h - r.xshift, r.ng)), v[0]);
     } else {
         double u[3], t[3];
         if constexpr (EM) {
@@ -1343,7 +1406,7 @@ __device__ __forceinline__ Half<ORDER, NV, EM> half_step(const Run &r, double x,
             t[1] = r.hdt * (r.bext[1] + gather1<ORDER>(bs, sh, nh));
             t[2] = r.hdt * (r.bext[2] + gather1<ORDER>(bs + r.tw, sh, nh));
         } else {
-            u[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h, r.ng)), v[0]);
+            u[0] = fma(r.hdt, gather_poly<ORDER>(es, cell_of<ORDER>(xs * r.inv_h - r.xshift, r.ng)), v[0]);
             u[1] = v[1];
             u[2] = v[2];
             t[0] = r.hdt * r.bext[0];
@@ -1444,7 +1507,22 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
 #pragma unroll
             for (int c = 0; c < T::ncur; ++c)
                 qv[c] = q * hs.vs[c];
-            dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv, valid, u == 0);
+            bool done = false;
+            if constexpr (!EM && ORDER == 1 && DEP != 2) {
+                if (r.cc) {
+                    // exact charge conservation: through the pieces of the path x^n -> x^{n+1}
+                    cc_pieces(r, cur.x[u], hs.x1, [&](double base, double t, double f) {
+                        double qf[T::ncur];
+#pragma unroll
+                        for (int c = 0; c < T::ncur; ++c)
+                            qf[c] = qv[c] * f;
+                        dep.add(jt, tw, ng, cc_stencil(base, t), qf, valid, false);
+                    });
+                    done = true;
+                }
+            }
+            if (!done)
+                dep.add(jt, tw, ng, stencil<ORDER>(hs.xh * r.inv_h), qv, valid, u == 0);
         }
         cur = nxt;
         bcur = bnxt;
@@ -1593,7 +1671,13 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
             const Half<ORDER, NV, EM> hs = half_step<ORDER, NV, EM>(r, cur.x[u], v, eg, bs);
             double vd[NV];
             if constexpr (NV == 1) {
-                vd[0] = fma(r.dt, gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng)), v[0]);
+                double eb1;
+                if constexpr (ORDER == 1)
+                    eb1 = r.cc ? cc_gather(r, ctb, cur.x[u], hs.x1)
+                               : gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
+                else
+                    eb1 = gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
+                vd[0] = fma(r.dt, eb1, v[0]);
             } else {
                 double e[3], b[3];
                 b[0] = r.bext[0];
@@ -1608,7 +1692,11 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                     b[1] = r.bext[1] + gather1<ORDER>(bb, sh, nh);
                     b[2] = r.bext[2] + gather1<ORDER>(bb + tw, sh, nh);
                 } else {
-                    e[0] = gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
+                    if constexpr (ORDER == 1)
+                        e[0] = r.cc ? cc_gather(r, ctb, cur.x[u], hs.x1)
+                                    : gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
+                    else
+                        e[0] = gather_poly<ORDER>(ctb, cell_of<ORDER>(hs.xh * r.inv_h, ng));
                     e[1] = 0.0;
                     e[2] = 0.0;
                     b[1] = r.bext[1];
@@ -1660,7 +1748,8 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
 #pragma unroll
                 for (int c = 0; c < T::ncur; ++c)
                     qv[c] = q * vn[c];
-                dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h), qv, valid, u == 0);
+                dep.add(jt, tw, ng, stencil<ORDER>(fma(r.hdt, vn[0], xw) * r.inv_h - r.xshift), qv, valid,
+                        u == 0);
             }
         }
         cur = nxt;
@@ -2160,7 +2249,7 @@ __device__ __forceinline__ void predeposit_body(const Run &r, const Work &wk,
 #pragma unroll
         for (int c = 0; c < T::ncur; ++c)
             qv[c] = q * V[c * r.vstride + p];
-        dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h), qv);
+        dep.add(jt, r.tw, r.ng, stencil<ORDER>(fma(r.hdt, V[p], X[p]) * r.inv_h - r.xshift), qv);
     }
     flag_over(dep, wk);
     __syncthreads();
@@ -2520,6 +2609,33 @@ __global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
 {
     extern __shared__ double smem[];
     gauss_body(r, wk, smem);
+}
+
+// Initial field of a charge-conserving run (Run::cc): Gauss' law on the half-node E,
+// (E_{i+1/2} - E_{i-1/2}) / h = rho_i - mean(rho), by a running sum from the density in
+// J2[0] (quadratic B-spline on the nodes), then the mean of E removed (E = -d(phi)/dx).
+// One workgroup; the running sum is serial (N_g additions).
+__global__ __launch_bounds__(1024) void k_gauss_cc(Run r, Work wk)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kRedSize];
+    const int ng = r.ng;
+    double *rho = smem;
+    rep_gather(rho, wk.J2[0], ng, r.nrep, 3 * ng);
+    __syncthreads();
+    const double m = block_mean(rho, ng, red);
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        rho[0] = 0.0;               // rho[i] now holds E_{i+1/2}
+        for (int i = 1; i < ng; ++i) {
+            e += r.h * (rho[i] - m);
+            rho[i] = e;
+        }
+    }
+    __syncthreads();
+    const double me = block_mean(rho, ng, red);
+    for (int i = threadIdx.x; i < ng; i += nthreads())
+        wk.E[i] = rho[i] - me;
 }
 
 // First row of (I - s L_h)^{-1} for the periodic 3-point Laplacian: circulant, so

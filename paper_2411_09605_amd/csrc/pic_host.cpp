@@ -48,6 +48,7 @@ constexpr size_t kMaxLds = 160 * 1024 - 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 bool is_det(const pic_params *p) { return (p->flags & PIC_F_DETERMINISTIC) != 0; }
+bool is_cc(const pic_params *p) { return (p->flags & PIC_F_CHARGE_CONSERVING) != 0; }
 bool is_std(const pic_params *p) { return p->scheme == PIC_STANDARD; }
 
 struct Layout {
@@ -303,8 +304,15 @@ int validate(const pic_params *p, std::string *err)
     if (p->rebin_every < 0)
         return fail(err, PIC_EINVAL, "rebin_every must be >= 0");
     if (p->flags & ~(uint32_t)(PIC_F_INIT_GAUSS | PIC_F_TRACK_IDS | PIC_F_INTERLEAVE |
-                               PIC_F_DETERMINISTIC | PIC_F_FILTER_RHO))
+                               PIC_F_DETERMINISTIC | PIC_F_FILTER_RHO | PIC_F_CHARGE_CONSERVING))
         return fail(err, PIC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (is_cc(p) && (p->scheme != PIC_ESEC2 || p->shape_order != 1))
+        return fail(err, PIC_EINVAL, "PIC_F_CHARGE_CONSERVING needs PIC_ESEC2 and shape_order 1");
+    if (is_cc(p) && (p->rebin_every > 0 || (p->deposit_mode != PIC_DEPOSIT_AUTO &&
+                                            p->deposit_mode != PIC_DEPOSIT_LDS_ATOMIC &&
+                                            p->deposit_mode != PIC_DEPOSIT_LDS_F64)))
+        return fail(err, PIC_EINVAL,
+                    "PIC_F_CHARGE_CONSERVING needs rebin_every == 0 and the LDS_ATOMIC or LDS_F64 deposit");
     if ((p->flags & PIC_F_DETERMINISTIC) && p->rebin_every > 0)
         return fail(err, PIC_EINVAL, "PIC_F_DETERMINISTIC needs rebin_every == 0");
     if ((p->flags & PIC_F_DETERMINISTIC) && p->deposit_mode != PIC_DEPOSIT_AUTO &&

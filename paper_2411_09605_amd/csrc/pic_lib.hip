@@ -289,6 +289,8 @@ void bind_run_work(const pic_params *p, const pic_buffers *b, const Layout &L, c
     r.det = is_det(p) ? 1 : 0;
     r.filter_rho = (p->flags & PIC_F_FILTER_RHO) ? 1 : 0;
     r.em_fields = has_em_fields(p) ? 1 : 0;
+    r.cc = is_cc(p) ? 1 : 0;
+    r.xshift = is_cc(p) ? 0.5 : 0.0;
     r.rec_cap = records_of(p);
     r.L = p->length;
     r.h = p->length / p->n_cells;
@@ -522,7 +524,15 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         hipLaunchKernelGGL((k_init_particles<3>), dim3(r.nblocks), dim3(c->threads), 0, c->stream, r, w,
                            b->x, b->v);
     hipLaunchKernelGGL(k_fx_setup, dim3(1), dim3(256), 0, c->stream, r, w);
-    if (p->flags & PIC_F_INIT_GAUSS) {
+    if ((p->flags & PIC_F_INIT_GAUSS) && is_cc(p)) {
+        // the density with the quadratic B-spline (one degree above the tent), then Gauss'
+        // law on the half-node E
+        hipLaunchKernelGGL((k_deposit_rho<2>), dim3(r.nblocks), dim3(c->threads), lds_deposit(p),
+                           c->stream, r, w, b->x);
+        if (r.det)
+            reduce_partials(c, w.J2[0], 1);
+        hipLaunchKernelGGL(k_gauss_cc, dim3(1), dim3(gt), p->n_cells * 8, c->stream, r, w);
+    } else if (p->flags & PIC_F_INIT_GAUSS) {
         dispatch(c, D_RHO);
         hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * p->n_cells * 8, c->stream, r, w);
     }

@@ -78,10 +78,14 @@ struct Run {
     int32_t interleave;    // 1: the particle passes deal batches round-robin (WaveBatches)
     int32_t det;           // 1: deterministic mode (static batches, ordered current sums)
     int32_t filter_rho;    // standard scheme: binomial filter on the charge density
+    int32_t cc;            // exact charge conservation (ESEC2, electrostatic, tents): E_x
+                           // and j on the half nodes, the centred deposit and v-dagger's
+                           // gather through the pieces of each path
     int32_t em_fields;     // EMEC(LI), EMEC(PSATD): a field launch before pass B computes
                            // E^{n+1}, B^{n+1} and the gathered averages (Work::pf); 0:
                            // pass B's prologue does (EMEC(LF), the batched form)
     double L, h, inv_h, dt, hdt, c2;
+    double xshift;         // grid offset of E_x and j in cells: 0.5 with cc (half nodes), else 0
     double qs;             // 1/h: deposit factor (times w_p)
     double wu;             // uniform weight L / N_p
     double fx_lim;         // contributions with |c| 2^S >= fx_lim leave the fixed-point tile

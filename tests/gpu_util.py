@@ -89,7 +89,8 @@ def run_pair(wl, steps, scheme=None, every=1, tol=TOL, **knobs):
     if (scheme or wl.scheme) == "standard":
         ost = oracle.StdState(wl, filter_rho=knobs.get("filter_rho", False))
     else:
-        ost = oracle.State(wl, scheme=scheme)
+        ost = oracle.State(wl, scheme=scheme,
+                           charge_conserving=knobs.get("charge_conserving", False))
     vscale = max(1.0, float(np.abs(wl.v).max()))
     grecs = [gpu.diagnostics()]
     orecs = [ost.run(0)]

@@ -67,7 +67,10 @@ def test_validation_accepts_and_sizes():
                dict(nv=3, scheme="emec_psatd", n_cells=3, shape_order=1),
                dict(nv=3, scheme="emec_psatd", n_cells=256, deterministic=True),
                dict(nv=3, scheme="emec_lf", n_cells=256, dt=0.039),
-               dict(nv=3, scheme="emec_lf", n_cells=100, length=10.0, dt=0.1, c=1.0)]:
+               dict(nv=3, scheme="emec_lf", n_cells=100, length=10.0, dt=0.1, c=1.0),
+               dict(shape_order=1, charge_conserving=True, init_gauss=True),
+               dict(shape_order=1, nv=3, charge_conserving=True, deposit_mode="lds_f64"),
+               dict(shape_order=1, charge_conserving=True, deterministic=True)]:
         p = _good(**kw)
         assert P.validate(p) == 0, (kw, P.last_error())
         assert P.workspace_size(p) > 0
@@ -108,6 +111,11 @@ def test_validation_lds_limits():
     (dict(nv=1, scheme="emec_lf"), -1), (dict(nv=3, scheme="emec_lf", c=0.0), -1),
     (dict(nv=3, scheme="emec_lf", n_cells=256, dt=0.05), -1),    # c dt > h: unstable leapfrog
     (dict(scheme=6), -1),
+    (dict(charge_conserving=True), -1),                               # quadratic shapes
+    (dict(shape_order=1, scheme="esec1", charge_conserving=True), -1),
+    (dict(shape_order=1, nv=3, scheme="emec_li", charge_conserving=True), -1),
+    (dict(shape_order=1, charge_conserving=True, rebin_every=4), -1),
+    (dict(shape_order=1, charge_conserving=True, deposit_mode="window"), -1),
 ])
 def test_validation_rejects(kw, code):
     import paper_2411_09605_amd as P
