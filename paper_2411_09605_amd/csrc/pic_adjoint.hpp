@@ -70,8 +70,12 @@ template <> __device__ __forceinline__ Stencil<2> dstencil<2>(double xi)
     return s;
 }
 
-// Gamma and its branch: ok = the root is real (no fallback).  num2 = 2 num, formed as in
-// the forward pass so that the branch taken is the forward run's.
+// Gamma and its branch: ok = the root is real (no fallback).  num2 = 2 num is formed as in
+// the forward pass, but from a recomputed state that agrees with the forward run only to
+// rounding (see adj_particle), and Gamma uses IEEE division and square root where the
+// forward pass uses a Newton-refined reciprocal and a Taylor series: a particle whose
+// radicand is within rounding of zero could take the other branch than in the forward run
+// (the tests compare the fallback counts of the two; they agree).
 __device__ __forceinline__ double adj_gamma(double num2, double den, double &rho, bool &ok)
 {
     rho = num2 / den;
@@ -99,7 +103,9 @@ __device__ __forceinline__ AdjOut<ORDER, STAGE> adj_particle(const Run &r, doubl
                                                             const double *jb2, const double *jb1)
 {
     AdjOut<ORDER, STAGE> o;
-    // forward recompute (the operations of pass A / pass B)
+    // forward recompute: the quantities of pass A / pass B, equal to theirs up to rounding
+    // (the gathers here take the stencil weights, the passes the cell polynomials of
+    // gather_poly; the derivative needs the weights anyway)
     const double xs = fma(r.hdt, v, x);
     o.ss = stencil<ORDER>(xs * r.inv_h);
     o.ns = slots_of<ORDER>(o.ss, r.ng);

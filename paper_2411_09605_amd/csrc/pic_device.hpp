@@ -151,16 +151,27 @@ __device__ __forceinline__ void load_weights(double (&w)[U], const double *__res
 template <int U> struct WaveBatches {
     static constexpr int kBatch = 64 * U;
     int64_t origin, step;
+    int64_t np, last;      // reversed order: batch start s maps to last - s while s < np
     int *ctr;
     int fixed;             // 1: static assignment
     int k;                 // static: index of the wavefront's current batch
+    // Interleaved runs (the state larger than the 256 MB Infinity Cache) can walk the state
+    // from its end (reverse): a pass that starts where the previous pass ended finds up to
+    // 256 MB of the state still in the cache.  The set of batches is the same either way.
     __device__ __forceinline__ WaveBatches(int64_t p0, int *counter, int interleave = 0,
-                                           int nblocks = 1, int static_order = 0)
+                                           int nblocks = 1, int static_order = 0,
+                                           int64_t n_particles = 0, bool reverse = false)
         : ctr(counter), fixed(static_order)
     {
         origin = interleave ? (int64_t)blockIdx.x * kBatch : p0;
         step = interleave ? (int64_t)nblocks * kBatch : (int64_t)kBatch;
         k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        np = (interleave && reverse && n_particles > 0) ? n_particles : 0;
+        last = np > 0 ? (np - 1) / kBatch * kBatch : 0;
+    }
+    __device__ __forceinline__ int64_t order(int64_t s) const
+    {
+        return s < np ? last - s : s;
     }
     __device__ __forceinline__ void reset() const
     {
@@ -170,19 +181,19 @@ template <int U> struct WaveBatches {
     // first particle of this wavefront's first batch (the same in every lane)
     __device__ __forceinline__ int64_t first() const
     {
-        return origin + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * step;
+        return order(origin + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * step);
     }
     // claim the next batch (every lane of the wavefront active)
     __device__ __forceinline__ int64_t claim()
     {
         if (fixed) {
             k += (int)(nthreads() >> 6);
-            return origin + (int64_t)k * step;
+            return order(origin + (int64_t)k * step);
         }
         int kc = 0;
         if ((threadIdx.x & 63) == 0)
             kc = atomicAdd(ctr, 1);
-        return origin + (int64_t)__builtin_amdgcn_readlane(kc, 0) * step;
+        return order(origin + (int64_t)__builtin_amdgcn_readlane(kc, 0) * step);
     }
 };
 
@@ -1439,7 +1450,8 @@ __device__ __forceinline__ void pass_a_body(const Run &r, const Work &wk, int pa
     double *bs = es + T::ne * tw;
     double *side = bs + T::nb * tw;       // [ncur][tw] FP64 side tile of the deposit
     double *ct = smem + coef_offset((2 * T::ncur + T::ne + T::nb) * tw);   // ES: coefficients
-    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
+    // pass A walks the state from its end, pass B from its start (see WaveBatches)
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det, r.np, true);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -1816,7 +1828,8 @@ __device__ __forceinline__ void esec1_body(const Run &r, const Work &wk, int par
 {
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
-    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
+    // one pass per step: alternate directions (see WaveBatches)
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det, r.np, (step & 1) != 0);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
@@ -2073,7 +2086,8 @@ __device__ __forceinline__ void std_pass_body(const Run &r, const Work &wk, int 
 {
     const int ng = r.ng, tw = r.tw;
     const unsigned lane = threadIdx.x & 63;
-    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det);
+    // one pass per step: alternate directions (see WaveBatches)
+    WaveBatches<U> wb(p0, wctr, r.interleave, r.nblocks, r.det, r.np, (step & 1) != 0);
     PBatch<U, NV> cur, nxt;
     int64_t bcur = wb.first();
     wb.reset();
