@@ -413,9 +413,10 @@ int pic_batch_destroy(pic_batch *ctx);
  * dx_p/dalpha_m = -sin(k_m x_p) / (k_m (1 + sum_j alpha_j cos(k_j x_p))).
  *
  * pic_adj_forward samples, initialises and runs N steps exactly as pic_init + pic_step,
- * storing the state (x, v, E) every checkpoint_every steps; pic_adj_backward recomputes
- * each segment from its checkpoint and runs the reverse of the steps, of the Gauss
- * solve and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in
+ * storing the particle state (x, v) every checkpoint_every steps and every step's grids
+ * (E^n and the two currents, 3 N_g values); pic_adj_backward recomputes each segment's
+ * states from its checkpoint and those grids (one gather-only launch per step) and runs
+ * the reverse of the steps, of the Gauss solve and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in
  * the derivative. */
 #define PIC_ADJ_MAX_MODES 16
 
@@ -452,8 +453,8 @@ typedef struct {                 /* DEVICE pointers, caller-owned, [N_p] unless 
 typedef struct pic_adj pic_adj;
 
 /* Workspace bytes (0 if the parameters are invalid; pic_last_error(NULL) says why).
- * About (2 ceil(N / K) + 2 K + 2) * 8 N_p bytes: checkpoints, one segment of states
- * and the adjoint state. */
+ * About (2 ceil(N / K) + 2 K + 2) * 8 N_p + 24 N N_g bytes: checkpoints, one segment of
+ * states, the adjoint state and every step's grids. */
 size_t pic_adj_workspace_size(const pic_adj_params *p);
 
 int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_stream,

@@ -428,16 +428,4 @@ __global__ void k_adj_loss(Work wk, int rec_cap, int64_t nsteps, double lw, doub
         *loss = lw * s;
 }
 
-// Copy of the fields of one step into the segment store: E^n, j^{n,*}, j^{*,n+1/2} (the
-// currents' replicas summed).
-__global__ void k_adj_save_grids(const double *E, const double *J1, const double *J2, int ng,
-                                 int nrep, double *dst)
-{
-    for (int i = threadIdx.x; i < ng; i += nthreads()) {
-        dst[i] = E[i];
-        dst[ng + i] = rep_sum(J1, i, nrep, 3 * ng);
-        dst[2 * ng + i] = rep_sum(J2, i, nrep, 3 * ng);
-    }
-}
-
 }  // namespace pic

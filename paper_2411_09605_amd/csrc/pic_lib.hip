@@ -1509,8 +1509,9 @@ namespace {
 
 struct AdjLayout {
     Layout fwd;                      // the forward run's workspace (first)
-    size_t ckx, ckv, ckE;            // checkpoints [ncp][N_p], [ncp][N_p], [ncp][N_g]
-    size_t segx, segv, segg;         // one segment: [K][N_p] x2, [K][3][N_g]
+    size_t ckx, ckv;                 // checkpoints [ncp][N_p], [ncp][N_p]
+    size_t segx, segv;               // one segment of states: [K][N_p] x2
+    size_t gall;                     // every step's grids [N][3][N_g]: E^n, j^{n,*}, j^{*,n+1/2}
     size_t ax, av, lam, G1, G2, rhobar, gpart;
     size_t total;
     int ncp;
@@ -1583,10 +1584,9 @@ AdjLayout adj_layout(const pic_adj_params *p)
     A.ncp = (p->n_steps + p->checkpoint_every - 1) / p->checkpoint_every;
     A.ckx = take((size_t)A.ncp * np * 8);
     A.ckv = take((size_t)A.ncp * np * 8);
-    A.ckE = take((size_t)A.ncp * ng * 8);
     A.segx = take(K * np * 8);
     A.segv = take(K * np * 8);
-    A.segg = take(K * 3 * ng * 8);
+    A.gall = take((size_t)p->n_steps * 3 * ng * 8);
     A.ax = take(np * 8);
     A.av = take(np * 8);
     A.lam = take(2 * ng * 8);
@@ -1614,7 +1614,7 @@ struct pic_adj {
     int forward_done;
     int poisoned;
     std::string err;
-    double *ckx, *ckv, *ckE, *segx, *segv, *segg;
+    double *ckx, *ckv, *segx, *segv, *gall;
 };
 
 namespace {
@@ -1642,7 +1642,8 @@ void adj_pass_a(pic_adj *c, int par, int64_t step, const double *X, const double
                        lds_pass_a(&c->q), c->stream, c->run, c->wk, par, step, X, V);
 }
 
-// save: null, or where the lead workgroup copies the step's grids (k_adj_save_grids' layout)
+// save: null, or where the lead workgroup copies the step's grids: E^n | j^{n,*} | j^{*,n+1/2}
+// (replicas summed), [3][N_g]
 template <int ORDER>
 void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *Xo, double *Vo,
                 double *save = nullptr)
@@ -1651,6 +1652,27 @@ void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *X
     wk.grid_save = save;
     hipLaunchKernelGGL((k_pass_b<ORDER, 1, false, true, 0>), dim3(c->run.nblocks), dim3(c->threads),
                        lds_pass_b(&c->q), c->stream, c->run, wk, par, X, V, Xo, Vo);
+}
+
+// Recompute of step n of the forward run from its state (X, V) into (Xo, Vo) in one
+// launch: pass B without its predictor deposit, its fields built from the grids the
+// forward pass B kept (g: E^n | j^{n,*} | j^{*,n+1/2}, one replica).  The prologue forms the
+// same sums in the same order as the forward run's pass B, so the new state is the
+// forward run's bit for bit; pass A and both deposits are not needed again.
+template <int ORDER>
+void adj_recompute(pic_adj *c, int par, const double *g, const double *X, const double *V,
+                   double *Xo, double *Vo)
+{
+    Run r = c->run;
+    r.nrep = 1;
+    Work wk = c->wk;
+    const int ng = c->p.n_cells;
+    wk.Ef[par] = const_cast<double *>(g);
+    wk.J1[par] = const_cast<double *>(g) + ng;
+    wk.J2[par] = const_cast<double *>(g) + 2 * ng;
+    wk.grid_save = nullptr;
+    hipLaunchKernelGGL((k_pass_b<ORDER, 1, false, false, 0>), dim3(c->run.nblocks), dim3(c->threads),
+                       lds_pass_b(&c->q), c->stream, r, wk, par, X, V, Xo, Vo);
 }
 
 template <int ORDER>
@@ -1704,10 +1726,10 @@ void adj_forward_launches(pic_adj *c)
             const int64_t cp = n / K;
             adj_copy(c, c->ckx + cp * r.np, X, r.np);
             adj_copy(c, c->ckv + cp * r.np, V, r.np);
-            adj_copy(c, c->ckE + cp * ng, w.Ef[par], ng);
         }
         adj_pass_a<ORDER>(c, par, n, X, V);
-        adj_pass_b<ORDER>(c, par, X, V, X, V);
+        // pass B's lead keeps the step's grids (E^n and the two currents, replicas summed)
+        adj_pass_b<ORDER>(c, par, X, V, X, V, c->gall + n * 3 * ng);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(gt), 0, c->stream, r, w, (int)(c->p.n_steps & 1),
                        (int64_t)c->p.n_steps);
@@ -1729,32 +1751,22 @@ void adj_backward_launches(pic_adj *c)
     int q = 0;
     for (int cp = c->A.ncp - 1; cp >= 0; --cp) {
         const int s0 = cp * K, len = std::min(K, N - s0);
-        // recompute the segment from its checkpoint, keeping every state and grid
+        // recompute the segment's states from its checkpoint with the grids the forward
+        // run kept (one gather-only launch per step)
         adj_copy(c, c->segx, c->ckx + (int64_t)cp * r.np, r.np);
         adj_copy(c, c->segv, c->ckv + (int64_t)cp * r.np, r.np);
-        adj_copy(c, w.Ef[0], c->ckE + (int64_t)cp * ng, ng);
-        fill_range(c->stream, w.J1[0], (int64_t)r.nrep * 3 * ng);
-        fill_range(c->stream, w.J2[0], (int64_t)r.nrep * 3 * ng);
-        adj_predeposit<ORDER>(c, c->segx, c->segv);
-        for (int j = 0; j < len; ++j) {
-            const int par = j & 1;
+        const double *gseg = c->gall + (int64_t)s0 * 3 * ng;
+        for (int j = 0; j + 1 < len; ++j) {
             double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
-            adj_pass_a<ORDER>(c, par, -1, Xj, Vj);          // step -1: no record
-            // the step's grids go to the segment store: from pass B's prologue, which sums
-            // the same replicas, or (last step of the segment, no pass B) on their own
-            double *gj = c->segg + (int64_t)j * 3 * ng;
-            if (j + 1 < len)
-                adj_pass_b<ORDER>(c, par, Xj, Vj, Xj + r.np, Vj + r.np, gj);
-            else
-                hipLaunchKernelGGL(k_adj_save_grids, dim3(1), dim3(256), 0, c->stream, w.Ef[par],
-                                   w.J1[par], w.J2[par], ng, r.nrep, gj);
+            adj_recompute<ORDER>(c, (int)((s0 + j) & 1), gseg + (int64_t)j * 3 * ng, Xj, Vj,
+                                 Xj + r.np, Vj + r.np);
         }
         // reverse steps of the segment: R1 of its last step, then per step R2 and R3 fused
         // with R1 of the step before (R3 alone for the segment's first step, whose
         // predecessor is in the previous segment)
         for (int j = len - 1; j >= 0; --j) {
             const double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
-            const double *g = c->segg + (int64_t)j * 3 * ng;
+            const double *g = gseg + (int64_t)j * 3 * ng;
             if (j == len - 1)
                 adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
             adj_rev<ORDER, 2>(c, q, Xj, Vj, g);
@@ -1824,10 +1836,9 @@ int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_st
     bind_run_work(&c->q, &fb, A.fwd, ws, c->run, c->wk);
     c->ckx = (double *)(ws + A.ckx);
     c->ckv = (double *)(ws + A.ckv);
-    c->ckE = (double *)(ws + A.ckE);
     c->segx = (double *)(ws + A.segx);
     c->segv = (double *)(ws + A.segv);
-    c->segg = (double *)(ws + A.segg);
+    c->gall = (double *)(ws + A.gall);
     AdjWork &aw = c->aw;
     const int ng = p->n_cells;
     aw.ax = (double *)(ws + A.ax);
