@@ -342,7 +342,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream_1d1v_512c_10M")
     ap.add_argument("--scheme", default=None,
-                    choices=("esec2", "esec1", "emec_li", "emec_psatd", "standard"),
+                    choices=("esec2", "esec1", "emec_li", "emec_psatd", "emec_lf", "standard"),
                     help="scheme to run the workload with (default: the workload's own)")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--rebin-every", type=int, default=0)
     ap.add_argument("--deterministic", action="store_true",
                     help="PIC_F_DETERMINISTIC (bit-reproducible current sums)")
+    ap.add_argument("--dt", type=float, default=None,
+                    help="time step instead of the workload's (e.g. EMEC(LF) needs c dt <= h)")
     ap.add_argument("--charge-conserving", action="store_true",
                     help="PIC_F_CHARGE_CONSERVING (exact charge conservation; ESEC2 with "
                          "tent shapes: the workload is run with shape order 1)")
@@ -394,6 +396,8 @@ def main():
         wl.scheme = args.scheme
     if args.charge_conserving:
         wl.order = 1
+    if args.dt is not None:
+        wl.dt = args.dt
     print(f"[bench] workload {args.workload}: {wl.n_particles} particles, {wl.n_cells} cells, "
           f"order {wl.order}, dt {wl.dt}", file=sys.stderr, flush=True)
     knobs = dict(block_threads=args.block_threads, grid_blocks=args.grid_blocks,
