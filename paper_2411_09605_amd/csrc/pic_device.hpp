@@ -727,7 +727,9 @@ __device__ __forceinline__ void cc_pieces(const Run &r, double x0, double x1, F 
     const double ua = x0 * r.inv_h - 0.5;
     const double base = floor(ua);
     const double xw = wrap_pos(x1, r.L);
-    const double m = rint((x1 - xw) / r.L);          // whole periods between x1 and xw
+    // whole periods between x1 and xw (x1 - xw is a multiple of L up to rounding, so the
+    // reciprocal of L, inv_h / N_g, serves)
+    const double m = rint((x1 - xw) * (r.inv_h / (double)r.ng));
     const double ta = ua - base;
     const double tb = (xw * r.inv_h - 0.5) + (m * (double)r.ng - base);
     const double lo = fmin(ta, tb), hi = fmax(ta, tb), len = hi - lo;
@@ -735,10 +737,11 @@ __device__ __forceinline__ void cc_pieces(const Run &r, double x0, double x1, F 
         visit(base, 0.5 * (ta + tb), 1.0);
         return;
     }
+    const double il = 1.0 / len;                    // one division per path
     double t = lo;
     for (;;) {
         const double e = fmin(floor(t) + 1.0, hi);
-        visit(base, 0.5 * (t + e), (e - t) / len);
+        visit(base, 0.5 * (t + e), (e - t) * il);
         if (e >= hi)
             break;
         t = e;
