@@ -453,8 +453,8 @@ typedef struct {                 /* DEVICE pointers, caller-owned, [N_p] unless 
 typedef struct pic_adj pic_adj;
 
 /* Workspace bytes (0 if the parameters are invalid; pic_last_error(NULL) says why).
- * About (2 ceil(N / K) + 2 K + 2) * 8 N_p + 24 N N_g bytes: checkpoints, one segment of
- * states, the adjoint state and every step's grids. */
+ * About (2 ceil(N / K) + 2 K) * 8 N_p + 48 N N_g bytes: checkpoints, one segment of
+ * states, the adjoint state and every step's grids and fields. */
 size_t pic_adj_workspace_size(const pic_adj_params *p);
 
 int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_stream,

@@ -2,8 +2,9 @@
 // electrostatic, for the loss J = lw * sum_{n=1..N} W_E^n (W_E of section 5.1) with
 // respect to the parameters of the initial condition.
 //
-// Reverse of one step n (state n -> n+1), with x*, v*, x^{n+1/2}, E*, E-bar and Gamma
-// recomputed from the stored state of step n and its grids (E^n, j^{n,*}, j^{*,n+1/2}):
+// Reverse of one step n (state n -> n+1), with x*, v*, x^{n+1/2} and Gamma recomputed
+// from the stored state of step n and the fields the forward pass B of that step built
+// and kept (E*, E-bar, E^{n+1}):
 //
 //   R1: per particle, the adjoint of v-dagger from the adjoint of v^{n+1} through
 //       v^{n+1} = Gamma v-dagger and Gamma = sqrt(1 + 2 num / den) (eq. (opt_solution);
@@ -28,6 +29,8 @@
 namespace pic {
 
 constexpr int kAdjMaxModes = 16;
+// Rows of the grids kept per forward step: E^n | j^{n,*} | j^{*,n+1/2} | E* | E-bar | E^{n+1}.
+constexpr int kSaveRows = 6;
 
 struct AdjParams {
     int32_t n_modes;
@@ -165,46 +168,17 @@ __device__ __forceinline__ AdjOut<ORDER, STAGE> adj_particle(const Run &r, doubl
     return o;
 }
 
-// The forward fields of step n in LDS: es (E*), eb (E-bar) ghost-padded, e1 (E^{n+1}).
-__device__ __forceinline__ void adj_fields(const Run &r, const Work &wk, const double *En,
-                                           const double *J1, const double *J2, double *es,
-                                           double *eb, double *e1, double *red)
-{
-    // electrostatic: the magnetic tiles and the Crank-Nicolson scratch are not touched
-    // the stored grids of a step are single (replicas already summed)
-    predictor_fields(r, En, nullptr, J1, es, es, red, 1);
-    field_update(r, wk, En, nullptr, J2, e1, e1, eb, eb, e1, red, 1);
-    __syncthreads();
-    ghost_fill(es, 1, r.ng, r.tw);
-    ghost_fill(eb, 1, r.ng, r.tw);
-}
-
 // The replica of the grid-adjoint deposits a workgroup adds into (replica stride ng).
 __device__ __forceinline__ double *g_slot(double *G, int nrep, int ng)
 {
     return G + (size_t)(blockIdx.x % nrep) * ng;
 }
 
-// lt = lambda + lbw E^{n+1} + G1 / 2 into lt (LDS [ng]); jb2 = -dt (lt - mean lt) into
-// the tile interior.  e1 must be visible.  G1 has nrep replicas.
-__device__ __forceinline__ void adj_current2(const Run &r, const AdjParams &ap, const double *lam,
-                                             const double *G1, const double *e1, double *lt,
-                                             double *jb2, double *red)
-{
-    const int ng = r.ng;
-    for (int i = threadIdx.x; i < ng; i += nthreads())
-        lt[i] = fma(ap.lbw, e1[i], lam[i]) + 0.5 * rep_sum(G1, i, r.nrep, ng);
-    __syncthreads();
-    const double m = block_mean(lt, ng, red);
-    for (int i = threadIdx.x; i < ng; i += nthreads())
-        jb2[kGhost + i] = -r.dt * (lt[i] - m);
-}
-
-// LDS of the reverse passes: es | eb | jb2 | jb1-or-tile (tw each) | e1 | lt (ng each), and
-// for the fused pass (STAGE 4) the previous step's es | eb | tile (tw each) | e1 (ng).
+// LDS of the reverse passes: es | eb | jb2 | jb1-or-tile (tw each) | lt (ng), and for the
+// fused pass (STAGE 4) the previous step's es | eb | tile (tw each).
 __host__ __device__ constexpr size_t adj_lds_doubles(int tw, int ng, int stage)
 {
-    return stage == 4 ? 7 * (size_t)tw + 3 * (size_t)ng : 4 * (size_t)tw + 2 * (size_t)ng;
+    return stage == 4 ? 7 * (size_t)tw + (size_t)ng : 4 * (size_t)tw + (size_t)ng;
 }
 
 // Reverse pass of step n.  STAGE 1, 2, 3 as described at the top; STAGE 4 is R3 of step n
@@ -229,42 +203,64 @@ __global__ __launch_bounds__(1024) void k_adj_reverse(Run r, Work wk, AdjWork aw
     // wavefronts claim batches of 64 particles (the counter is set before the barriers below)
     WaveBatches<1> wb(p0, &wctr);
     wb.reset();
-    double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw;
-    double *e1 = t4 + tw, *lt = e1 + ng;
-    double *esm = lt + ng, *ebm = esm + tw, *tm = ebm + tw, *e1m = tm + tw;   // STAGE 4
-    adj_fields(r, wk, g, g + ng, g + 2 * ng, es, eb, e1, red);
-    if constexpr (STAGE == 4) {
-        __syncthreads();
-        adj_fields(r, wk, gm, gm + ng, gm + 2 * ng, esm, ebm, e1m, red);
+    double *es = smem, *eb = es + tw, *jb2 = eb + tw, *t4 = jb2 + tw, *lt = t4 + tw;
+    double *esm = lt + ng, *ebm = esm + tw, *tm = ebm + tw;   // STAGE 4
+    // One round of loads: the fields the forward pass B built for step n (and n - 1),
+    // E* | E-bar | E^{n+1} after the three grids, and the grid adjoints.
+    //   lt = lambda + lbw E^{n+1} + G1 / 2 (the adjoint of E^{n+1}); t4 = G2 (STAGE >= 3)
+    double m[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < ng; i += nthreads()) {
+        es[kGhost + i] = g[3 * ng + i];
+        eb[kGhost + i] = g[4 * ng + i];
+        if constexpr (STAGE == 4) {
+            esm[kGhost + i] = gm[3 * ng + i];
+            ebm[kGhost + i] = gm[4 * ng + i];
+        }
+        if constexpr (STAGE >= 2) {
+            const double g1 = rep_sum(aw.G1[q], i, nrep, ng);
+            const double l = fma(ap.lbw, g[5 * ng + i], aw.lam[q][i]) + 0.5 * g1;
+            lt[i] = l;
+            m[0] += l;
+            if constexpr (STAGE >= 3) {
+                const double g2 = rep_sum(aw.G2[q], i, nrep, ng);
+                t4[kGhost + i] = g2;
+                m[1] += g2;
+                // adjoint of E^n for step n - 1
+                if (blockIdx.x == 0)
+                    aw.lam[q ^ 1][i] = l + 0.5 * g1 + g2;
+            }
+        }
     }
     if constexpr (STAGE >= 2) {
-        __syncthreads();
-        adj_current2(r, ap, aw.lam[q], aw.G1[q], e1, lt, jb2, red);
-    }
-    if constexpr (STAGE == 2) {
-        // the next reverse step deposits into the other parity's G1 (in the pass after this)
-        if (blockIdx.x == 0)
-            rep_zero(aw.G1[q ^ 1], ng, nrep, ng);
-    }
-    if constexpr (STAGE >= 3) {
-        for (int i = threadIdx.x; i < ng; i += nthreads())
-            t4[kGhost + i] = rep_sum(aw.G2[q], i, nrep, ng);
-        const double m = block_mean(t4 + kGhost, ng, red);
-        if (blockIdx.x == 0) {
-            // adjoint of E^n for step n - 1; clear the other parity's G2
-            for (int i = threadIdx.x; i < ng; i += nthreads())
-                aw.lam[q ^ 1][i] = lt[i] + 0.5 * rep_sum(aw.G1[q], i, nrep, ng) + t4[kGhost + i];
-            rep_zero(aw.G2[q ^ 1], ng, nrep, ng);
+        block_reduce<0u>(m, red);
+        const double mean_l = m[0] / ng, mean_g2 = m[1] / ng;
+        // jb2 = -dt (lt - mean lt): the adjoint of the centred current (Ampere update with
+        // its mean removed); jb1 = -dt/2 (G2 - mean G2), the predictor current's
+        for (int i = threadIdx.x; i < ng; i += nthreads()) {
+            jb2[kGhost + i] = -r.dt * (lt[i] - mean_l);
+            if constexpr (STAGE >= 3)
+                t4[kGhost + i] = -r.hdt * (t4[kGhost + i] - mean_g2);
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < ng; i += nthreads())
-            t4[kGhost + i] = -r.hdt * (t4[kGhost + i] - m);
-    } else {
-        tile_zero(t4, tw);
     }
+    if (blockIdx.x == 0) {
+        // the next reverse step deposits into the other parity's G1 (R2, in the pass after
+        // this) and G2; the lead of R3 clears the latter
+        if constexpr (STAGE == 2)
+            rep_zero(aw.G1[q ^ 1], ng, nrep, ng);
+        if constexpr (STAGE >= 3)
+            rep_zero(aw.G2[q ^ 1], ng, nrep, ng);
+    }
+    if constexpr (STAGE <= 2)
+        tile_zero(t4, tw);
     if constexpr (STAGE == 4)
         tile_zero(tm, tw);
     __syncthreads();
+    ghost_fill(es, 1, ng, tw);
+    ghost_fill(eb, 1, ng, tw);
+    if constexpr (STAGE == 4) {
+        ghost_fill(esm, 1, ng, tw);
+        ghost_fill(ebm, 1, ng, tw);
+    }
     if constexpr (STAGE >= 2)
         ghost_fill(jb2, 1, ng, tw);
     if constexpr (STAGE >= 3)

@@ -1652,6 +1652,17 @@ __device__ __forceinline__ void pass_b_body(const Run &r, const Work &wk, int pa
                 for (int i = threadIdx.x; i < 2 * ng; i += nthreads())
                     wk.Bf[par ^ 1][i] = b1[i];
         }
+        if constexpr (!EM) {
+            if (wk.grid_save) {
+                // the fields this step gathers, for the adjoint's reverse passes
+                double *sv = wk.grid_save + 3 * ng;
+                for (int i = threadIdx.x; i < ng; i += nthreads()) {
+                    sv[i] = es[kGhost + i];
+                    sv[ng + i] = eb[kGhost + i];
+                    sv[2 * ng + i] = e1[i];
+                }
+            }
+        }
         double we, wb;
         field_energies(r, e1, b1, &we, &wb, red);
         if (threadIdx.x == 0) {

@@ -1510,8 +1510,10 @@ namespace {
 struct AdjLayout {
     Layout fwd;                      // the forward run's workspace (first)
     size_t ckx, ckv;                 // checkpoints [ncp][N_p], [ncp][N_p]
-    size_t segx, segv;               // one segment of states: [K][N_p] x2
-    size_t gall;                     // every step's grids [N][3][N_g]: E^n, j^{n,*}, j^{*,n+1/2}
+    size_t segx, segv;               // states 1..K-1 of a segment (state 0 is its
+                                     // checkpoint): [K - 1][N_p] x2
+    size_t gall;                     // every step's grids [N][6][N_g]: E^n, j^{n,*}, j^{*,n+1/2},
+                                     // E*, E-bar, E^{n+1}
     size_t ax, av, lam, G1, G2, rhobar, gpart;
     size_t total;
     int ncp;
@@ -1584,9 +1586,9 @@ AdjLayout adj_layout(const pic_adj_params *p)
     A.ncp = (p->n_steps + p->checkpoint_every - 1) / p->checkpoint_every;
     A.ckx = take((size_t)A.ncp * np * 8);
     A.ckv = take((size_t)A.ncp * np * 8);
-    A.segx = take(K * np * 8);
-    A.segv = take(K * np * 8);
-    A.gall = take((size_t)p->n_steps * 3 * ng * 8);
+    A.segx = take((K - 1) * np * 8);
+    A.segv = take((K - 1) * np * 8);
+    A.gall = take((size_t)p->n_steps * kSaveRows * ng * 8);
     A.ax = take(np * 8);
     A.av = take(np * 8);
     A.lam = take(2 * ng * 8);
@@ -1642,8 +1644,9 @@ void adj_pass_a(pic_adj *c, int par, int64_t step, const double *X, const double
                        lds_pass_a(&c->q), c->stream, c->run, c->wk, par, step, X, V);
 }
 
-// save: null, or where the lead workgroup copies the step's grids: E^n | j^{n,*} | j^{*,n+1/2}
-// (replicas summed), [3][N_g]
+// save: null, or where the lead workgroup copies the step's grids, E^n | j^{n,*} |
+// j^{*,n+1/2} (replicas summed), and the fields built from them, E* | E-bar | E^{n+1}:
+// [kSaveRows][N_g]
 template <int ORDER>
 void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *Xo, double *Vo,
                 double *save = nullptr)
@@ -1719,17 +1722,21 @@ void adj_forward_launches(pic_adj *c)
     hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w);
     adj_predeposit<ORDER>(c, X, V);
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
-    const int K = c->p.checkpoint_every;
-    for (int64_t n = 0; n < c->p.n_steps; ++n) {
+    const int64_t K = c->p.checkpoint_every, N = c->p.n_steps;
+    adj_copy(c, c->ckx, X, r.np);
+    adj_copy(c, c->ckv, V, r.np);
+    for (int64_t n = 0; n < N; ++n) {
         const int par = (int)(n & 1);
-        if (n % K == 0) {
-            const int64_t cp = n / K;
-            adj_copy(c, c->ckx + cp * r.np, X, r.np);
-            adj_copy(c, c->ckv + cp * r.np, V, r.np);
-        }
-        adj_pass_a<ORDER>(c, par, n, X, V);
-        // pass B's lead keeps the step's grids (E^n and the two currents, replicas summed)
-        adj_pass_b<ORDER>(c, par, X, V, X, V, c->gall + n * 3 * ng);
+        // a checkpointed state is written by the pass B before it straight into its slot
+        // and read from there; the others live in x, v
+        const bool in_ck = n > 0 && n % K == 0, out_ck = (n + 1) % K == 0 && n + 1 < N;
+        const double *Xi = in_ck ? c->ckx + (n / K) * r.np : X;
+        const double *Vi = in_ck ? c->ckv + (n / K) * r.np : V;
+        double *Xo = out_ck ? c->ckx + ((n + 1) / K) * r.np : X;
+        double *Vo = out_ck ? c->ckv + ((n + 1) / K) * r.np : V;
+        adj_pass_a<ORDER>(c, par, n, Xi, Vi);
+        // pass B's lead keeps the step's grids and the fields built from them
+        adj_pass_b<ORDER>(c, par, Xi, Vi, Xo, Vo, c->gall + n * kSaveRows * ng);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(gt), 0, c->stream, r, w, (int)(c->p.n_steps & 1),
                        (int64_t)c->p.n_steps);
@@ -1751,27 +1758,27 @@ void adj_backward_launches(pic_adj *c)
     int q = 0;
     for (int cp = c->A.ncp - 1; cp >= 0; --cp) {
         const int s0 = cp * K, len = std::min(K, N - s0);
-        // recompute the segment's states from its checkpoint with the grids the forward
-        // run kept (one gather-only launch per step)
-        adj_copy(c, c->segx, c->ckx + (int64_t)cp * r.np, r.np);
-        adj_copy(c, c->segv, c->ckv + (int64_t)cp * r.np, r.np);
-        const double *gseg = c->gall + (int64_t)s0 * 3 * ng;
-        for (int j = 0; j + 1 < len; ++j) {
-            double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
-            adj_recompute<ORDER>(c, (int)((s0 + j) & 1), gseg + (int64_t)j * 3 * ng, Xj, Vj,
-                                 Xj + r.np, Vj + r.np);
-        }
+        // the states of the segment: its checkpoint, then the recomputed ones
+        const double *ckx = c->ckx + (int64_t)cp * r.np, *ckv = c->ckv + (int64_t)cp * r.np;
+        auto sx = [&](int j) { return j == 0 ? ckx : c->segx + (int64_t)(j - 1) * r.np; };
+        auto sv = [&](int j) { return j == 0 ? ckv : c->segv + (int64_t)(j - 1) * r.np; };
+        const double *gseg = c->gall + (int64_t)s0 * kSaveRows * ng;
+        // recompute them from the checkpoint with the grids the forward run kept (one
+        // gather-only launch per step)
+        for (int j = 0; j + 1 < len; ++j)
+            adj_recompute<ORDER>(c, (int)((s0 + j) & 1), gseg + (int64_t)j * kSaveRows * ng, sx(j),
+                                 sv(j), c->segx + (int64_t)j * r.np, c->segv + (int64_t)j * r.np);
         // reverse steps of the segment: R1 of its last step, then per step R2 and R3 fused
         // with R1 of the step before (R3 alone for the segment's first step, whose
         // predecessor is in the previous segment)
         for (int j = len - 1; j >= 0; --j) {
-            const double *Xj = c->segx + (int64_t)j * r.np, *Vj = c->segv + (int64_t)j * r.np;
-            const double *g = gseg + (int64_t)j * 3 * ng;
+            const double *Xj = sx(j), *Vj = sv(j);
+            const double *g = gseg + (int64_t)j * kSaveRows * ng;
             if (j == len - 1)
                 adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
             adj_rev<ORDER, 2>(c, q, Xj, Vj, g);
             if (j > 0)
-                adj_rev<ORDER, 4>(c, q, Xj, Vj, g, Xj - r.np, Vj - r.np, g - 3 * ng);
+                adj_rev<ORDER, 4>(c, q, Xj, Vj, g, sx(j - 1), sv(j - 1), g - kSaveRows * ng);
             else
                 adj_rev<ORDER, 3>(c, q, Xj, Vj, g);
             q ^= 1;

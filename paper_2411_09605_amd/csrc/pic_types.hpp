@@ -109,8 +109,9 @@ struct Work {
     // B*[2][ng] of the current step (EMEC(PSATD)), and the E [3][ng] | B^{n+1/2} [2][ng]
     // that pass B gathers
     double *prow, *ps, *pf;
-    double *grid_save;     // [3][ng] or null: pass B's lead copies E^n, j^{n,*} and
-                           // j^{*,n+1/2} (replicas summed) here (adjoint recompute)
+    double *grid_save;     // [6][ng] or null: pass B's lead copies E^n, j^{n,*},
+                           // j^{*,n+1/2} (replicas summed) and the fields it built from
+                           // them, E*, E-bar, E^{n+1}, here (adjoint recompute)
     double *spart;         // [nblocks][kNS] pass-B scalars of the newest state
     double *part;          // deterministic mode: [nblocks][3][ng] per-workgroup deposits,
                            // summed in workgroup order by k_reduce_partials
