@@ -414,10 +414,11 @@ int pic_batch_destroy(pic_batch *ctx);
  *
  * pic_adj_forward samples, initialises and runs N steps exactly as pic_init + pic_step,
  * storing the particle state (x, v) every checkpoint_every steps and every step's grids
- * (E^n and the two currents, 3 N_g values); pic_adj_backward recomputes each segment's
- * states from its checkpoint and those grids (one gather-only launch per step) and runs
- * the reverse of the steps, of the Gauss solve and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in
- * the derivative. */
+ * and fields (E^n, the two currents, E*, E-bar and E^{n+1}: 6 N_g values);
+ * pic_adj_backward recomputes each segment's states from its checkpoint and those grids
+ * (one gather-only launch per step) and runs the reverse of the steps, of the Gauss solve
+ * and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in the
+ * derivative. */
 #define PIC_ADJ_MAX_MODES 16
 
 typedef struct {

@@ -46,11 +46,12 @@ def _gpu_grad(wl, every, **kw):
     return J, g, adj
 
 
-@pytest.mark.parametrize("order,every", [(1, 7), (2, 7), (2, 60)])
+@pytest.mark.parametrize("order,every", [(1, 7), (2, 7), (2, 60), (2, 80)])
 def test_gradient_matches_oracle_tangent(order, every):
     """60 steps, 20k particles, 4 modes: loss, records and final state against the
     oracle's run; the gradient (4 amplitudes, beam speed, beam spread) against the
-    oracle's forward-mode gradient.  every = 7 leaves a ragged last segment."""
+    oracle's forward-mode gradient.  every = 7 leaves a ragged last segment; 60 makes the
+    run one segment, 80 one segment shorter than the interval."""
     _say(f"case: adjoint order {order} checkpoint every {every}")
     wl = _wl(order=order)
     J, g, adj = _gpu_grad(wl, every)
