@@ -968,16 +968,6 @@ __device__ __forceinline__ void ghost_fill(double *tile, int ncomp, int ng, int 
     }
 }
 
-// Cooperative load of ncomp node arrays (stride ng) into a ghost-padded tile.
-__device__ __forceinline__ void tile_load_ghost(double *tile, const double *src, int ncomp,
-                                                int ng, int tw)
-{
-    for (int idx = threadIdx.x; idx < ncomp * tw; idx += nthreads()) {
-        const int c = idx / tw, j = idx % tw;
-        tile[idx] = src[c * ng + wrap_node(j - kGhost, ng)];
-    }
-}
-
 // Interiors of the ghost-padded E [3][tw] and B [2][tw] tiles from a field block
 // E [3][ng] | B [2][ng] (Work::ps or Work::pf); the caller fills the ghosts.
 __device__ __forceinline__ void psatd_tiles(const Run &r, const double *src, double *et, double *bt)
