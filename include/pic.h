@@ -418,7 +418,14 @@ int pic_batch_destroy(pic_batch *ctx);
  * pic_adj_backward recomputes each segment's states from its checkpoint and those grids
  * (one gather-only launch per step) and runs the reverse of the steps, of the Gauss solve
  * and of the sampling.  The fallback Gamma := 1 (section 3.2) is a constant in the
- * derivative. */
+ * derivative.
+ * Streams: the context enqueues on the caller's stream.  The backward sweep recomputes the
+ * next segment's states on a side stream of its own (created by pic_adj_init on the
+ * caller's stream's device, default priority, destroyed by pic_adj_destroy) while the
+ * caller's stream reverses the current segment; events order the two, and the sweep's
+ * last launch on the caller's stream waits for the side stream, so work enqueued after
+ * pic_adj_backward on the caller's stream sees all of it.  pic_adj_init fails with
+ * PIC_EDEVICE if the stream or its events cannot be created. */
 #define PIC_ADJ_MAX_MODES 16
 
 typedef struct {
@@ -454,7 +461,7 @@ typedef struct {                 /* DEVICE pointers, caller-owned, [N_p] unless 
 typedef struct pic_adj pic_adj;
 
 /* Workspace bytes (0 if the parameters are invalid; pic_last_error(NULL) says why).
- * About (2 ceil(N / K) + 2 K) * 8 N_p + 48 N N_g bytes: checkpoints, one segment of
+ * About (2 ceil(N / K) + 4 K - 2) * 8 N_p + 48 N N_g bytes: checkpoints, two segments of
  * states, the adjoint state and every step's grids and fields. */
 size_t pic_adj_workspace_size(const pic_adj_params *p);
 

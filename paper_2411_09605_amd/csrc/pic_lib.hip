@@ -1511,7 +1511,8 @@ struct AdjLayout {
     Layout fwd;                      // the forward run's workspace (first)
     size_t ckx, ckv;                 // checkpoints [ncp][N_p], [ncp][N_p]
     size_t segx, segv;               // states 1..K-1 of a segment (state 0 is its
-                                     // checkpoint): [K - 1][N_p] x2
+                                     // checkpoint), two segments by parity:
+                                     // [2][K - 1][N_p] x2
     size_t gall;                     // every step's grids [N][6][N_g]: E^n, j^{n,*}, j^{*,n+1/2},
                                      // E*, E-bar, E^{n+1}
     size_t ax, av, lam, G1, G2, rhobar, gpart;
@@ -1586,8 +1587,8 @@ AdjLayout adj_layout(const pic_adj_params *p)
     A.ncp = (p->n_steps + p->checkpoint_every - 1) / p->checkpoint_every;
     A.ckx = take((size_t)A.ncp * np * 8);
     A.ckv = take((size_t)A.ncp * np * 8);
-    A.segx = take((K - 1) * np * 8);
-    A.segv = take((K - 1) * np * 8);
+    A.segx = take(2 * (K - 1) * np * 8);
+    A.segv = take(2 * (K - 1) * np * 8);
     A.gall = take((size_t)p->n_steps * kSaveRows * ng * 8);
     A.ax = take(np * 8);
     A.av = take(np * 8);
@@ -1617,6 +1618,10 @@ struct pic_adj {
     int poisoned;
     std::string err;
     double *ckx, *ckv, *segx, *segv, *gall;
+    // the backward sweep recomputes the next segment's states on a stream of its own while
+    // the caller's stream reverses the current one; events order the two
+    hipStream_t side;
+    hipEvent_t ev_start, ev_join, ev_rec[2], ev_rev[2];
 };
 
 namespace {
@@ -1663,8 +1668,8 @@ void adj_pass_b(pic_adj *c, int par, const double *X, const double *V, double *X
 // same sums in the same order as the forward run's pass B, so the new state is the
 // forward run's bit for bit; pass A and both deposits are not needed again.
 template <int ORDER>
-void adj_recompute(pic_adj *c, int par, const double *g, const double *X, const double *V,
-                   double *Xo, double *Vo)
+void adj_recompute(pic_adj *c, hipStream_t stream, int par, const double *g, const double *X,
+                   const double *V, double *Xo, double *Vo)
 {
     Run r = c->run;
     r.nrep = 1;
@@ -1675,7 +1680,7 @@ void adj_recompute(pic_adj *c, int par, const double *g, const double *X, const 
     wk.J2[par] = const_cast<double *>(g) + 2 * ng;
     wk.grid_save = nullptr;
     hipLaunchKernelGGL((k_pass_b<ORDER, 1, false, false, 0>), dim3(c->run.nblocks), dim3(c->threads),
-                       lds_pass_b(&c->q), c->stream, r, wk, par, X, V, Xo, Vo);
+                       lds_pass_b(&c->q), stream, r, wk, par, X, V, Xo, Vo);
 }
 
 template <int ORDER>
@@ -1755,35 +1760,59 @@ void adj_backward_launches(pic_adj *c)
     fill_range(c->stream, c->aw.lam[0], 2 * (int64_t)ng);    // both parities
     fill_range(c->stream, c->aw.G1[0], 2 * (int64_t)r.nrep * ng);
     fill_range(c->stream, c->aw.G2[0], 2 * (int64_t)r.nrep * ng);
+    // States of segment cp: its checkpoint, then the recomputed ones in the segment buffer
+    // of its parity.
+    const int64_t seglen = (int64_t)(std::min(K, N) - 1) * r.np;
+    auto sx = [&](int cp, int j) {
+        return j == 0 ? c->ckx + (int64_t)cp * r.np : c->segx + (cp & 1) * seglen + (int64_t)(j - 1) * r.np;
+    };
+    auto sv = [&](int cp, int j) {
+        return j == 0 ? c->ckv + (int64_t)cp * r.np : c->segv + (cp & 1) * seglen + (int64_t)(j - 1) * r.np;
+    };
+    auto grids = [&](int cp, int j) { return c->gall + ((int64_t)cp * K + j) * kSaveRows * ng; };
+    // recompute a segment's states from its checkpoint with the grids the forward run kept
+    // (one gather-only launch per step), on the side stream
+    auto recompute = [&](int cp) {
+        const int s0 = cp * K, len = std::min(K, N - s0);
+        for (int j = 0; j + 1 < len; ++j)
+            adj_recompute<ORDER>(c, c->side, (int)((s0 + j) & 1), grids(cp, j), sx(cp, j), sv(cp, j),
+                                 sx(cp, j + 1), sv(cp, j + 1));
+        (void)hipEventRecord(c->ev_rec[cp & 1], c->side);
+    };
+    // the side stream starts after everything enqueued before this call
+    (void)hipEventRecord(c->ev_start, c->stream);
+    (void)hipStreamWaitEvent(c->side, c->ev_start, 0);
+    recompute(c->A.ncp - 1);
     int q = 0;
     for (int cp = c->A.ncp - 1; cp >= 0; --cp) {
         const int s0 = cp * K, len = std::min(K, N - s0);
-        // the states of the segment: its checkpoint, then the recomputed ones
-        const double *ckx = c->ckx + (int64_t)cp * r.np, *ckv = c->ckv + (int64_t)cp * r.np;
-        auto sx = [&](int j) { return j == 0 ? ckx : c->segx + (int64_t)(j - 1) * r.np; };
-        auto sv = [&](int j) { return j == 0 ? ckv : c->segv + (int64_t)(j - 1) * r.np; };
-        const double *gseg = c->gall + (int64_t)s0 * kSaveRows * ng;
-        // recompute them from the checkpoint with the grids the forward run kept (one
-        // gather-only launch per step)
-        for (int j = 0; j + 1 < len; ++j)
-            adj_recompute<ORDER>(c, (int)((s0 + j) & 1), gseg + (int64_t)j * kSaveRows * ng, sx(j),
-                                 sv(j), c->segx + (int64_t)j * r.np, c->segv + (int64_t)j * r.np);
+        if (cp > 0) {
+            // the next segment's buffer was last read by the reverse of segment cp + 1
+            if (cp + 1 < c->A.ncp)
+                (void)hipStreamWaitEvent(c->side, c->ev_rev[(cp + 1) & 1], 0);
+            recompute(cp - 1);
+        }
+        (void)hipStreamWaitEvent(c->stream, c->ev_rec[cp & 1], 0);
         // reverse steps of the segment: R1 of its last step, then per step R2 and R3 fused
         // with R1 of the step before (R3 alone for the segment's first step, whose
         // predecessor is in the previous segment)
         for (int j = len - 1; j >= 0; --j) {
-            const double *Xj = sx(j), *Vj = sv(j);
-            const double *g = gseg + (int64_t)j * kSaveRows * ng;
+            const double *Xj = sx(cp, j), *Vj = sv(cp, j);
+            const double *g = grids(cp, j);
             if (j == len - 1)
                 adj_rev<ORDER, 1>(c, q, Xj, Vj, g);
             adj_rev<ORDER, 2>(c, q, Xj, Vj, g);
             if (j > 0)
-                adj_rev<ORDER, 4>(c, q, Xj, Vj, g, sx(j - 1), sv(j - 1), g - kSaveRows * ng);
+                adj_rev<ORDER, 4>(c, q, Xj, Vj, g, sx(cp, j - 1), sv(cp, j - 1), g - kSaveRows * ng);
             else
                 adj_rev<ORDER, 3>(c, q, Xj, Vj, g);
             q ^= 1;
         }
+        (void)hipEventRecord(c->ev_rev[cp & 1], c->stream);
     }
+    // join: later work on the caller's stream follows everything on the side stream
+    (void)hipEventRecord(c->ev_join, c->side);
+    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
     // reverse of the Gauss start and of the sampling
     const int gt = grid_threads_of(ng);
     hipLaunchKernelGGL(k_adj_rhobar, dim3(1), dim3(gt), 3 * ng * 8, c->stream, r, w, c->aw, q);
@@ -1791,6 +1820,48 @@ void adj_backward_launches(pic_adj *c)
                        c->stream, r, c->aw, c->ap, c->ckx, c->b.s, c->b.g);
     hipLaunchKernelGGL(k_adj_grad_final, dim3(1), dim3(256), 0, c->stream, c->aw, r.nblocks, c->ap.nparam,
                        c->b.grad);
+}
+
+// The side stream (default priority, on the caller's stream's device) and the events of
+// the backward sweep.  Returns the first error; what was created is released by
+// adj_free_side.
+hipError_t adj_make_side(pic_adj *c, hipStream_t caller)
+{
+    c->side = nullptr;
+    c->ev_start = c->ev_join = nullptr;
+    c->ev_rec[0] = c->ev_rec[1] = c->ev_rev[0] = c->ev_rev[1] = nullptr;
+    int dev = 0, cur = 0;
+    hipError_t e = hipStreamGetDevice(caller, &dev);
+    if (e == hipSuccess)
+        e = hipGetDevice(&cur);
+    if (e != hipSuccess)
+        return e;
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess)
+        return e;
+    e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    hipEvent_t *evs[6] = {&c->ev_start, &c->ev_join, &c->ev_rec[0], &c->ev_rec[1], &c->ev_rev[0],
+                          &c->ev_rev[1]};
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+    if (dev != cur) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess)
+            e = e2;
+    }
+    return e;
+}
+
+void adj_free_side(pic_adj *c)
+{
+    if (c->side)
+        (void)hipStreamSynchronize(c->side);
+    hipEvent_t evs[6] = {c->ev_start, c->ev_join, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]};
+    for (hipEvent_t ev : evs)
+        if (ev)
+            (void)hipEventDestroy(ev);
+    if (c->side)
+        (void)hipStreamDestroy(c->side);
+    c->side = nullptr;
 }
 
 }  // namespace
@@ -1824,6 +1895,12 @@ int pic_adj_init(const pic_adj_params *p, const pic_adj_buffers *b, void *hip_st
     pic_adj *c = new (std::nothrow) pic_adj();
     if (!c)
         return fail(nullptr, PIC_ENOMEM, "out of host memory");
+    if (adj_make_side(c, (hipStream_t)hip_stream) != hipSuccess) {
+        adj_free_side(c);
+        delete c;
+        (void)hipGetLastError();
+        return fail(nullptr, PIC_EDEVICE, "could not create the adjoint's side stream and events");
+    }
     c->p = *p;
     c->b = *b;
     c->q = adj_forward_params(p);
@@ -1929,6 +2006,7 @@ int pic_adj_destroy(pic_adj *c)
 {
     if (!c)
         return PIC_ESTATE;
+    adj_free_side(c);
     delete c;
     return PIC_OK;
 }
