@@ -127,14 +127,15 @@ def test_psatd_launch_shapes_and_deposits(case):
 
 def test_psatd_full_size_parity_and_energy():
     """The 2e7-particle Weibel workload with the PSATD field solve: 10 steps element by
-    element against the oracle (at steps 5 and 10), then 290 more steps with the energy
-    bar."""
+    element against the oracle (at steps 5 and 10), then the rest of its 1000 steps with
+    the energy bar."""
     _say("case: PSATD weibel FULL 2e7 x 256, 10 steps vs oracle")
     wl = workloads.weibel()
     grec, orec, gpu, _ = gu.run_pair(wl, 10, scheme=S, every=5)
-    _say("  290 more steps on the GPU")
-    gpu.step(290)
+    _say(f"  {wl.steps - 10} more steps on the GPU")
+    gpu.step(wl.steps - 10)
     rec = np.concatenate([grec, gpu.diagnostics()])
+    assert rec["step"][-1] == wl.steps
     clean = rec["fallbacks_total"] == 0
     _say(f"  fallbacks {int(rec['fallbacks_total'][-1])}, max energy error "
          f"{rec['rel_energy_err'].max():.3e}")
