@@ -283,6 +283,9 @@ def catalogue() -> Dict[str, dict]:
         "two_stream_1d1v_512c_40M": dict(builder="two_stream", n_particles=40_000_000),
         "weibel_1d3v_256c_20M": dict(builder="weibel"),
         "batched_landau_512runs": dict(builder="batched_landau"),
+        # one Landau run with the ensemble's total particle count (1.7 GB of state): the
+        # plain passes at the batched form's size
+        "landau_1d1v_512c_108M": dict(builder="landau", n_particles=107_838_210, n_cells=512),
         "adjoint_two_stream_256c_1M": dict(builder="adjoint_two_stream"),
     }
 
