@@ -56,6 +56,17 @@ def test_batched_landau_runs_match_oracle(order):
     _run_batch_vs_oracle(runs, 10)
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_batched_esec1_runs_match_oracle(order):
+    """ESEC1 (no predictor current: pass B without its deposit) over 9 Landau runs of uneven
+    size."""
+    _say(f"case: batch of 9 ESEC1 landau runs, order {order}")
+    runs = workloads.batched_landau(n_runs=9, np_scale=0.01, order=order, steps=10)
+    for wl in runs:
+        wl.scheme = "esec1"
+    _run_batch_vs_oracle(runs, 10)
+
+
 def test_batched_small_launch_shape():
     """Tiny workgroups and chunks with a grid much smaller than the item table, so every
     workgroup strides over items of many runs."""
