@@ -68,6 +68,21 @@ def test_gradient_matches_oracle_tangent(order, every):
     assert err <= GRAD_TOL * np.abs(go).max(), (g, go)
 
 
+def test_gradient_odd_grid_matches_oracle_tangent():
+    """An odd grid (37 cells: no Nyquist mode in the Gauss solve and its reverse) with 6000
+    particles, 30 steps and checkpoints every 9: loss, final state and gradient against the
+    oracle."""
+    _say("case: adjoint odd grid 37 cells, checkpoint every 9")
+    wl = _wl(n=6000, ng=37, steps=30)
+    J, g, adj = _gpu_grad(wl, 9)
+    Jo, go, out = oracle.two_stream_gradient(wl, wl.steps)
+    assert abs(J - Jo) <= 1e-10 * abs(Jo), (J, Jo)
+    x = adj.x.cpu().numpy()
+    d = np.abs(x - out["x"])
+    assert np.minimum(d, wl.length - d).max() <= 1e-10 * wl.length
+    assert np.abs(g - go).max() <= GRAD_TOL * np.abs(go).max(), (g, go)
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     _say("case: adjoint checkpoint intervals 1, 13, 50")
     wl = _wl(steps=50, n=8000, ng=32)
