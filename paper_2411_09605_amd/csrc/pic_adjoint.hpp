@@ -341,7 +341,7 @@ __global__ __launch_bounds__(1024) void k_adj_sample(Run r, AdjParams ap, const 
 // rhobar = Gauss solve of lambda^0 (one workgroup): the Gauss map rho -> E is a real
 // circulant whose eigenvalues 1 / (i k_m) are imaginary, so its transpose is its
 // negative and the adjoint of rho is -rhobar.
-__global__ __launch_bounds__(1024) void k_adj_rhobar(Run r, Work wk, AdjWork aw, int q, int table)
+__global__ __launch_bounds__(1024) void k_adj_rhobar(Run r, Work wk, AdjWork aw, int q)
 {
     extern __shared__ double smem[];
     Work t = wk;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(1024) void k_adj_rhobar(Run r, Work wk, AdjWork aw,
     t.E = aw.rhobar;
     Run r1 = r;
     r1.nrep = 1;
-    gauss_body(r1, t, smem, table);
+    gauss_body(r1, t, smem);
 }
 
 // Per workgroup: the adjoint of x^0 gets the Gauss start's term, then the partial sums

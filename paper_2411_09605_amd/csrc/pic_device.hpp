@@ -2576,24 +2576,22 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 // Initial Gauss solve: dE/dx = rho - 1 with rho in J2[0], into the caller's E_x.
 // Spectrally on the nodes: E_m = rho_m / (i k_m), k_m = 2 pi m / L for 0 < |m| < N/2, mean
 // and Nyquist modes zero (the Poisson form, eq. (poisson), in 1D).
-// LDS: rho | Re E_m | Im E_m, and with `table` the cosines and sines of 2 pi j / N_g,
-// computed once by the same calls the sums would make term by term (the sums index them
-// with m l mod N_g), so the result is the same bit for bit; without it (a grid too large
-// for the table) each term calls sincospi.
-__host__ __device__ constexpr size_t gauss_lds_doubles(int ng, bool table)
+// LDS: rho | Re E_m | Im E_m | the cosines and sines of 2 pi j / N_g, computed once by the
+// same calls the sums would make term by term (the sums index them with m l mod N_g), so
+// the result is the same bit for bit (5 N_g doubles: every grid the passes accept fits).
+__host__ __device__ constexpr size_t gauss_lds_doubles(int ng)
 {
-    return (table ? 5 : 3) * (size_t)ng;
+    return 5 * (size_t)ng;
 }
 
-__device__ void gauss_body(const Run &r, const Work &wk, double *smem, int table)
+__device__ void gauss_body(const Run &r, const Work &wk, double *smem)
 {
     const int ng = r.ng;
     double *rho = smem, *er = smem + ng, *ei = smem + 2 * ng;
     double *tc = smem + 3 * ng, *ts = smem + 4 * ng;
     rep_gather(rho, wk.J2[0], ng, r.nrep, 3 * ng);
-    if (table)
-        for (int j = threadIdx.x; j < ng; j += nthreads())
-            sincospi(2.0 * (double)j / ng, &ts[j], &tc[j]);
+    for (int j = threadIdx.x; j < ng; j += nthreads())
+        sincospi(2.0 * (double)j / ng, &ts[j], &tc[j]);
     __syncthreads();
     if (r.filter_rho) {
         // the standard scheme's filtered density (as in k_std_field), through ei
@@ -2609,15 +2607,8 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem, int table
         if (m != 0 && 2 * m != ng) {
             int ml = 0;                        // m l mod N_g
             for (int l = 0; l < ng; ++l) {
-                double sn, cs;
-                if (table) {
-                    sn = ts[ml];
-                    cs = tc[ml];
-                } else {
-                    sincospi(2.0 * (double)ml / ng, &sn, &cs);
-                }
-                re += rho[l] * cs;
-                im -= rho[l] * sn;
+                re += rho[l] * tc[ml];
+                im -= rho[l] * ts[ml];
                 ml += m;
                 ml -= ml >= ng ? ng : 0;
             }
@@ -2635,14 +2626,7 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem, int table
         double acc = 0.0;
         int mi = i;                            // m i mod N_g, from m = 1
         for (int m = 1; m < ng; ++m) {
-            double sn, cs;
-            if (table) {
-                sn = ts[mi];
-                cs = tc[mi];
-            } else {
-                sincospi(2.0 * (double)mi / ng, &sn, &cs);
-            }
-            acc += er[m] * cs - ei[m] * sn;
+            acc += er[m] * tc[mi] - ei[m] * ts[mi];
             mi += i;
             mi -= mi >= ng ? ng : 0;
         }
@@ -2650,10 +2634,10 @@ __device__ void gauss_body(const Run &r, const Work &wk, double *smem, int table
     }
 }
 
-__global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk, int table)
+__global__ __launch_bounds__(1024) void k_gauss(Run r, Work wk)
 {
     extern __shared__ double smem[];
-    gauss_body(r, wk, smem, table);
+    gauss_body(r, wk, smem);
 }
 
 // Initial field of a charge-conserving run (Run::cc): Gauss' law on the half-node E,
@@ -3132,13 +3116,13 @@ __global__ __launch_bounds__(1024) void k_batch_fx_setup(Batch b)
     fx_setup_body(r, wk, red);
 }
 
-__global__ __launch_bounds__(1024) void k_batch_gauss(Batch b, int table)
+__global__ __launch_bounds__(1024) void k_batch_gauss(Batch b)
 {
     extern __shared__ double smem[];
     const BatchRun &br = b.runs[blockIdx.x];
     const Run r = uniform_copy(br.r);
     const Work wk = uniform_copy(br.wk);
-    gauss_body(r, wk, smem, table);
+    gauss_body(r, wk, smem);
 }
 
 __global__ __launch_bounds__(1024) void k_batch_cn_init(Batch b)

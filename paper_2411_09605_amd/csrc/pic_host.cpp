@@ -156,7 +156,7 @@ size_t lds_need(const pic_params *p)
                : is_std(p) ? std::max(lds_std_pass_of(p->shape_order, (size_t)p->n_cells),
                                       lds_std_field_of((size_t)p->n_cells))
                            : std::max(lds_pass_a(p), lds_pass_b(p));
-    m = std::max(m, (size_t)3 * p->n_cells * 8);
+    m = std::max(m, (size_t)5 * p->n_cells * 8);   // the Gauss solve with its twiddle table
     if (has_em_fields(p))
         m = std::max(m, lds_psatd_of((size_t)p->n_cells));
     m = std::max(m, lds_deposit(p));

@@ -46,9 +46,8 @@ struct pic_ctx {
 
 namespace {
 
-// The Gauss solve (gauss_body) takes its twiddle table whenever that fits in LDS.
-int gauss_table(int ng) { return gauss_lds_doubles(ng, true) * 8 <= kMaxLds ? 1 : 0; }
-size_t gauss_lds(int ng) { return gauss_lds_doubles(ng, gauss_table(ng) != 0) * 8; }
+// LDS of the Gauss solve (gauss_body).
+size_t gauss_lds(int ng) { return gauss_lds_doubles(ng) * 8; }
 
 // ----------------------------------------------------------- kernel dispatch tables
 // kind: 0 = 1D-1V electrostatic, 1 = 1D-3V electrostatic, 2 = 1D-3V electromagnetic
@@ -538,8 +537,7 @@ int init_ctx(pic_ctx *c, const pic_params *p, const pic_buffers *b, hipStream_t 
         hipLaunchKernelGGL(k_gauss_cc, dim3(1), dim3(gt), p->n_cells * 8, c->stream, r, w);
     } else if (p->flags & PIC_F_INIT_GAUSS) {
         dispatch(c, D_RHO);
-        hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), gauss_lds(p->n_cells), c->stream, r, w,
-                           gauss_table(p->n_cells));
+        hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), gauss_lds(p->n_cells), c->stream, r, w);
     }
     if (has_em_fields(p))
         hipLaunchKernelGGL(k_em_rows, dim3((unsigned)((p->n_cells + 255) / 256), kPsatdRows), dim3(256),
@@ -1177,7 +1175,6 @@ struct pic_batch {
     Batch bt;
     int threads, grid, kind;
     size_t lds_a, lds_b, lds_dep, lds_gauss;
-    int gauss_table;
     int64_t steps_done;
     std::vector<int64_t> records_read;
     std::vector<DevState *> st;
@@ -1240,8 +1237,7 @@ void batch_init_kind(pic_batch *c)
     if (c->p.flags & PIC_BF_INIT_GAUSS) {
         hipLaunchKernelGGL((k_batch_deposit_rho<ORDER>), dim3(c->grid), dim3(c->threads), c->lds_dep,
                            c->stream, c->bt);
-        hipLaunchKernelGGL(k_batch_gauss, dim3(c->p.n_runs), dim3(512), c->lds_gauss, c->stream, c->bt,
-                           c->gauss_table);
+        hipLaunchKernelGGL(k_batch_gauss, dim3(c->p.n_runs), dim3(512), c->lds_gauss, c->stream, c->bt);
     }
     if (EM)
         hipLaunchKernelGGL(k_batch_cn_init, dim3(c->p.n_runs), dim3(512), 0, c->stream, c->bt);
@@ -1399,7 +1395,6 @@ int pic_batch_init(const pic_batch_params *p, const pic_batch_buffers *b, void *
     c->lds_a = lds_pass_a_of(em, p->shape_order, ng);
     c->lds_b = lds_pass_b_of(em, p->shape_order, ng);
     c->lds_dep = 2 * (em ? 3 : 1) * tw * 8;
-    c->gauss_table = gauss_table((int)ng);
     c->lds_gauss = gauss_lds((int)ng);
 
     if (hipMemcpy(ws + L.runs, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1732,7 +1727,7 @@ void adj_forward_launches(pic_adj *c)
     hipLaunchKernelGGL(k_fx_setup, dim3(1), dim3(256), 0, c->stream, r, w);
     hipLaunchKernelGGL((k_deposit_rho<ORDER>), dim3(r.nblocks), dim3(c->threads), lds_deposit(&c->q),
                        c->stream, r, w, X);
-    hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), gauss_lds(ng), c->stream, r, w, gauss_table(ng));
+    hipLaunchKernelGGL(k_gauss, dim3(1), dim3(gt), gauss_lds(ng), c->stream, r, w);
     adj_predeposit<ORDER>(c, X, V);
     hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(gt), 0, c->stream, r, w);
     const int64_t K = c->p.checkpoint_every, N = c->p.n_steps;
@@ -1823,8 +1818,7 @@ void adj_backward_launches(pic_adj *c)
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
     // reverse of the Gauss start and of the sampling
     const int gt = grid_threads_of(ng);
-    hipLaunchKernelGGL(k_adj_rhobar, dim3(1), dim3(gt), gauss_lds(ng), c->stream, r, w, c->aw, q,
-                       gauss_table(ng));
+    hipLaunchKernelGGL(k_adj_rhobar, dim3(1), dim3(gt), gauss_lds(ng), c->stream, r, w, c->aw, q);
     hipLaunchKernelGGL((k_adj_grad<ORDER>), dim3(r.nblocks), dim3(c->threads), tile_width(&c->q) * 8,
                        c->stream, r, c->aw, c->ap, c->ckx, c->b.s, c->b.g);
     hipLaunchKernelGGL(k_adj_grad_final, dim3(1), dim3(256), 0, c->stream, c->aw, r.nblocks, c->ap.nparam,
